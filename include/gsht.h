@@ -1,0 +1,198 @@
+/*
+ * gsht.h -- general spin-weighted spherical harmonic synthesis and its adjoint
+ * on arbitrary points, for AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Reinecke, Belkner & Carron (2023), "Improved CMB
+ * (de-)lensing using general spherical harmonic transforms":
+ *
+ *   synthesis (Sect. 2, eq. "forward" for spin 0, eq. "forwardpol" with chi = 0
+ *   for spin s > 0):
+ *       spin 0:  T_i = sum_{l <= lmax} sum_{|m| <= min(l, mmax)} a_lm  Y_lm(theta_i, phi_i)
+ *       spin s:  Q_i + i U_i = - sum_{l, |m|} (G_lm + i C_lm) sY_lm(theta_i, phi_i)
+ *   adjoint (Sect. 2, eq. "adjoint" and the gradient/curl split that follows
+ *   eq. "forwardpol"):
+ *       spin 0:  b_lm = sum_i T_i Y*_lm(theta_i, phi_i)
+ *       spin s:  S+_lm = sum_i (Q + iU)_i sY*_lm,  S-_lm = sum_i (Q - iU)_i (-s)Y*_lm,
+ *                G_lm = -(S+ + (-1)^s S-)/2,        C_lm = -(S+ - (-1)^s S-)/(2i)
+ *
+ * computed as in Sect. 3: ring-by-ring Legendre synthesis onto an equidistant
+ * (Clenshaw-Curtis) ring grid with ntheta >= lmax + 2 rings including both poles,
+ * doubling of the theta range to a 2-D torus with the (-1)^(s+m) mirror sign, a
+ * 2-D FFT with correction by the kernel's Fourier transform, and a type-2 NUFFT
+ * (interpolation with an exponential-of-semicircle kernel) onto the points.  The
+ * adjoint runs the type-1 NUFFT (spreading), the FFT back, undoubling and the
+ * adjoint Legendre step.  The NUFFT is the only approximate step; its relative
+ * L2 error is controlled by epsilon (Sect. 3; accuracy metric of Sect. 4).
+ *
+ * Common conventions of every entry point
+ *   - All array pointers are DEVICE pointers (hipMalloc'd or equivalent) unless a
+ *     parameter says otherwise.  The caller owns every buffer it passes; the
+ *     library never frees or retains caller memory beyond the call, except that
+ *     a plan keeps its own sorted copy of the point coordinates.
+ *   - a_lm layout: complex, m-major triangular, one block per component:
+ *       idx(l, m) = m (2 lmax + 1 - m) / 2 + l,  0 <= m <= mmax,  m <= l <= lmax,
+ *       nalm = (mmax + 1)(lmax + 1) - mmax (mmax + 1) / 2,  array [ncomp][nalm].
+ *     ncomp = 1 (T) for spin 0 and 2 (G, C) for spin > 0.  Real-field convention
+ *     a_{l,-m} = (-1)^m conj(a_lm).  Imag(a_l0) and entries with l < spin are
+ *     ignored by the synthesis and returned as exactly 0 by the adjoint.
+ *   - Maps: real, [ncomp][npts]: T for spin 0, (Q, U) for spin > 0.
+ *   - theta, phi: FP64 in every precision.  theta must lie in [0, pi]; phi may be
+ *     any finite value (it is reduced modulo 2 pi).
+ *   - Precision GSHT_F64: a_lm complex128, maps float64, FFT/NUFFT in FP64,
+ *     1e-13 <= epsilon <= 0.1.  GSHT_F32: a_lm complex64, maps float32, FFT and
+ *     NUFFT in FP32 with FP64 point-to-grid offsets, 1e-5 <= epsilon <= 0.1.  The
+ *     Legendre recurrence is FP64 in both.
+ *   - Streams: hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it and the call returns without waiting, except where noted.
+ *     Inputs must stay unchanged until the stream has reached the call.
+ *   - Errors: every function returns a gsht_status; it never aborts or throws.
+ *     Invalid arguments are rejected before any device work.  gsht_last_error()
+ *     returns a thread-local message describing the last non-OK status.
+ */
+#ifndef GSHT_H
+#define GSHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSHT_OK = 0,
+    GSHT_EINVAL = -1,       /* invalid argument (sizes, ranges, NULL, theta outside [0, pi], NaN) */
+    GSHT_ENOMEM = -2,       /* device or host allocation failed, or above GSHT_MAX_WORKSPACE_BYTES */
+    GSHT_EHIP = -3,         /* a HIP or rocFFT call failed; see gsht_last_error() */
+    GSHT_EUNSUPPORTED = -4  /* valid request this build does not support (e.g. npts >= 2^31) */
+} gsht_status;
+
+typedef enum { GSHT_F64 = 0, GSHT_F32 = 1 } gsht_precision;
+
+/* Opaque plan: geometry (sorted points), grid sizes, FFT plans and workspace. */
+typedef struct gsht_plan gsht_plan;
+
+/*
+ * One-shot synthesis (Sect. 2, eq. "forward" / "forwardpol"; steps of Sect. 3).
+ *   alm   [ncomp][nalm] complex (complex128 for F64, complex64 for F32), read only.
+ *   map   [ncomp][npts] real (float64 / float32), overwritten.
+ * Builds a plan (bin sort of the points, FFT plans, workspace), runs it and
+ * frees it; the plan construction synchronises hip_stream once to validate
+ * the coordinates.  Use the plan API below to reuse a geometry.
+ */
+int gsht_synth_general(const void *alm, int lmax, int mmax, int spin,
+                       const double *theta, const double *phi, int64_t npts,
+                       double epsilon, gsht_precision prec, void *map, void *hip_stream);
+
+/*
+ * One-shot adjoint synthesis (Sect. 2, eq. "adjoint" and the gradient/curl split;
+ * the reversed steps of Sect. 3).
+ *   map   [ncomp][npts] real, read only.
+ *   alm   [ncomp][nalm] complex, overwritten (not accumulated).
+ * Same plan handling as gsht_synth_general.
+ */
+int gsht_adjoint_synth_general(const void *map, int lmax, int mmax, int spin,
+                               const double *theta, const double *phi, int64_t npts,
+                               double epsilon, gsht_precision prec, void *alm,
+                               void *hip_stream);
+
+/* Thread-local description of the last non-OK status ("" if none).  Host pointer,
+ * valid until the next library call on the same thread. */
+const char *gsht_last_error(void);
+
+/*
+ * Plan API: geometry reuse for many maps on the same points (Sect. 4 notes that
+ * many maps are deflected with one set of angles).
+ * gsht_plan_create validates the arguments, copies and bin-sorts the points
+ * into grid tiles, builds the FFT plans and allocates all workspace; it
+ * synchronises hip_stream before returning.  *p is set to NULL on failure.
+ * theta/phi are only read during the call.
+ */
+int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin,
+                     const double *theta, const double *phi, int64_t npts,
+                     double epsilon, gsht_precision prec, void *hip_stream);
+
+/* Synthesis with a plan: alm -> map (layouts as in gsht_synth_general).  Does not
+ * allocate and does not synchronise.  Calls on one plan must not overlap. */
+int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
+
+/* Adjoint with a plan: map -> alm.  Does not allocate and does not synchronise. */
+int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream);
+
+/* Release a plan and its workspace (NULL is ignored).  Synchronises the device. */
+void gsht_plan_destroy(gsht_plan *p);
+
+/* Sizes and parameters chosen by a plan (host struct filled by gsht_plan_get_info). */
+typedef struct {
+    int lmax, mmax, spin, ncomp;
+    int64_t npts;
+    double epsilon;
+    int precision;      /* gsht_precision */
+    int ntheta;         /* rings of the equidistant grid, poles included (>= lmax + 2) */
+    int ndouble;        /* 2 ntheta - 2: length of the doubled meridian */
+    int n1, n2;         /* oversampled torus (theta, phi) */
+    int w;              /* kernel support in grid cells */
+    double beta;        /* kernel shape: psi(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1 */
+    int nrows;          /* torus rows kept (theta in [0, pi] plus the kernel halo) */
+    int a_min;          /* torus row index (may be negative, modulo n1) of kept row 0 */
+    int tile1, tile2;   /* tile size in grid cells (rows, columns) */
+    int ntile1, ntile2; /* tiles per dimension; tile key = (row / tile1) * ntile2 + col / tile2 */
+    int64_t nchunks;    /* work items of the interpolation / spreading kernels */
+    int64_t workspace_bytes;
+} gsht_plan_info;
+
+/* Fill *info from a plan (host only). */
+int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info);
+
+/*
+ * Copy the plan's bin sort out to caller device buffers:
+ *   perm        int32 [npts]: perm[k] = input index of the k-th point in tile order
+ *               (stable: ties keep input order);
+ *   tile_start  int32 [ntile1 * ntile2 + 1]: first sorted position of each tile.
+ * Tile key of a point: u = theta * (n1 / (2 pi)), v = phi * (n2 / (2 pi)) (single
+ * rounded FP64 products), a0 = ceil(u - w/2), b0 = ceil(v - w/2),
+ * key = ((a0 - a_min) / tile1) * ntile2 + ((b0 mod n2) / tile2).
+ */
+int gsht_plan_get_sort(const gsht_plan *p, int32_t *perm, int32_t *tile_start, void *hip_stream);
+
+/*
+ * Per-stage timing.  With profiling on, every plan call records HIP events around
+ * each stage on hip_stream; gsht_plan_get_stage_times() synchronises on those events
+ * and returns, per stage, the total milliseconds and the number of recorded calls
+ * since profiling was switched on.  Stage ids are listed by gsht_stage_name().
+ */
+int gsht_plan_set_profiling(gsht_plan *p, int on);
+int gsht_plan_get_stage_times(gsht_plan *p, double *ms, int64_t *count, int nstages);
+int gsht_num_stages(void);
+const char *gsht_stage_name(int stage);
+
+/*
+ * Stage entry point: the "synthesis" and "doubling" steps of Sect. 3 alone.
+ * Evaluates F_m(theta_j) = sum_l c_lm sY_lm(theta_j, 0) on the rings
+ * theta_j = pi j / (ntheta - 1), j = 0..ntheta-1, and writes the doubled meridian
+ *   F[col][j]                       for j < ntheta,
+ *   F[col][2 ntheta - 2 - j] = (-1)^(s+m) F[col][j]   for 0 < j < ntheta - 1,
+ * where c_lm = a_lm (spin 0) or -(G_lm + i C_lm) (spin > 0, real-field convention
+ * for m < 0).  Columns: spin 0 -> col = m, 0..mmax; spin > 0 -> col = m + mmax,
+ * -mmax..mmax.  F is complex (complex128 for F64, complex64 for F32),
+ * [ncol][2 ntheta - 2].  ntheta >= lmax + 2 is required only for the later steps;
+ * here any ntheta >= 2 is accepted.
+ */
+int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int ntheta,
+                        gsht_precision prec, void *F, void *hip_stream);
+
+/*
+ * Stage entry point: "undoubling" and "adjoint synthesis" of Sect. 3.  Input F in
+ * the doubled layout above; rings 0 < j < ntheta - 1 receive
+ *   H_m(theta_j) = F[col][j] + (-1)^(s+m) F[col][2 ntheta - 2 - j],
+ * the poles H_m = F[col][j].  Output (overwritten): spin 0 b_lm = sum_j Y_lm(theta_j,0) H_m;
+ * spin s: S+ = sum_j sY_lm H_m, S- = sum_j (-s)Y_lm conj(H_{-m}), then the
+ * gradient/curl split as in gsht_adjoint_synth_general.
+ */
+int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int ntheta,
+                                gsht_precision prec, void *alm, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSHT_H */

@@ -1,0 +1,687 @@
+// C ABI of the gfx950 general-SHT library: argument validation, plan
+// construction (grid sizes, kernel parameters, deconvolution tables, bin sort,
+// rocFFT plans, workspace) and the order of the steps of Sect. 3.
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gsht_internal.hpp"
+
+namespace gsht {
+std::vector<StartInfo> make_start_info(int lmax, int mmax, int spin);
+}
+
+using namespace gsht;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return GSHT_OK;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(GSHT_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+#define FFT_TRY(expr)                                                                          \
+    do {                                                                                       \
+        rocfft_status s_ = (expr);                                                             \
+        if (s_ != rocfft_status_success)                                                       \
+            return fail(GSHT_EHIP, "%s failed: rocfft status %d", #expr, (int)s_);             \
+    } while (0)
+
+std::once_flag g_fft_once;
+
+bool smooth7(long n)
+{
+    if (n < 1)
+        return false;
+    for (long f : {2L, 3L, 5L, 7L})
+        while (n % f == 0)
+            n /= f;
+    return n == 1;
+}
+
+long next_smooth_even(long n)
+{
+    if (n < 2)
+        n = 2;
+    while (!(smooth7(n) && n % 2 == 0))
+        ++n;
+    return n;
+}
+
+// Relative L2 error of the 2-D type-2 NUFFT with this kernel at oversampling 2,
+// beta = 2.3 w, measured for w = 4..16 on random Fourier series.
+const double kEsError[17] = {0, 0, 0, 0, 7.8e-4, 8.8e-5, 9.7e-6, 1.2e-6, 1.5e-7,
+                             1.7e-8, 2.0e-9, 2.0e-10, 2.0e-11, 2.1e-12, 2.0e-13, 2.4e-14, 3.0e-15};
+
+int choose_w(double eps, int wmax)
+{
+    for (int w = 4; w <= wmax; ++w)
+        if (kEsError[w] <= 0.25 * eps)
+            return w;
+    return wmax;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &wt)
+{
+    x.assign(n, 0.0);
+    wt.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            pp = n * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / pp;
+            z -= dz;
+            if (fabs(dz) < 1e-16)
+                break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        wt[i] = wt[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+// h / psihat(k) for k = 0..kmax on an n-point periodic grid:
+//   psihat(k) = (w h / 2) J(k),  J(k) = int_{-1}^{1} exp(beta (sqrt(1 - z^2) - 1)) cos(pi k w z / n) dz
+// so h / psihat(k) = 2 / (w J(k)).
+std::vector<double> deconv_table(int kmax, int n, int w, double beta, double extra)
+{
+    const int nq = std::max(96, 4 * w + 64);
+    std::vector<double> z, wt;
+    gauss_legendre(nq, z, wt);
+    std::vector<double> phi(nq);
+    for (int i = 0; i < nq; ++i)
+        phi[i] = wt[i] * exp(beta * (sqrt(std::max(0.0, 1.0 - z[i] * z[i])) - 1.0));
+    std::vector<double> out((size_t)kmax + 1);
+    for (int k = 0; k <= kmax; ++k) {
+        double J = 0;
+        const double f = M_PI * (double)k * (double)w / (double)n;
+        for (int i = 0; i < nq; ++i)
+            J += phi[i] * cos(f * z[i]);
+        out[(size_t)k] = extra * 2.0 / ((double)w * J);
+    }
+    return out;
+}
+
+int check_common(int lmax, int mmax, int spin, int64_t npts, double eps, int prec)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "precision must be GSHT_F64 (0) or GSHT_F32 (1), got %d", prec);
+    if (lmax < 0 || lmax > 32766)
+        return fail(GSHT_EINVAL, "lmax must be in [0, 32766], got %d", lmax);
+    if (mmax < 0 || mmax > lmax)
+        return fail(GSHT_EINVAL, "mmax must be in [0, lmax], got mmax=%d lmax=%d", mmax, lmax);
+    if (spin < 0 || spin > lmax)
+        return fail(GSHT_EINVAL, "spin must be in [0, lmax], got spin=%d lmax=%d", spin, lmax);
+    if (npts < 0)
+        return fail(GSHT_EINVAL, "npts must be >= 0, got %lld", (long long)npts);
+    if (npts >= (int64_t)1 << 31)
+        return fail(GSHT_EUNSUPPORTED, "npts must be < 2^31, got %lld", (long long)npts);
+    const double lo = prec == GSHT_F64 ? 1e-13 : 1e-5;
+    if (!(eps >= lo && eps <= 0.1))
+        return fail(GSHT_EINVAL, "epsilon must be in [%g, 0.1] for this precision, got %g", lo, eps);
+    return GSHT_OK;
+}
+
+int64_t workspace_cap()
+{
+    const char *e = getenv("GSHT_MAX_WORKSPACE_BYTES");
+    if (!e || !*e)
+        return INT64_MAX;
+    return (int64_t)strtoll(e, nullptr, 10);
+}
+
+template <typename T>
+int dev_alloc(gsht_plan *p, T **ptr, size_t bytes)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GSHT_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    p->allocations.push_back(q);
+    *ptr = (T *)q;
+    return GSHT_OK;
+}
+
+void free_plan(gsht_plan *p)
+{
+    if (!p)
+        return;
+    (void)hipDeviceSynchronize();
+    for (FFTPlan *f : {&p->fD_fwd, &p->fD_inv, &p->fT_inv, &p->fT_fwd, &p->fP_inv, &p->fP_fwd}) {
+        if (f->info)
+            rocfft_execution_info_destroy(f->info);
+        if (f->plan)
+            rocfft_plan_destroy(f->plan);
+    }
+    for (void *q : p->allocations)
+        (void)hipFree(q);
+    for (int i = 0; i < 2 * ST_COUNT; ++i)
+        if (p->ev[i])
+            (void)hipEventDestroy(p->ev[i]);
+    delete p;
+}
+
+int make_fft(FFTPlan &f, rocfft_transform_type type, rocfft_result_placement place, int prec,
+             size_t len, size_t batch)
+{
+    const rocfft_precision rp = prec == GSHT_F64 ? rocfft_precision_double : rocfft_precision_single;
+    FFT_TRY(rocfft_plan_create(&f.plan, place, type, rp, 1, &len, batch, nullptr));
+    FFT_TRY(rocfft_plan_get_work_buffer_size(f.plan, &f.work_bytes));
+    FFT_TRY(rocfft_execution_info_create(&f.info));
+    return GSHT_OK;
+}
+
+int run_fft(const FFTPlan &f, void *in, void *out, void *work, size_t work_bytes, hipStream_t s)
+{
+    FFT_TRY(rocfft_execution_info_set_stream(f.info, s));
+    if (f.work_bytes)
+        FFT_TRY(rocfft_execution_info_set_work_buffer(f.info, work, work_bytes));
+    void *ib[1] = {in};
+    void *ob[1] = {out};
+    FFT_TRY(rocfft_execute(f.plan, ib, out ? ob : nullptr, f.info));
+    return GSHT_OK;
+}
+
+// Compute grid sizes and kernel parameters (host only).
+void choose_sizes(gsht_plan *p)
+{
+    p->ncomp = p->spin ? 2 : 1;
+    p->nalm = (int64_t)(p->mmax + 1) * (p->lmax + 1) - (int64_t)p->mmax * (p->mmax + 1) / 2;
+    long nt = std::max(p->lmax + 2, 2);
+    while (!smooth7(2 * nt - 2))
+        ++nt;
+    p->ntheta = (int)nt;
+    p->nd = 2 * p->ntheta - 2;
+    p->w = choose_w(p->eps, p->prec == GSHT_F64 ? 16 : 8);
+    p->beta = 2.3 * p->w;
+    const double sigma = 2.0;
+    p->n1 = (int)next_smooth_even(std::max<long>((long)ceil(sigma * (2 * p->lmax + 1)), 2 * p->w + 4));
+    p->n2 = (int)next_smooth_even(std::max<long>((long)ceil(sigma * (2 * p->mmax + 1)), 2 * p->w + 4));
+    p->a_min = -(p->w / 2);
+    p->nrows = p->n1 / 2 + p->w + 2;
+    p->t1 = 32;
+    p->t2 = 32;
+    p->nt1 = (p->nrows + p->t1 - 1) / p->t1;
+    p->nt2 = (p->n2 + p->t2 - 1) / p->t2;
+    p->ntiles = (int64_t)p->nt1 * p->nt2;
+    p->ncol = p->spin ? 2 * p->mmax + 1 : p->mmax + 1;
+    p->npairs = (p->ntheta + 1) / 2;
+}
+
+// Allocate the Legendre tables and upload the start data and deconvolution tables.
+int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
+{
+    int rc;
+    if ((rc = dev_alloc(p, &p->leg.ab, sizeof(double2) * (size_t)p->nalm)) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->leg.norm, sizeof(double) * (size_t)p->nalm)) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->leg.start, sizeof(StartInfo) * (size_t)(p->mmax + 1))) != GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &p->uprep, sizeof(double) * 2 * p->ncomp * (size_t)p->nalm)) != GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &p->acc, sizeof(double) * 2 * p->ncomp * (size_t)p->nalm)) != GSHT_OK)
+        return rc;
+    std::vector<StartInfo> si = make_start_info(p->lmax, p->mmax, p->spin);
+    HIP_TRY(hipMemcpyAsync(p->leg.start, si.data(), sizeof(StartInfo) * si.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_leg_tables(*p, s));
+    if (with_deconv) {
+        std::vector<double> k1 = deconv_table(p->lmax, p->n1, p->w, p->beta, 1.0 / p->nd);
+        std::vector<double> k2 = deconv_table(p->mmax, p->n2, p->w, p->beta, 1.0);
+        if ((rc = dev_alloc(p, &p->kfac1, sizeof(double) * k1.size())) != GSHT_OK) return rc;
+        if ((rc = dev_alloc(p, &p->kfac2, sizeof(double) * k2.size())) != GSHT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(p->kfac1, k1.data(), sizeof(double) * k1.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(p->kfac2, k2.data(), sizeof(double) * k2.size(),
+                               hipMemcpyHostToDevice, s));
+    }
+    // the host vectors above are synchronised before they go out of scope
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSHT_OK;
+}
+
+size_t csize(int prec) { return prec == GSHT_F64 ? 16 : 8; }
+
+int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double *theta,
+                     const double *phi, int64_t npts, double eps, int prec, hipStream_t s)
+{
+    int rc;
+    gsht_plan *p = new gsht_plan();
+    p->lmax = lmax;
+    p->mmax = mmax;
+    p->spin = spin;
+    p->npts = npts;
+    p->eps = eps;
+    p->prec = prec;
+    choose_sizes(p);
+    const size_t cs = csize(prec), rs = cs / 2;
+    const size_t gcols = spin ? (size_t)p->n2 : (size_t)p->n2 / 2 + 1;
+    // workspace estimate (before allocating anything large)
+    int64_t ws = 0;
+    ws += (int64_t)p->nalm * (16 + 8 + 2 * 16 * p->ncomp);   // ab, norm, uprep, acc
+    ws += (int64_t)p->ncol * p->nd * cs + (int64_t)p->ncol * p->n1 * cs;
+    ws += (int64_t)p->nrows * gcols * cs + (spin ? 0 : (int64_t)p->nrows * p->n2 * rs);
+    ws += npts * (16 + 4) + (p->ntiles + 1) * 4;
+    p->workspace_bytes = ws;
+    if (ws > workspace_cap()) {
+        delete p;
+        return fail(GSHT_ENOMEM, "workspace of %lld bytes exceeds GSHT_MAX_WORKSPACE_BYTES",
+                    (long long)ws);
+    }
+    std::call_once(g_fft_once, []() { rocfft_setup(); });
+    if ((rc = setup_legendre(p, s, true)) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->D, (size_t)p->ncol * p->nd * cs)) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->E, (size_t)p->ncol * p->n1 * cs)) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->G, (size_t)p->nrows * gcols * cs)) != GSHT_OK) { free_plan(p); return rc; }
+    if (!spin && (rc = dev_alloc(p, &p->g, (size_t)p->nrows * p->n2 * rs)) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->sth, sizeof(double) * (size_t)std::max<int64_t>(npts, 1))) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->sph, sizeof(double) * (size_t)std::max<int64_t>(npts, 1))) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->perm, sizeof(int32_t) * (size_t)std::max<int64_t>(npts, 1))) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = dev_alloc(p, &p->tile_start, sizeof(int32_t) * (size_t)(p->ntiles + 1))) != GSHT_OK) { free_plan(p); return rc; }
+    {
+        int64_t ninv = 0;
+        hipError_t e = run_binsort(*p, theta, phi, s, &ninv);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return fail(GSHT_EHIP, "bin sort failed: %s", hipGetErrorString(e));
+        }
+        if (ninv > 0) {
+            free_plan(p);
+            return fail(GSHT_EINVAL, "%lld point(s) have theta outside [0, pi] or non-finite phi",
+                        (long long)ninv);
+        }
+    }
+    // FFT plans
+    const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;
+    rc = make_fft(p->fD_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, nd, p->ncol);
+    if (rc == GSHT_OK) rc = make_fft(p->fD_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, nd, p->ncol);
+    if (rc == GSHT_OK) rc = make_fft(p->fT_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n1, p->ncol);
+    if (rc == GSHT_OK) rc = make_fft(p->fT_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n1, p->ncol);
+    if (rc == GSHT_OK) {
+        if (spin) {
+            rc = make_fft(p->fP_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n2, p->nrows);
+            if (rc == GSHT_OK) rc = make_fft(p->fP_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n2, p->nrows);
+        } else {
+            rc = make_fft(p->fP_inv, rocfft_transform_type_real_inverse, rocfft_placement_notinplace, prec, n2, p->nrows);
+            if (rc == GSHT_OK) rc = make_fft(p->fP_fwd, rocfft_transform_type_real_forward, rocfft_placement_notinplace, prec, n2, p->nrows);
+        }
+    }
+    if (rc != GSHT_OK) {
+        free_plan(p);
+        return rc;
+    }
+    size_t wb = 0;
+    for (FFTPlan *f : {&p->fD_fwd, &p->fD_inv, &p->fT_inv, &p->fT_fwd, &p->fP_inv, &p->fP_fwd})
+        wb = std::max(wb, f->work_bytes);
+    if (wb) {
+        if ((rc = dev_alloc(p, &p->fftwork, wb)) != GSHT_OK) { free_plan(p); return rc; }
+        p->fftwork_bytes = wb;
+    }
+    p->workspace_bytes += (int64_t)wb;
+    *out = p;
+    return ok();
+}
+
+// ---- profiling ----------------------------------------------------------------
+
+struct StageScope {
+    gsht_plan *p;
+    int st;
+    hipStream_t s;
+    StageScope(gsht_plan *p_, int st_, hipStream_t s_) : p(p_), st(st_), s(s_)
+    {
+        if (!p->profiling)
+            return;
+        if (p->ev_pending[st]) {  // fold in the previous call's interval first
+            float ms = 0;
+            (void)hipEventSynchronize(p->ev[2 * st + 1]);
+            if (hipEventElapsedTime(&ms, p->ev[2 * st], p->ev[2 * st + 1]) == hipSuccess) {
+                p->st_ms[st] += ms;
+                p->st_count[st] += 1;
+            }
+            p->ev_pending[st] = 0;
+        }
+        (void)hipEventRecord(p->ev[2 * st], s);
+    }
+    ~StageScope()
+    {
+        if (!p->profiling)
+            return;
+        (void)hipEventRecord(p->ev[2 * st + 1], s);
+        p->ev_pending[st] = 1;
+    }
+};
+
+#define STAGE(st) StageScope stage_scope_##st(p, st, s)
+
+int check_launch(hipError_t e, const char *what)
+{
+    if (e != hipSuccess)
+        return fail(GSHT_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return GSHT_OK;
+}
+
+#define RUN(stage, expr)                                                                       \
+    do {                                                                                       \
+        STAGE(stage);                                                                          \
+        int rc_ = check_launch((expr), #expr);                                                 \
+        if (rc_ != GSHT_OK)                                                                    \
+            return rc_;                                                                        \
+    } while (0)
+
+#define RUNFFT(stage, expr)                                                                    \
+    do {                                                                                       \
+        STAGE(stage);                                                                          \
+        int rc_ = (expr);                                                                      \
+        if (rc_ != GSHT_OK)                                                                    \
+            return rc_;                                                                        \
+    } while (0)
+
+int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s)
+{
+    RUN(ST_PREP, launch_prep_alm(*p, alm, s));
+    RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, s));
+    RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_DECONV_FWD, launch_deconv_fwd(*p, s));
+    RUNFFT(ST_FFT_THETA_INV, run_fft(p->fT_inv, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_TRANSPOSE_FWD, launch_transpose_fwd(*p, s));
+    if (p->spin)
+        RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
+    else
+        RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, p->g, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_INTERP, launch_interp(*p, map, s));
+    return ok();
+}
+
+int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s)
+{
+    const size_t cs = csize(p->prec);
+    if (p->spin)
+        RUN(ST_ZERO_GRID, launch_zero(p->G, (size_t)p->nrows * p->n2 * cs, s));
+    else
+        RUN(ST_ZERO_GRID, launch_zero(p->g, (size_t)p->nrows * p->n2 * (cs / 2), s));
+    RUN(ST_SPREAD, launch_spread(*p, map, s));
+    if (p->spin)
+        RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
+    else
+        RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->g, p->G, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_TRANSPOSE_ADJ, launch_transpose_adj(*p, s));
+    RUNFFT(ST_FFT_THETA_FWD, run_fft(p->fT_fwd, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_DECONV_ADJ, launch_deconv_adj(*p, s));
+    RUNFFT(ST_FFT_D_INV, run_fft(p->fD_inv, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
+    RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, s));
+    RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, s));
+    return ok();
+}
+
+const char *kStageNames[ST_COUNT] = {
+    "prep_alm",     "legendre_synth", "fft_doubled_fwd", "deconv_fwd", "fft_theta_inv",
+    "transpose_fwd", "fft_phi_inv",   "interp",          "zero_grid",  "spread",
+    "fft_phi_fwd",  "transpose_adj",  "fft_theta_fwd",   "deconv_adj", "fft_doubled_inv",
+    "legendre_adj", "finalize"};
+
+}  // namespace
+
+extern "C" {
+
+const char *gsht_last_error(void) { return g_last_error.c_str(); }
+
+int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
+                     const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                     void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan output pointer is NULL");
+    *p = nullptr;
+    int rc = check_common(lmax, mmax, spin, npts, epsilon, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (npts > 0 && (!theta || !phi))
+        return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
+    return plan_create_impl(p, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec,
+                            (hipStream_t)hip_stream);
+}
+
+int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!alm || (!map && p->npts > 0))
+        return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    return plan_synth_impl(p, alm, map, (hipStream_t)hip_stream);
+}
+
+int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!alm || (!map && p->npts > 0))
+        return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+}
+
+void gsht_plan_destroy(gsht_plan *p) { free_plan(p); }
+
+int gsht_synth_general(const void *alm, int lmax, int mmax, int spin, const double *theta,
+                       const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                       void *map, void *hip_stream)
+{
+    if (!alm || (!map && npts > 0))
+        return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    gsht_plan *p = nullptr;
+    int rc = gsht_plan_create(&p, lmax, mmax, spin, theta, phi, npts, epsilon, prec, hip_stream);
+    if (rc != GSHT_OK)
+        return rc;
+    rc = plan_synth_impl(p, alm, map, (hipStream_t)hip_stream);
+    free_plan(p);
+    return rc;
+}
+
+int gsht_adjoint_synth_general(const void *map, int lmax, int mmax, int spin, const double *theta,
+                               const double *phi, int64_t npts, double epsilon,
+                               gsht_precision prec, void *alm, void *hip_stream)
+{
+    if (!alm || (!map && npts > 0))
+        return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    gsht_plan *p = nullptr;
+    int rc = gsht_plan_create(&p, lmax, mmax, spin, theta, phi, npts, epsilon, prec, hip_stream);
+    if (rc != GSHT_OK)
+        return rc;
+    rc = plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+    free_plan(p);
+    return rc;
+}
+
+int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
+{
+    if (!p || !info)
+        return fail(GSHT_EINVAL, "plan/info must not be NULL");
+    info->lmax = p->lmax;
+    info->mmax = p->mmax;
+    info->spin = p->spin;
+    info->ncomp = p->ncomp;
+    info->npts = p->npts;
+    info->epsilon = p->eps;
+    info->precision = p->prec;
+    info->ntheta = p->ntheta;
+    info->ndouble = p->nd;
+    info->n1 = p->n1;
+    info->n2 = p->n2;
+    info->w = p->w;
+    info->beta = p->beta;
+    info->nrows = p->nrows;
+    info->a_min = p->a_min;
+    info->tile1 = p->t1;
+    info->tile2 = p->t2;
+    info->ntile1 = p->nt1;
+    info->ntile2 = p->nt2;
+    info->nchunks = p->nchunks;
+    info->workspace_bytes = p->workspace_bytes;
+    return ok();
+}
+
+int gsht_plan_get_sort(const gsht_plan *p, int32_t *perm, int32_t *tile_start, void *hip_stream)
+{
+    if (!p || !perm || !tile_start)
+        return fail(GSHT_EINVAL, "plan/perm/tile_start must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (p->npts > 0)
+        HIP_TRY(hipMemcpyAsync(perm, p->perm, sizeof(int32_t) * (size_t)p->npts,
+                               hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(tile_start, p->tile_start, sizeof(int32_t) * (size_t)(p->ntiles + 1),
+                           hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+int gsht_plan_set_profiling(gsht_plan *p, int on)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (on) {
+        for (int i = 0; i < 2 * ST_COUNT; ++i)
+            if (!p->ev[i])
+                HIP_TRY(hipEventCreate(&p->ev[i]));
+    }
+    for (int i = 0; i < ST_COUNT; ++i) {
+        p->st_ms[i] = 0;
+        p->st_count[i] = 0;
+        p->ev_pending[i] = 0;
+    }
+    p->profiling = on ? 1 : 0;
+    return ok();
+}
+
+int gsht_plan_get_stage_times(gsht_plan *p, double *ms, int64_t *count, int nstages)
+{
+    if (!p || !ms || !count)
+        return fail(GSHT_EINVAL, "plan/ms/count must not be NULL");
+    for (int st = 0; st < ST_COUNT; ++st) {
+        if (p->ev_pending[st]) {
+            float t = 0;
+            HIP_TRY(hipEventSynchronize(p->ev[2 * st + 1]));
+            HIP_TRY(hipEventElapsedTime(&t, p->ev[2 * st], p->ev[2 * st + 1]));
+            p->st_ms[st] += t;
+            p->st_count[st] += 1;
+            p->ev_pending[st] = 0;
+        }
+    }
+    for (int st = 0; st < nstages && st < ST_COUNT; ++st) {
+        ms[st] = p->st_ms[st];
+        count[st] = p->st_count[st];
+    }
+    return ok();
+}
+
+int gsht_num_stages(void) { return ST_COUNT; }
+
+const char *gsht_stage_name(int stage)
+{
+    if (stage < 0 || stage >= ST_COUNT)
+        return "";
+    return kStageNames[stage];
+}
+
+int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int ntheta,
+                        gsht_precision prec, void *F, void *hip_stream)
+{
+    int rc = check_common(lmax, mmax, spin, 0, prec == GSHT_F64 ? 1e-10 : 1e-5, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (ntheta < 2 || ntheta > 1 << 20)
+        return fail(GSHT_EINVAL, "ntheta must be in [2, 2^20], got %d", ntheta);
+    if (!alm || !F)
+        return fail(GSHT_EINVAL, "alm/F must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    gsht_plan *p = new gsht_plan();
+    p->lmax = lmax;
+    p->mmax = mmax;
+    p->spin = spin;
+    p->prec = (int)prec;
+    p->ncomp = spin ? 2 : 1;
+    p->nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+    p->ntheta = ntheta;
+    p->nd = 2 * ntheta - 2;
+    p->ncol = spin ? 2 * mmax + 1 : mmax + 1;
+    p->npairs = (ntheta + 1) / 2;
+    if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
+    int rc2 = check_launch(launch_prep_alm(*p, alm, s), "prep_alm");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(launch_leg_synth(*p, F, s), "legendre_synth");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
+    free_plan(p);
+    return rc2 == GSHT_OK ? ok() : rc2;
+}
+
+int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int ntheta,
+                                gsht_precision prec, void *alm, void *hip_stream)
+{
+    int rc = check_common(lmax, mmax, spin, 0, prec == GSHT_F64 ? 1e-10 : 1e-5, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (ntheta < 2 || ntheta > 1 << 20)
+        return fail(GSHT_EINVAL, "ntheta must be in [2, 2^20], got %d", ntheta);
+    if (!alm || !F)
+        return fail(GSHT_EINVAL, "alm/F must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    gsht_plan *p = new gsht_plan();
+    p->lmax = lmax;
+    p->mmax = mmax;
+    p->spin = spin;
+    p->prec = (int)prec;
+    p->ncomp = spin ? 2 : 1;
+    p->nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+    p->ntheta = ntheta;
+    p->nd = 2 * ntheta - 2;
+    p->ncol = spin ? 2 * mmax + 1 : mmax + 1;
+    p->npairs = (ntheta + 1) / 2;
+    if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
+    int rc2 = check_launch(launch_leg_adjoint(*p, F, s), "legendre_adjoint");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(launch_leg_finalize(*p, alm, s), "finalize");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
+    free_plan(p);
+    return rc2 == GSHT_OK ? ok() : rc2;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal declarations of the gfx950 general-SHT library: the plan object, the
+// per-m start data of the Legendre recurrence and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gsht.h"
+
+namespace gsht {
+
+// Start data of the recurrence for one m: the first non-zero degree l0 and, for
+// the two channels sigma = +s and sigma = -s, the l-independent factor of
+// sY_{l0 m} as (mantissa, binary exponent) and the half-angle exponents:
+//   sY_{l0 m}(theta) = mant * 2^ex * sin(theta/2)^a * cos(theta/2)^b.
+struct StartInfo {
+    int l0;
+    int a_p, b_p, ex_p;  // channel +s
+    int a_m, b_m, ex_m;  // channel -s
+    int pad;
+    double mant_p, mant_m;
+};
+
+// Device tables of the normalised recurrence p_{l+1} = (a_l x + sigma b_l) p_l - p_{l-1},
+// p_l = sY_lm / N_l (identical a_l, b_l, N_l for both channels).
+struct LegendreTables {
+    double2 *ab = nullptr;     // [nalm]  (a_l, b_l) at idx(l, m), valid for l0 <= l < lmax
+    double *norm = nullptr;    // [nalm]  N_l
+    StartInfo *start = nullptr;  // [mmax + 1]
+};
+
+enum Stage {
+    ST_PREP = 0,
+    ST_LEG_SYNTH,
+    ST_FFT_D_FWD,
+    ST_DECONV_FWD,
+    ST_FFT_THETA_INV,
+    ST_TRANSPOSE_FWD,
+    ST_FFT_PHI_INV,
+    ST_INTERP,
+    ST_ZERO_GRID,
+    ST_SPREAD,
+    ST_FFT_PHI_FWD,
+    ST_TRANSPOSE_ADJ,
+    ST_FFT_THETA_FWD,
+    ST_DECONV_ADJ,
+    ST_FFT_D_INV,
+    ST_LEG_ADJ,
+    ST_FINALIZE,
+    ST_COUNT
+};
+
+struct FFTPlan {
+    rocfft_plan plan = nullptr;
+    rocfft_execution_info info = nullptr;
+    size_t work_bytes = 0;
+};
+
+}  // namespace gsht
+
+struct gsht_plan {
+    // problem
+    int lmax = 0, mmax = 0, spin = 0, ncomp = 1;
+    int64_t npts = 0;
+    double eps = 0;
+    int prec = GSHT_F64;
+    int64_t nalm = 0;
+    // grids
+    int ntheta = 0, nd = 0, n1 = 0, n2 = 0, w = 0;
+    double beta = 0;
+    int nrows = 0, a_min = 0;
+    int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
+    int64_t ntiles = 0, nchunks = 0;
+    int ncol = 0, npairs = 0;
+    int64_t workspace_bytes = 0;
+    // device tables
+    gsht::LegendreTables leg;
+    double *uprep = nullptr;   // prepared coefficients [nalm][2 or 4]
+    double *kfac1 = nullptr;   // [lmax + 1] theta deconvolution factor (incl. 1/nd)
+    double *kfac2 = nullptr;   // [mmax + 1] phi deconvolution factor
+    // geometry
+    double *sth = nullptr, *sph = nullptr;  // sorted coordinates
+    int32_t *perm = nullptr;                // sorted position -> input index
+    int32_t *tile_start = nullptr;          // [ntiles + 1]
+    int4 *chunks = nullptr;                 // [nchunks] (tile, begin, end, 0)
+    // work buffers
+    void *D = nullptr;     // [ncol][nd] complex
+    void *E = nullptr;     // [ncol][n1] complex
+    void *G = nullptr;     // complex grid [nrows][n2] (spin > 0) or half spectrum [nrows][n2/2+1]
+    void *g = nullptr;     // real grid [nrows][n2] (spin 0 only)
+    double *acc = nullptr; // adjoint accumulators [nalm][2 * ncomp]
+    // FFT plans
+    gsht::FFTPlan fD_fwd, fD_inv, fT_inv, fT_fwd, fP_inv, fP_fwd;
+    void *fftwork = nullptr;
+    size_t fftwork_bytes = 0;
+    // profiling
+    int profiling = 0;
+    hipEvent_t ev[2 * gsht::ST_COUNT] = {};
+    int ev_pending[gsht::ST_COUNT] = {};
+    double st_ms[gsht::ST_COUNT] = {};
+    int64_t st_count[gsht::ST_COUNT] = {};
+    std::vector<void *> allocations;
+};
+
+namespace gsht {
+
+// ---- Legendre step (legendre.hip) ------------------------------------------
+hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s);
+hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, hipStream_t s);
+hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s);
+hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s);
+hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, hipStream_t s);
+
+// ---- staging (staging.hip) -------------------------------------------------
+hipError_t launch_deconv_fwd(const gsht_plan &p, hipStream_t s);     // D -> E
+hipError_t launch_transpose_fwd(const gsht_plan &p, hipStream_t s);  // E -> G
+hipError_t launch_transpose_adj(const gsht_plan &p, hipStream_t s);  // G -> E
+hipError_t launch_deconv_adj(const gsht_plan &p, hipStream_t s);     // E -> D
+hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
+
+// ---- points (nufft.hip) ----------------------------------------------------
+// Bin sort; returns the number of invalid coordinates through *n_invalid (host)
+// after synchronising the stream.
+hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hipStream_t s,
+                       int64_t *n_invalid);
+hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s);
+hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s);
+
+}  // namespace gsht

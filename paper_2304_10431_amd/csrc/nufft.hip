@@ -1,0 +1,654 @@
+// Point side of the general SHT on gfx950: the bin sort of points into grid
+// tiles, the type-2 NUFFT interpolation ("NUFFT" step of Sect. 3) and its exact
+// transpose, the type-1 spreading (first adjoint step of Sect. 3).
+//
+// Kernel: psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, the exponential of
+// semicircle of Barnett et al. (2019) named in Sect. 3.  A point at
+// u = theta n1 / (2 pi), v = phi n2 / (2 pi) touches the w x w cells
+// a0 + i, b0 + j with a0 = ceil(u - w/2), b0 = ceil(v - w/2), with weights
+// psi((u - a0 - i) 2/w) psi((v - b0 - j) 2/w).  Offsets are formed in FP64 and
+// only then rounded to the working precision.
+//
+// Points are processed in tile order: every work item ("chunk") holds at most
+// CHUNK consecutive sorted points of one tile, and stages that tile's grid patch
+// (tile plus a w - 1 halo) in LDS.  Spreading accumulates into the LDS patch with
+// LDS atomics and then flushes the patch to the grid with global atomics.
+#include "gsht_internal.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace gsht {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;  // per thread
+constexpr int SORT_BLOCK = SORT_THREADS * SORT_ITEMS;
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int CHUNK = 512;
+constexpr int NUFFT_THREADS = 256;
+
+// ---- keys ------------------------------------------------------------------------
+
+struct KeyParams {
+    double c1, c2, half;
+    int a_min, n2, t1, t2, nt2, nrows, w;
+};
+
+// Single-rounded products and differences (no FMA contraction), so that the keys
+// match a plain FP64 evaluation bit for bit.
+__device__ inline double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ inline double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+
+__global__ void keys_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
+                            int64_t npts, KeyParams kp, int32_t *__restrict__ keys,
+                            int32_t *__restrict__ vals, unsigned long long *__restrict__ n_invalid)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts)
+        return;
+    const double th = theta[i], ph = phi[i];
+    int key = 0;
+    const bool ok = (th >= 0.0) && (th <= 3.141592653589793) && isfinite(ph);
+    if (!ok) {
+        atomicAdd(n_invalid, 1ull);
+    } else {
+        const double u = mul_rn(th, kp.c1);
+        const double v = mul_rn(ph, kp.c2);
+        const int64_t a0 = (int64_t)ceil(sub_rn(u, kp.half));
+        const double vb = ceil(sub_rn(v, kp.half));
+        int64_t r0 = a0 - kp.a_min;
+        if (r0 < 0)
+            r0 = 0;
+        if (r0 > kp.nrows - kp.w)
+            r0 = kp.nrows - kp.w;
+        // b0 mod n2 without overflowing for large |phi|
+        double bm = fmod(vb, (double)kp.n2);
+        if (bm < 0)
+            bm += kp.n2;
+        int bi = (int)bm;
+        if (bi >= kp.n2)
+            bi -= kp.n2;
+        key = (int)(r0 / kp.t1) * kp.nt2 + bi / kp.t2;
+    }
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+}
+
+// ---- stable LSD radix sort of (key, value) pairs -------------------------------
+
+__global__ __launch_bounds__(SORT_THREADS) void radix_hist_kernel(const int32_t *__restrict__ keys,
+                                                                  int64_t n, int shift, int nblocks,
+                                                                  int32_t *__restrict__ counts)
+{
+    __shared__ int h[RADIX];
+    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS)
+        h[d] = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * SORT_BLOCK;
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        const int64_t i = b0 + it * SORT_THREADS + threadIdx.x;
+        if (i < n)
+            atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < RADIX; d += SORT_THREADS)
+        counts[(size_t)d * nblocks + blockIdx.x] = h[d];
+}
+
+// Exclusive scan helpers (int32, total < 2^31).
+constexpr int SCAN_TILE = 1024;
+
+__global__ __launch_bounds__(SCAN_TILE) void scan_tile_sums(const int32_t *__restrict__ in, int64_t n,
+                                                            int32_t *__restrict__ sums)
+{
+    __shared__ int s[SCAN_TILE];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+    s[threadIdx.x] = (i < n) ? in[i] : 0;
+    __syncthreads();
+    for (int d = SCAN_TILE / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            s[threadIdx.x] += s[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        sums[blockIdx.x] = s[0];
+}
+
+// Single block: exclusive scan of the tile sums in place (sequential over
+// groups of SCAN_TILE, each group scanned in LDS).
+__global__ __launch_bounds__(SCAN_TILE) void scan_sums_kernel(int32_t *__restrict__ sums, int64_t n)
+{
+    __shared__ int s[SCAN_TILE];
+    int carry = 0;
+    for (int64_t g = 0; g < n; g += SCAN_TILE) {
+        const int64_t i = g + threadIdx.x;
+        const int v = (i < n) ? sums[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < SCAN_TILE; d <<= 1) {
+            const int t = ((int)threadIdx.x >= d) ? s[threadIdx.x - d] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n)
+            sums[i] = carry + s[threadIdx.x] - v;
+        const int tot = s[SCAN_TILE - 1];
+        __syncthreads();
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_TILE) void scan_apply_kernel(const int32_t *__restrict__ in, int64_t n,
+                                                               const int32_t *__restrict__ sums,
+                                                               int32_t *__restrict__ out)
+{
+    __shared__ int s[SCAN_TILE];
+    const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+    const int v = (i < n) ? in[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_TILE; d <<= 1) {
+        const int t = ((int)threadIdx.x >= d) ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n)
+        out[i] = sums[blockIdx.x] + s[threadIdx.x] - v;
+}
+
+static hipError_t exclusive_scan(const int32_t *in, int64_t n, int32_t *out, int32_t *tmp,
+                                 hipStream_t s)
+{
+    const int64_t ntile = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)ntile), dim3(SCAN_TILE), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_TILE), 0, s, tmp, ntile);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)ntile), dim3(SCAN_TILE), 0, s, in, n, tmp,
+                       out);
+    return hipGetLastError();
+}
+
+// Stable scatter: items of a block are ranked in input order.  Each round takes
+// SORT_THREADS consecutive items; within a wave, lanes with equal digits are found
+// with one ballot per digit bit.
+__global__ __launch_bounds__(SORT_THREADS) void radix_scatter_kernel(
+    const int32_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n, int shift,
+    int nblocks, const int32_t *__restrict__ offsets, int32_t *__restrict__ kout,
+    int32_t *__restrict__ vout)
+{
+    constexpr int NW = SORT_THREADS / 64;
+    __shared__ int run[RADIX];
+    __shared__ int wcnt[NW][RADIX];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int d = tid; d < RADIX; d += SORT_THREADS)
+        run[d] = offsets[(size_t)d * nblocks + blockIdx.x];
+    const int64_t b0 = (int64_t)blockIdx.x * SORT_BLOCK;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        for (int d = tid; d < NW * RADIX; d += SORT_THREADS)
+            (&wcnt[0][0])[d] = 0;
+        __syncthreads();
+        const int64_t i = b0 + (int64_t)it * SORT_THREADS + tid;
+        const bool valid = i < n;
+        const int k = valid ? kin[i] : 0;
+        const int dg = valid ? ((k >> shift) & (RADIX - 1)) : 0;
+        unsigned long long eq = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            const unsigned long long bb = __ballot(valid && ((dg >> b) & 1));
+            eq &= ((dg >> b) & 1) ? bb : ~bb;
+        }
+        const int rank_w = __popcll(eq & lt);
+        if (valid && rank_w == 0)
+            wcnt[wv][dg] = __popcll(eq);
+        __syncthreads();
+        if (valid) {
+            int off = run[dg];
+            for (int w2 = 0; w2 < wv; ++w2)
+                off += wcnt[w2][dg];
+            const int dst = off + rank_w;
+            if (dst >= 0 && dst < n) {
+                kout[dst] = k;
+                vout[dst] = vin[i];
+            }
+        }
+        __syncthreads();
+        for (int d = tid; d < RADIX; d += SORT_THREADS) {
+            int t = 0;
+            for (int w2 = 0; w2 < NW; ++w2)
+                t += wcnt[w2][d];
+            run[d] += t;
+        }
+        __syncthreads();
+    }
+}
+
+// tile_start[t] = first sorted position with key >= t.
+__global__ void tile_start_kernel(const int32_t *__restrict__ skeys, int64_t n, int64_t ntiles,
+                                  int32_t *__restrict__ start)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n)
+        return;
+    const int64_t lo = (p == 0) ? 0 : (int64_t)skeys[p - 1] + 1;
+    const int64_t hi = (p == n) ? ntiles : (int64_t)skeys[p];
+    for (int64_t t = lo; t <= hi; ++t)
+        start[t] = (int32_t)p;
+}
+
+__global__ void chunk_count_kernel(const int32_t *__restrict__ start, int64_t ntiles,
+                                   int32_t *__restrict__ cnt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles)
+        return;
+    const int c = start[t + 1] - start[t];
+    cnt[t] = (c + CHUNK - 1) / CHUNK;
+}
+
+__global__ void chunk_fill_kernel(const int32_t *__restrict__ start, const int32_t *__restrict__ coff,
+                                  int64_t ntiles, int4 *__restrict__ chunks)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles)
+        return;
+    const int b = start[t], e = start[t + 1];
+    int o = coff[t];
+    for (int c = b; c < e; c += CHUNK)
+        chunks[o++] = make_int4((int)t, c, (c + CHUNK < e) ? c + CHUNK : e, 0);
+}
+
+__global__ void gather_coords_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
+                                     const int32_t *__restrict__ perm, int64_t n,
+                                     double *__restrict__ sth, double *__restrict__ sph)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n)
+        return;
+    const int32_t i = perm[p];
+    sth[p] = theta[i];
+    sph[p] = phi[i];
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hipStream_t s,
+                       int64_t *n_invalid)
+{
+    const int64_t n = p.npts;
+    hipError_t e;
+    *n_invalid = 0;
+    // scratch: keys/vals double buffers, counts, scan temp
+    const int64_t nblocks = (n + SORT_BLOCK - 1) / SORT_BLOCK;
+    const int64_t ncount = nblocks * RADIX;
+    const int64_t nscan = (std::max(ncount, p.ntiles) + SCAN_TILE - 1) / SCAN_TILE + 1;
+    int32_t *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr, *cnt = nullptr,
+            *tmp = nullptr;
+    unsigned long long *inval = nullptr;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t ncnt = (size_t)std::max<int64_t>(std::max(ncount, p.ntiles + 1), 1);
+    if ((e = hipMalloc(&k0, nn * 4)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&k1, nn * 4)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&v0, nn * 4)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&v1, nn * 4)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&cnt, ncnt * 4)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&tmp, (size_t)nscan * 4 + 16)) != hipSuccess) goto out;
+    if ((e = hipMalloc(&inval, sizeof(unsigned long long))) != hipSuccess) goto out;
+    if ((e = launch_zero(inval, sizeof(unsigned long long), s)) != hipSuccess) goto out;
+    if (n > 0) {
+        KeyParams kp;
+        kp.c1 = (double)p.n1 / (2.0 * 3.141592653589793);
+        kp.c2 = (double)p.n2 / (2.0 * 3.141592653589793);
+        kp.half = 0.5 * (double)p.w;
+        kp.a_min = p.a_min;
+        kp.n2 = p.n2;
+        kp.t1 = p.t1;
+        kp.t2 = p.t2;
+        kp.nt2 = p.nt2;
+        kp.nrows = p.nrows;
+        kp.w = p.w;
+        hipLaunchKernelGGL(keys_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, theta, phi, n, kp, k0,
+                           v0, inval);
+        if ((e = hipGetLastError()) != hipSuccess) goto out;
+        int bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) < p.ntiles)
+            ++bits;
+        for (int shift = 0; shift < bits; shift += RADIX_BITS) {
+            hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nblocks), dim3(SORT_THREADS), 0, s,
+                               k0, n, shift, (int)nblocks, cnt);
+            if ((e = exclusive_scan(cnt, ncount, cnt, tmp, s)) != hipSuccess) goto out;
+            hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nblocks), dim3(SORT_THREADS), 0,
+                               s, k0, v0, n, shift, (int)nblocks, cnt, k1, v1);
+            if ((e = hipGetLastError()) != hipSuccess) goto out;
+            std::swap(k0, k1);
+            std::swap(v0, v1);
+        }
+    }
+    hipLaunchKernelGGL(tile_start_kernel, dim3(nblk(n + 1, 256)), dim3(256), 0, s, k0, n, p.ntiles,
+                       p.tile_start);
+    if ((e = hipMemcpyAsync(p.perm, v0, nn * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
+    if (n > 0) {
+        hipLaunchKernelGGL(gather_coords_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, theta, phi,
+                           p.perm, n, p.sth, p.sph);
+    }
+    // chunk list
+    hipLaunchKernelGGL(chunk_count_kernel, dim3(nblk(p.ntiles, 256)), dim3(256), 0, s, p.tile_start,
+                       p.ntiles, cnt);
+    if ((e = exclusive_scan(cnt, p.ntiles, cnt, tmp, s)) != hipSuccess) goto out;
+    {
+        int32_t last_off = 0, last_cnt = 0, tot;
+        unsigned long long hinv = 0;
+        // total chunks = offset of the last tile + its chunk count
+        int32_t ends[2];
+        if ((e = hipMemcpyAsync(&last_off, cnt + (p.ntiles - 1), 4, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess) goto out;
+        if ((e = hipMemcpyAsync(ends, p.tile_start + (p.ntiles - 1), 8, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess) goto out;
+        if ((e = hipMemcpyAsync(&hinv, inval, sizeof(hinv), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            goto out;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) goto out;
+        last_cnt = (ends[1] - ends[0] + CHUNK - 1) / CHUNK;
+        tot = last_off + last_cnt;
+        *n_invalid = (int64_t)hinv;
+        p.nchunks = tot;
+        if (tot > 0) {
+            if ((e = hipMalloc(&p.chunks, (size_t)tot * sizeof(int4))) != hipSuccess) goto out;
+            p.allocations.push_back(p.chunks);
+            hipLaunchKernelGGL(chunk_fill_kernel, dim3(nblk(p.ntiles, 256)), dim3(256), 0, s,
+                               p.tile_start, cnt, p.ntiles, p.chunks);
+            if ((e = hipGetLastError()) != hipSuccess) goto out;
+        }
+        e = hipStreamSynchronize(s);
+    }
+out:
+    hipFree(k0);
+    hipFree(k1);
+    hipFree(v0);
+    hipFree(v1);
+    hipFree(cnt);
+    hipFree(tmp);
+    hipFree(inval);
+    return e;
+}
+
+// ---- interpolation and spreading ------------------------------------------------
+
+template <typename T> struct cpl;
+template <> struct cpl<float> { using type = float2; };
+template <> struct cpl<double> { using type = double2; };
+
+template <typename T> __device__ inline T es_kernel(T z, T beta);
+template <> __device__ inline float es_kernel<float>(float z, float beta)
+{
+    return __expf(beta * (sqrtf(fmaxf(0.0f, 1.0f - z * z)) - 1.0f));
+}
+template <> __device__ inline double es_kernel<double>(double z, double beta)
+{
+    return exp(beta * (sqrt(fmax(0.0, 1.0 - z * z)) - 1.0));
+}
+
+struct GridGeom {
+    double c1, c2, half;
+    int a_min, n2, stride, nrows, t1, t2, nt2;
+    int64_t npts;
+};
+
+// Cell indices and kernel weights of one point, relative to a patch origin.
+template <typename T, int W>
+__device__ inline void point_weights(double th, double ph, const GridGeom &g, int row0, int col0,
+                                     T beta, int &lr, int &lc, T (&wx)[W], T (&wy)[W])
+{
+    const double u = __dmul_rn(th, g.c1);
+    const double v = __dmul_rn(ph, g.c2);
+    const double a0 = ceil(__dsub_rn(u, g.half));
+    const double b0 = ceil(__dsub_rn(v, g.half));
+    const double dx = u - a0, dy = v - b0;  // in (w/2 - 1, w/2]
+    double bm = fmod(b0, (double)g.n2);
+    if (bm < 0)
+        bm += g.n2;
+    int bi = (int)bm;
+    if (bi >= g.n2)
+        bi -= g.n2;
+    int r0 = (int)a0 - g.a_min;
+    if (r0 < 0)
+        r0 = 0;
+    if (r0 > g.nrows - W)
+        r0 = g.nrows - W;
+    lr = r0 - row0;
+    lc = bi - col0;
+    const T sc = (T)(2.0 / W);
+    const T fx = (T)dx, fy = (T)dy;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        wx[i] = es_kernel<T>((fx - (T)i) * sc, beta);
+        wy[i] = es_kernel<T>((fy - (T)i) * sc, beta);
+    }
+}
+
+template <typename T, int W, bool CPLX>
+__global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
+    const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
+    const int32_t *__restrict__ perm, const void *__restrict__ gridv, GridGeom g, T beta,
+    T *__restrict__ out)
+{
+    using C = typename cpl<T>::type;
+    using V = typename std::conditional<CPLX, C, T>::type;
+    extern __shared__ unsigned char smem_raw[];
+    V *patch = reinterpret_cast<V *>(smem_raw);
+    const V *grid = reinterpret_cast<const V *>(gridv);
+    const int4 ck = chunks[blockIdx.x];
+    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
+        const int pr = idx / PC, pc = idx - (idx / PC) * PC;
+        const int r = row0 + pr;
+        int c = col0 + pc;
+        if (c >= g.n2)
+            c -= g.n2;
+        V v{};
+        if (r < g.nrows)
+            v = grid[(size_t)r * g.stride + c];
+        patch[idx] = v;
+    }
+    __syncthreads();
+    for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
+        T wx[W], wy[W];
+        int lr, lc;
+        point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
+        if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
+            continue;  // cannot happen for points sorted by the same arithmetic
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const V *rowp = patch + (lr + i) * PC + lc;
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if constexpr (CPLX) {
+                    const C v = rowp[j];
+                    sr = fma(wy[j], v.x, sr);
+                    si = fma(wy[j], v.y, si);
+                } else {
+                    sr = fma(wy[j], rowp[j], sr);
+                }
+            }
+            ar = fma(wx[i], sr, ar);
+            if constexpr (CPLX)
+                ai = fma(wx[i], si, ai);
+        }
+        const int32_t dst = perm[p];
+        out[dst] = ar;
+        if constexpr (CPLX)
+            out[g.npts + dst] = ai;
+    }
+}
+
+template <typename T, int W, bool CPLX>
+__global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
+    const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
+    const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
+    T *__restrict__ grid)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *patch = reinterpret_cast<T *>(smem_raw);  // interleaved (re, im) when CPLX
+    constexpr int NC = CPLX ? 2 : 1;
+    const int4 ck = chunks[blockIdx.x];
+    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    for (int idx = threadIdx.x; idx < PR * PC * NC; idx += NUFFT_THREADS)
+        patch[idx] = (T)0;
+    __syncthreads();
+    for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
+        T wx[W], wy[W];
+        int lr, lc;
+        point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
+        if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
+            continue;  // cannot happen for points sorted by the same arithmetic
+        const int32_t src = perm[p];
+        const T yr = in[src];
+        const T yi = CPLX ? in[g.npts + src] : (T)0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const T fr = wx[i] * yr, fi = wx[i] * yi;
+            T *rowp = patch + ((lr + i) * PC + lc) * NC;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                atomicAdd(rowp + NC * j, fr * wy[j]);
+                if constexpr (CPLX)
+                    atomicAdd(rowp + NC * j + 1, fi * wy[j]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
+        const int pr = idx / PC, pc = idx - (idx / PC) * PC;
+        const int r = row0 + pr;
+        if (r >= g.nrows)
+            continue;
+        int c = col0 + pc;
+        if (c >= g.n2)
+            c -= g.n2;
+        T *dst = grid + ((size_t)r * g.stride + c) * NC;
+        const T vr = patch[idx * NC];
+        if (vr != (T)0)
+            unsafeAtomicAdd(dst, vr);
+        if constexpr (CPLX) {
+            const T vi = patch[idx * NC + 1];
+            if (vi != (T)0)
+                unsafeAtomicAdd(dst + 1, vi);
+        }
+    }
+}
+
+static GridGeom make_geom(const gsht_plan &p)
+{
+    GridGeom g;
+    g.c1 = (double)p.n1 / (2.0 * 3.141592653589793);
+    g.c2 = (double)p.n2 / (2.0 * 3.141592653589793);
+    g.half = 0.5 * (double)p.w;
+    g.a_min = p.a_min;
+    g.n2 = p.n2;
+    g.stride = p.n2;  // complex grid: n2 complex per row; real grid: n2 reals per row
+    g.nrows = p.nrows;
+    g.t1 = p.t1;
+    g.t2 = p.t2;
+    g.nt2 = p.nt2;
+    g.npts = p.npts;
+    return g;
+}
+
+template <typename T, int W>
+static hipError_t interp_w(const gsht_plan &p, void *map, hipStream_t s)
+{
+    const GridGeom g = make_geom(p);
+    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    if (p.spin) {
+        const size_t sm = (size_t)PR * PC * sizeof(typename cpl<T>::type);
+        hipLaunchKernelGGL((interp_kernel<T, W, true>), dim3((unsigned)p.nchunks),
+                           dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm, p.G, g,
+                           (T)p.beta, (T *)map);
+    } else {
+        const size_t sm = (size_t)PR * PC * sizeof(T);
+        hipLaunchKernelGGL((interp_kernel<T, W, false>), dim3((unsigned)p.nchunks),
+                           dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm, p.g, g,
+                           (T)p.beta, (T *)map);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int W>
+static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
+{
+    const GridGeom g = make_geom(p);
+    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    if (p.spin) {
+        const size_t sm = (size_t)PR * PC * 2 * sizeof(T);
+        hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),
+                           dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
+                           (const T *)map, g, (T)p.beta, (T *)p.G);
+    } else {
+        const size_t sm = (size_t)PR * PC * sizeof(T);
+        hipLaunchKernelGGL((spread_kernel<T, W, false>), dim3((unsigned)p.nchunks),
+                           dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
+                           (const T *)map, g, (T)p.beta, (T *)p.g);
+    }
+    return hipGetLastError();
+}
+
+#define GSHT_W_CASES(F, T)                                                                       \
+    switch (p.w) {                                                                               \
+    case 4: return F<T, 4>(p, map, s);                                                           \
+    case 5: return F<T, 5>(p, map, s);                                                           \
+    case 6: return F<T, 6>(p, map, s);                                                           \
+    case 7: return F<T, 7>(p, map, s);                                                           \
+    case 8: return F<T, 8>(p, map, s);                                                           \
+    case 9: return F<T, 9>(p, map, s);                                                           \
+    case 10: return F<T, 10>(p, map, s);                                                         \
+    case 11: return F<T, 11>(p, map, s);                                                         \
+    case 12: return F<T, 12>(p, map, s);                                                         \
+    case 13: return F<T, 13>(p, map, s);                                                         \
+    case 14: return F<T, 14>(p, map, s);                                                         \
+    case 15: return F<T, 15>(p, map, s);                                                         \
+    case 16: return F<T, 16>(p, map, s);                                                         \
+    default: return hipErrorInvalidValue;                                                        \
+    }
+
+#define GSHT_W_CASES_F32(F)                                                                      \
+    switch (p.w) {                                                                               \
+    case 4: return F<float, 4>(p, map, s);                                                       \
+    case 5: return F<float, 5>(p, map, s);                                                       \
+    case 6: return F<float, 6>(p, map, s);                                                       \
+    case 7: return F<float, 7>(p, map, s);                                                       \
+    case 8: return F<float, 8>(p, map, s);                                                       \
+    default: return hipErrorInvalidValue;                                                        \
+    }
+
+hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s)
+{
+    if (p.nchunks == 0)
+        return hipSuccess;
+    if (p.prec == GSHT_F64) {
+        GSHT_W_CASES(interp_w, double)
+    } else {
+        GSHT_W_CASES_F32(interp_w)
+    }
+}
+
+hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s)
+{
+    if (p.nchunks == 0)
+        return hipSuccess;
+    if (p.prec == GSHT_F64) {
+        GSHT_W_CASES(spread_w, double)
+    } else {
+        GSHT_W_CASES_F32(spread_w)
+    }
+}
+
+}  // namespace gsht

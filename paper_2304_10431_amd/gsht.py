@@ -1,0 +1,244 @@
+"""Python binding of ``libgsht.so`` (ctypes).  Argument marshalling only.
+
+Every function takes torch tensors that live on the current HIP device and
+passes their device pointers and torch's current stream to the C ABI declared
+in ``include/gsht.h``; all arithmetic runs in the library's HIP kernels.  If the
+library is missing or cannot be loaded, importing this module raises.
+
+Layouts (see the header): a_lm [ncomp][nalm] complex (m-major triangular),
+maps [ncomp][npts] real, theta/phi float64.  Precision "f64" -> complex128 /
+float64, "f32" -> complex64 / float32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsht.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libgsht.so not found at %s; build it with "
+                      "`python -m paper_2304_10431_amd.build`" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+GSHT_OK, GSHT_EINVAL, GSHT_ENOMEM, GSHT_EHIP, GSHT_EUNSUPPORTED = 0, -1, -2, -3, -4
+F64, F32 = 0, 1
+_PREC = {"f64": F64, "f32": F32, F64: F64, F32: F32}
+_CDT = {F64: torch.complex128, F32: torch.complex64}
+_RDT = {F64: torch.float64, F32: torch.float32}
+
+
+class GshtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("gsht status %d: %s" % (code, msg))
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("spin", ctypes.c_int),
+                ("ncomp", ctypes.c_int), ("npts", ctypes.c_int64), ("epsilon", ctypes.c_double),
+                ("precision", ctypes.c_int), ("ntheta", ctypes.c_int), ("ndouble", ctypes.c_int),
+                ("n1", ctypes.c_int), ("n2", ctypes.c_int), ("w", ctypes.c_int),
+                ("beta", ctypes.c_double), ("nrows", ctypes.c_int), ("a_min", ctypes.c_int),
+                ("tile1", ctypes.c_int), ("tile2", ctypes.c_int), ("ntile1", ctypes.c_int),
+                ("ntile2", ctypes.c_int), ("nchunks", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp, _i, _i64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "gsht_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
+    "gsht_adjoint_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
+    "gsht_plan_create": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
+    "gsht_plan_synth": [_vp, _vp, _vp, _vp],
+    "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
+    "gsht_plan_get_info": [_vp, ctypes.POINTER(PlanInfo)],
+    "gsht_plan_get_sort": [_vp, _vp, _vp, _vp],
+    "gsht_plan_set_profiling": [_vp, _i],
+    "gsht_plan_get_stage_times": [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i],
+    "gsht_legendre_rings": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
+    "gsht_legendre_rings_adjoint": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
+    "gsht_num_stages": [],
+    "gsht_stage_name": [_i],
+    "gsht_last_error": [],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.gsht_last_error.restype = ctypes.c_char_p
+_lib.gsht_stage_name.restype = ctypes.c_char_p
+_lib.gsht_plan_destroy.argtypes = [_vp]
+_lib.gsht_plan_destroy.restype = None
+
+EXPORTED = list(_SIGS) + ["gsht_plan_destroy"]
+
+
+def _check(rc: int):
+    if rc != GSHT_OK:
+        raise GshtError(rc, _lib.gsht_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def nalm(lmax: int, mmax: int) -> int:
+    return (mmax + 1) * (lmax + 1) - mmax * (mmax + 1) // 2
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be on a HIP device" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def _coords(theta, phi):
+    _need(theta, torch.float64, None, "theta")
+    _need(phi, torch.float64, tuple(theta.shape), "phi")
+    return theta.numel()
+
+
+def synth_general(alm, theta, phi, lmax: int, mmax: int, spin: int, epsilon: float,
+                  precision="f64", out=None):
+    """One-shot gsht_synth_general; returns the map [ncomp][npts]."""
+    prec = _PREC[precision]
+    ncomp = 1 if spin == 0 else 2
+    npts = _coords(theta, phi)
+    _need(alm, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    if out is None:
+        out = torch.empty((ncomp, npts), dtype=_RDT[prec], device=alm.device)
+    _need(out, _RDT[prec], (ncomp, npts), "out")
+    _check(_lib.gsht_synth_general(_ptr(alm), lmax, mmax, spin, _ptr(theta), _ptr(phi), npts,
+                                   float(epsilon), prec, _ptr(out), _stream()))
+    return out
+
+
+def adjoint_synth_general(maps, theta, phi, lmax: int, mmax: int, spin: int, epsilon: float,
+                          precision="f64", out=None):
+    """One-shot gsht_adjoint_synth_general; returns a_lm [ncomp][nalm]."""
+    prec = _PREC[precision]
+    ncomp = 1 if spin == 0 else 2
+    npts = _coords(theta, phi)
+    _need(maps, _RDT[prec], (ncomp, npts), "map")
+    if out is None:
+        out = torch.empty((ncomp, nalm(lmax, mmax)), dtype=_CDT[prec], device=maps.device)
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "out")
+    _check(_lib.gsht_adjoint_synth_general(_ptr(maps), lmax, mmax, spin, _ptr(theta), _ptr(phi),
+                                           npts, float(epsilon), prec, _ptr(out), _stream()))
+    return out
+
+
+class Plan:
+    """gsht_plan wrapper: geometry, FFT plans and workspace reused across calls."""
+
+    def __init__(self, theta, phi, lmax: int, mmax: int, spin: int, epsilon: float,
+                 precision="f64"):
+        self.prec = _PREC[precision]
+        self.lmax, self.mmax, self.spin = lmax, mmax, spin
+        self.ncomp = 1 if spin == 0 else 2
+        self.npts = _coords(theta, phi)
+        self.device = theta.device
+        h = ctypes.c_void_p(0)
+        _check(_lib.gsht_plan_create(ctypes.byref(h), lmax, mmax, spin, _ptr(theta), _ptr(phi),
+                                     self.npts, float(epsilon), self.prec, _stream()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gsht_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(_lib.gsht_plan_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def synth(self, alm, out=None):
+        _need(alm, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "alm")
+        if out is None:
+            out = torch.empty((self.ncomp, self.npts), dtype=_RDT[self.prec], device=self.device)
+        _need(out, _RDT[self.prec], (self.ncomp, self.npts), "out")
+        _check(_lib.gsht_plan_synth(self._h, _ptr(alm), _ptr(out), _stream()))
+        return out
+
+    def adjoint(self, maps, out=None):
+        _need(maps, _RDT[self.prec], (self.ncomp, self.npts), "map")
+        if out is None:
+            out = torch.empty((self.ncomp, nalm(self.lmax, self.mmax)), dtype=_CDT[self.prec],
+                              device=self.device)
+        _need(out, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "out")
+        _check(_lib.gsht_plan_adjoint(self._h, _ptr(maps), _ptr(out), _stream()))
+        return out
+
+    def sort(self):
+        inf = self.info()
+        perm = torch.empty(max(self.npts, 1), dtype=torch.int32, device=self.device)
+        start = torch.empty(inf["ntile1"] * inf["ntile2"] + 1, dtype=torch.int32, device=self.device)
+        _check(_lib.gsht_plan_get_sort(self._h, _ptr(perm), _ptr(start), _stream()))
+        return perm[:self.npts], start
+
+    def set_profiling(self, on: bool):
+        _check(_lib.gsht_plan_set_profiling(self._h, 1 if on else 0))
+
+    def stage_times(self) -> dict:
+        n = _lib.gsht_num_stages()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(_lib.gsht_plan_get_stage_times(self._h, ms, cnt, n))
+        return {_lib.gsht_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
+
+
+def legendre_rings(alm, lmax: int, mmax: int, spin: int, ntheta: int, precision="f64", out=None):
+    """Stage entry point gsht_legendre_rings; returns F [ncol][2 ntheta - 2] complex."""
+    prec = _PREC[precision]
+    ncomp = 1 if spin == 0 else 2
+    ncol = mmax + 1 if spin == 0 else 2 * mmax + 1
+    _need(alm, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    if out is None:
+        out = torch.empty((ncol, 2 * ntheta - 2), dtype=_CDT[prec], device=alm.device)
+    _need(out, _CDT[prec], (ncol, 2 * ntheta - 2), "F")
+    _check(_lib.gsht_legendre_rings(_ptr(alm), lmax, mmax, spin, ntheta, prec, _ptr(out), _stream()))
+    return out
+
+
+def legendre_rings_adjoint(F, lmax: int, mmax: int, spin: int, ntheta: int, precision="f64",
+                           out=None):
+    """Stage entry point gsht_legendre_rings_adjoint; returns a_lm [ncomp][nalm]."""
+    prec = _PREC[precision]
+    ncomp = 1 if spin == 0 else 2
+    ncol = mmax + 1 if spin == 0 else 2 * mmax + 1
+    _need(F, _CDT[prec], (ncol, 2 * ntheta - 2), "F")
+    if out is None:
+        out = torch.empty((ncomp, nalm(lmax, mmax)), dtype=_CDT[prec], device=F.device)
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    _check(_lib.gsht_legendre_rings_adjoint(_ptr(F), lmax, mmax, spin, ntheta, prec, _ptr(out),
+                                            _stream()))
+    return out
+
+
+def last_error() -> str:
+    return _lib.gsht_last_error().decode()

@@ -1,0 +1,253 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+* Legendre stage (exact up to rounding): F[col][j] on the doubled meridian vs the
+  oracle's ring synthesis plus the doubling rule of Sect. 3; its adjoint vs the
+  oracle's ring adjoint after the undoubling rule.
+* Bin sort: bit-exact vs a stable argsort of the oracle's tile keys.
+* End to end: synthesis and adjoint within the requested epsilon (relative L2,
+  the effective accuracy of Sect. 4), both precisions, spins 0..3, ragged sizes,
+  poles, phi wrap-around, mmax < lmax, empty point sets.
+* Adjointness of the GPU pair in FP64.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2304_10431_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2304_10431_amd import gsht
+    return gsht
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def ring_thetas(ntheta):
+    return np.pi * np.arange(ntheta) / (ntheta - 1)
+
+
+def doubled_reference(alm, lmax, mmax, spin, ntheta):
+    th = ring_thetas(ntheta)
+    F = oracle.ring_synth(alm, lmax, mmax, spin, th)       # [2mmax+1][ntheta]
+    nd = 2 * ntheta - 2
+    ms = np.arange(-mmax, mmax + 1)
+    out = np.zeros((2 * mmax + 1, nd), complex)
+    out[:, :ntheta] = F
+    sign = (-1.0) ** ((spin + ms) % 2)
+    for j in range(1, ntheta - 1):
+        out[:, nd - j] = sign * F[:, j]                       # doubling rule (Sect. 3)
+    if spin == 0:
+        out = out[mmax:]                                       # columns m >= 0
+    return out
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) /
+                 max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
+
+
+LEG_CASES = [
+    # lmax, mmax, spin, ntheta
+    (0, 0, 0, 2),
+    (1, 1, 1, 3),
+    (7, 5, 0, 9),
+    (40, 40, 0, 42),
+    (40, 33, 2, 43),
+    (63, 63, 3, 65),
+    (130, 100, 2, 140),
+    (200, 200, 0, 203),
+    (300, 300, 2, 302),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("lmax,mmax,spin,ntheta", LEG_CASES)
+def test_legendre_stage_matches_oracle(G, lmax, mmax, spin, ntheta, prec):
+    say("legendre stage", lmax, mmax, spin, ntheta, prec)
+    rng = np.random.default_rng(lmax * 7 + spin)
+    a = wl.gaussian_alm(lmax, mmax, spin, rng, cl=np.ones(lmax + 1))
+    ref = doubled_reference(a, lmax, mmax, spin, ntheta)
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    F = G.legendre_rings(dev(a).to(cdt), lmax, mmax, spin, ntheta, prec).cpu().numpy()
+    tol = 1e-12 if prec == "f64" else 3e-7
+    assert rel_l2(F, ref) < tol, rel_l2(F, ref)
+
+
+@pytest.mark.parametrize("lmax,mmax,spin,ntheta", LEG_CASES)
+def test_legendre_adjoint_stage_matches_oracle(G, lmax, mmax, spin, ntheta):
+    say("legendre adjoint stage", lmax, mmax, spin, ntheta)
+    rng = np.random.default_rng(100 + lmax + spin)
+    nd = 2 * ntheta - 2
+    ncol = mmax + 1 if spin == 0 else 2 * mmax + 1
+    F = rng.standard_normal((ncol, nd)) + 1j * rng.standard_normal((ncol, nd))
+    # undoubling rule (Sect. 3): interior rings add the mirrored row with (-1)^(s+m)
+    ms = np.arange(0, mmax + 1) if spin == 0 else np.arange(-mmax, mmax + 1)
+    sign = (-1.0) ** ((spin + ms) % 2)
+    H = F[:, :ntheta].copy()
+    for j in range(1, ntheta - 1):
+        H[:, j] += sign * F[:, nd - j]
+    Hfull = np.zeros((2 * mmax + 1, ntheta), complex)
+    if spin == 0:
+        Hfull[mmax:] = H
+    else:
+        Hfull[:] = H
+    ref = oracle.ring_adjoint(Hfull, lmax, mmax, spin, ring_thetas(ntheta))
+    got = G.legendre_rings_adjoint(dev(F), lmax, mmax, spin, ntheta, "f64").cpu().numpy()
+    assert rel_l2(got, ref) < 1e-12, rel_l2(got, ref)
+    # l < spin entries and Im of m = 0 are exactly zero
+    if spin > 0:
+        for l in range(min(spin, lmax + 1)):
+            assert np.all(got[:, oracle.alm_index(l, 0, lmax)] == 0)
+    assert np.all(got[:, :lmax + 1].imag == 0)
+
+
+def make_case(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        return wl.uniform_sphere(n, rng)
+    if kind == "poles":
+        th, ph = wl.uniform_sphere(n, rng)
+        th[: n // 4] = 0.0
+        th[n // 4: n // 2] = np.pi
+        th[n // 2: 3 * n // 4] = rng.uniform(0, 1e-6, n // 4)
+        return th, ph
+    if kind == "wrap":
+        th, ph = wl.uniform_sphere(n, rng)
+        ph[: n // 3] = 2 * np.pi - rng.uniform(0, 1e-9, n // 3)
+        ph[n // 3: 2 * n // 3] = rng.uniform(-20.0, 20.0, n - n // 3 - (n - 2 * n // 3))
+        return th, ph
+    if kind == "gl":
+        nr = max(4, int(math.sqrt(n / 2)))
+        th, ph, _ = wl.gl_grid(nr, 2 * nr + 1)
+        return wl.deflect(th, ph, seed)
+    raise ValueError(kind)
+
+
+E2E = [
+    # lmax, mmax, spin, npts, kind, prec, eps
+    (127, 127, 0, 20000, "uniform", "f64", 1e-10),
+    (127, 127, 0, 20000, "uniform", "f32", 1e-5),
+    (64, 50, 2, 5000, "poles", "f64", 1e-10),
+    (64, 64, 2, 5000, "wrap", "f64", 1e-12),
+    (96, 96, 1, 7000, "gl", "f64", 1e-8),
+    (80, 80, 3, 4000, "uniform", "f32", 1e-5),
+    (33, 20, 2, 3001, "uniform", "f32", 1e-3),
+    (200, 150, 0, 9000, "gl", "f64", 1e-13),
+    (5, 5, 0, 1000, "uniform", "f64", 1e-10),
+    (2, 2, 2, 700, "poles", "f64", 1e-10),
+]
+
+
+@pytest.mark.parametrize("lmax,mmax,spin,npts,kind,prec,eps", E2E)
+def test_synthesis_within_epsilon(G, lmax, mmax, spin, npts, kind, prec, eps):
+    say("synth", lmax, mmax, spin, npts, kind, prec, eps)
+    th, ph = make_case(kind, npts, 7 + lmax)
+    rng = np.random.default_rng(3 + spin)
+    a = wl.gaussian_alm(lmax, mmax, spin, rng)
+    ref = oracle.synth(a, lmax, mmax, spin, th, ph)
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    got = G.synth_general(dev(a).to(cdt), dev(th), dev(ph), lmax, mmax, spin, eps, prec)
+    got = got.cpu().numpy().astype(np.float64)
+    err = oracle.eps_eff(got, ref)
+    say("  eps_eff", err)
+    assert err <= eps, err
+
+
+@pytest.mark.parametrize("lmax,mmax,spin,npts,kind,prec,eps", E2E)
+def test_adjoint_within_epsilon(G, lmax, mmax, spin, npts, kind, prec, eps):
+    say("adjoint", lmax, mmax, spin, npts, kind, prec, eps)
+    th, ph = make_case(kind, npts, 11 + lmax)
+    rng = np.random.default_rng(5 + spin)
+    y = rng.standard_normal((oracle.ncomp(spin), npts))
+    ref = oracle.adjoint(y, lmax, mmax, spin, th, ph)
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    got = G.adjoint_synth_general(dev(y).to(rdt), dev(th), dev(ph), lmax, mmax, spin, eps, prec)
+    got = got.cpu().numpy().astype(np.complex128)
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    err = oracle.eps_eff(got * w, ref * w)
+    say("  eps_eff", err)
+    assert err <= eps, err
+    assert np.all(got[:, :lmax + 1].imag == 0)
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_gpu_pair_is_adjoint(G, spin):
+    lmax, mmax, npts = 150, 140, 30000
+    rng = np.random.default_rng(50 + spin)
+    th, ph = wl.uniform_sphere(npts, rng)
+    x = wl.gaussian_alm(lmax, mmax, spin, rng, cl=np.ones(lmax + 1))
+    y = rng.standard_normal((oracle.ncomp(spin), npts))
+    plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, 1e-10, "f64")
+    ax = plan.synth(dev(x)).cpu().numpy()
+    ahy = plan.adjoint(dev(y)).cpu().numpy()
+    lhs = float(np.sum(y * ax))
+    rhs = oracle.alm_inner(x, ahy, lmax, mmax)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(ax), (lhs, rhs)
+
+
+@pytest.mark.parametrize("kind,npts", [("uniform", 50000), ("gl", 40000), ("poles", 3000),
+                                       ("wrap", 20001)])
+def test_binsort_bit_exact(G, kind, npts):
+    say("binsort", kind, npts)
+    th, ph = make_case(kind, npts, 99)
+    plan = G.Plan(dev(th), dev(ph), 127, 127, 2, 1e-5, "f32")
+    inf = plan.info()
+    perm, start = plan.sort()
+    keys = oracle.bin_keys(th, ph, inf["n1"], inf["n2"], inf["w"], inf["a_min"], inf["tile1"],
+                           inf["tile2"], inf["ntile2"])
+    ntiles = inf["ntile1"] * inf["ntile2"]
+    ref_perm, ref_start = oracle.binsort(keys, ntiles)
+    assert np.array_equal(perm.cpu().numpy(), ref_perm)
+    assert np.array_equal(start.cpu().numpy(), ref_start)
+
+
+def test_empty_point_set(G):
+    th = torch.zeros(0, dtype=torch.float64, device="cuda")
+    a = torch.zeros((2, oracle.nalm(16, 16)), dtype=torch.complex128, device="cuda")
+    m = G.synth_general(a, th, th.clone(), 16, 16, 2, 1e-10, "f64")
+    assert m.shape == (2, 0)
+    b = G.adjoint_synth_general(m, th, th.clone(), 16, 16, 2, 1e-10, "f64")
+    assert torch.all(b == 0)
+
+
+def test_invalid_theta_rejected(G):
+    th = torch.tensor([0.1, 3.5, 1.0], dtype=torch.float64, device="cuda")
+    ph = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(G.GshtError) as ei:
+        G.Plan(th, ph, 8, 8, 0, 1e-10, "f64")
+    assert ei.value.code == G.GSHT_EINVAL
+    ph2 = torch.tensor([0.0, float("nan"), 1.0], dtype=torch.float64, device="cuda")
+    th2 = torch.tensor([0.1, 0.2, 1.0], dtype=torch.float64, device="cuda")
+    with pytest.raises(G.GshtError):
+        G.Plan(th2, ph2, 8, 8, 0, 1e-10, "f64")
+
+
+def test_plan_reuse_and_repeatability(G):
+    """Same plan, several maps: results identical run to run (forward is atomic-free)."""
+    lmax, spin = 100, 2
+    rng = np.random.default_rng(1)
+    th, ph = wl.uniform_sphere(8000, rng)
+    plan = G.Plan(dev(th), dev(ph), lmax, lmax, spin, 1e-10, "f64")
+    for rep in range(3):
+        a = wl.gaussian_alm(lmax, lmax, spin, np.random.default_rng(rep))
+        m1 = plan.synth(dev(a))
+        m2 = plan.synth(dev(a))
+        assert torch.equal(m1, m2)
+        ref = oracle.synth(a, lmax, lmax, spin, th[:500], ph[:500])
+        assert oracle.eps_eff(m1[:, :500].cpu().numpy(), ref) < 1e-10
