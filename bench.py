@@ -1,0 +1,217 @@
+"""Benchmark: general spin-2 synthesis + adjoint at lmax 4096 on ~48M deflected points.
+
+One step = one synthesis (a_lm -> map) plus one adjoint (map -> a_lm) through the
+C ABI (plan API, geometry reused as in the paper's lensing use), with all inputs
+resident in HBM.  Forms timed:
+
+  * FP32 form, epsilon = 1e-5   (headline ``value``: seconds per step)
+  * FP64 form, epsilon = 1e-5   (for the FP32-vs-FP64 speed-up at equal accuracy)
+  * FP64 form, epsilon = 1e-10
+
+Workload: spin 2, lmax = mmax = 4096, Gaussian E/B a_lm, points of a 6144-ring
+longitude-thinned Gauss-Legendre grid displaced by a 2.5 arcmin rms deflection
+field (about 4.8e7 points; the "~5e7 pixel" intermediate grid of the paper's
+Sect. 4 benchmark).  Synthetic data, generated with fixed seeds.
+
+Also reported: the dominant kernel's achieved fraction of the MI355X FP64 vector
+peak (Legendre recurrence), per-stage times from HIP events inside the library,
+and the FP64 CPU oracle timed on a bounded sample of points on the host cores
+(with the GPU result's effective accuracy on that sample).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "synth+adjoint s @ lmax4096 spin2 ~50M pts: FP32 eps1e-5 vs FP64 eps1e-10; %roof"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def legendre_flops(lmax, mmax, spin, npairs):
+    """Algorithmic FP64 flops of one Legendre launch: per (l, m, ring pair) unit,
+    8 flop for spin 0 (2 FMA recurrence + 2 FMA accumulation) and 24 flop for
+    spin > 0 (2 recurrences + 4 complex-by-real accumulations), over
+    max(m, s) <= l <= lmax, 0 <= m <= mmax."""
+    units = 0
+    for m in range(mmax + 1):
+        l0 = max(m, spin)
+        if l0 <= lmax:
+            units += lmax - l0 + 1
+    per = 8 if spin == 0 else 24
+    return per * units * npairs
+
+
+def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup):
+    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    t0 = time.time()
+    plan = gsht.Plan(th, ph, lmax, mmax, spin, eps, prec)
+    torch.cuda.synchronize()
+    t_plan = time.time() - t0
+    a = alm.to(cdt)
+    m = plan.synth(a)
+    b = plan.adjoint(m)
+    for _ in range(warmup):
+        plan.synth(a, out=m)
+        plan.adjoint(m, out=b)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.synth(a, out=m)
+        plan.adjoint(m, out=b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stages = plan.stage_times()
+    plan.set_profiling(False)
+    info = plan.info()
+    return plan, m, dict(s_per_step=dt, plan_s=t_plan, stages=stages, info=info)
+
+
+def cpu_baseline(spec, th_h, ph_h, alm_h, m_gpu_h, nsample, eps):
+    """Oracle (FP64 direct sum, all host cores) on a bounded random sample of the
+    workload's points, scaled linearly to the full point count."""
+    import oracle
+    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(th_h.size, nsample, replace=False))
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.time()
+    ref = oracle.synth(alm_h, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
+    t_syn = time.time() - t0
+    y = np.random.default_rng(7).standard_normal((ref.shape[0], nsample))
+    t0 = time.time()
+    oracle.adjoint(y, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
+    t_adj = time.time() - t0
+    npts = th_h.size
+    per_step = (t_syn + t_adj) * npts / nsample
+    err = {k: oracle.eps_eff(v[:, idx], ref) for k, v in m_gpu_h.items()}
+    return dict(value=per_step, unit="s", cores=cores, kind="oracle",
+                sample="%d random points of the %d-point workload: synthesis %.1f s + adjoint "
+                       "%.1f s on %d threads, scaled linearly to all points" %
+                       (nsample, npts, t_syn, t_adj, cores)), err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="pollens_thin6144")
+    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
+              "(the multi-GPU sharding is described, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_10431_amd import gsht
+    from paper_2304_10431_amd import workloads as wl
+
+    spec = wl.WORKLOADS[args.workload]
+    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    t0 = time.time()
+    if spec["points"] == "thin":
+        th0, ph0 = wl.thinned_gl_grid(spec["nring"])
+    elif spec["points"] == "gl":
+        th0, ph0, _ = wl.gl_grid(spec["nring"], spec["nphi"])
+    else:
+        th0, ph0 = wl.uniform_sphere(spec["npts"], np.random.default_rng(wl.seed_for(spec["id"])))
+    th = torch.from_numpy(th0).cuda()
+    ph = torch.from_numpy(ph0).cuda()
+    del th0, ph0
+    if spec["points"] != "uniform":
+        th, ph = wl.deflect(th, ph, wl.seed_for(spec["id"]) + 500)
+    alm_h = wl.make_alm(spec)
+    alm = torch.from_numpy(alm_h).cuda()
+    torch.cuda.synchronize()
+    npts = th.numel()
+    log("inputs ready: %d points, %.1f s" % (npts, time.time() - t0))
+
+    forms = [("f32", 1e-5)]
+    if not args.no_f64:
+        forms += [("f64", 1e-5), ("f64", 1e-10)]
+    results = {}
+    maps = {}
+    for prec, eps in forms:
+        plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup)
+        key = "%s_eps%.0e" % (prec, eps)
+        results[key] = r
+        maps[key] = m.detach().to(torch.float64).cpu().numpy()
+        log("%s: %.2f ms/step (plan %.2f s)" % (key, 1e3 * r["s_per_step"], r["plan_s"]))
+        plan.close()
+        del plan, m
+        torch.cuda.empty_cache()
+
+    head = results["f32_eps1e-05"]
+    info = head["info"]
+    st = head["stages"]
+    leg_ms, leg_n = st["legendre_synth"]
+    leg_avg_s = leg_ms / max(leg_n, 1) / 1e3
+    flops = legendre_flops(lmax, mmax, spin, (info["ntheta"] + 1) // 2)
+    achieved = flops / leg_avg_s / 1e12
+    adj_ms, adj_n = st["legendre_adj"]
+    adj_avg_s = adj_ms / max(adj_n, 1) / 1e3
+
+    out = {
+        "metric": METRIC,
+        "value": head["s_per_step"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * head["s_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FFT/NUFFT), f64 Legendre",
+        "data": "synthetic",
+        "config": {"workload": "%s: spin %d, lmax=mmax=%d, %d points (6144-ring thinned "
+                               "Gauss-Legendre grid, 2.5 arcmin rms deflection), FP32 eps 1e-5"
+                               % (args.workload, spin, lmax, npts),
+                   "npts": npts, "lmax": lmax, "mmax": mmax, "spin": spin},
+        "forms": {k: {"s_per_step": v["s_per_step"], "plan_s": v["plan_s"],
+                      "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
+                      "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
+                  for k, v in results.items()},
+        "roofline": {"kernel": "legendre_synth", "bound": "alu",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "avg_launch_ms": leg_avg_s * 1e3,
+                     "legendre_adj_frac": flops / adj_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
+    }
+    if "f64_eps1e-05" in results:
+        out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / head["s_per_step"]
+    if "f64_eps1e-10" in results:
+        out["f64_eps1e-10_s"] = results["f64_eps1e-10"]["s_per_step"]
+    if not args.no_cpu:
+        th_h = th.cpu().numpy()
+        ph_h = ph.cpu().numpy()
+        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, maps, args.cpu_sample, 1e-5)
+        out["cpu_baseline"] = cb
+        out["eps_eff_on_sample"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,6 +173,7 @@ def test_synthesis_within_epsilon(G, lmax, mmax, spin, npts, kind, prec, eps):
 def test_adjoint_within_epsilon(G, lmax, mmax, spin, npts, kind, prec, eps):
     say("adjoint", lmax, mmax, spin, npts, kind, prec, eps)
     th, ph = make_case(kind, npts, 11 + lmax)
+    npts = th.size
     rng = np.random.default_rng(5 + spin)
     y = rng.standard_normal((oracle.ncomp(spin), npts))
     ref = oracle.adjoint(y, lmax, mmax, spin, th, ph)
