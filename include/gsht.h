@@ -37,7 +37,9 @@
  *     ignored by the synthesis and returned as exactly 0 by the adjoint.
  *   - Maps: real, [ncomp][npts]: T for spin 0, (Q, U) for spin > 0.
  *   - theta, phi: FP64 in every precision.  theta must lie in [0, pi]; phi may be
- *     any finite value (it is reduced modulo 2 pi).
+ *     any value with |phi| <= 2^20 (it is wrapped modulo 2 pi on the grid; the
+ *     kernel offsets carry an absolute error of about |phi| 2^-52, so accuracy
+ *     is as stated for |phi| of order 2 pi).  Other values give GSHT_EINVAL.
  *   - Precision GSHT_F64: a_lm complex128, maps float64, FFT/NUFFT in FP64,
  *     1e-13 <= epsilon <= 0.1.  GSHT_F32: a_lm complex64, maps float32, FFT and
  *     NUFFT in FP32 with FP64 point-to-grid offsets, 1e-5 <= epsilon <= 0.1.  The

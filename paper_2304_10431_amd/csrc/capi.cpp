@@ -78,6 +78,23 @@ long next_smooth_even(long n)
     return n;
 }
 
+// Oversampled torus length: the smallest 2^k, 3 * 2^k or 5 * 2^k (k >= 1) that is
+// at least 0.999 * target (an oversampling factor of 2 may thus become 1.998, which
+// changes the kernel error negligibly) and at least floor_n.  These lengths run as
+// one or two passes in rocFFT, unlike lengths with several factors of 7.
+long fft_size(double target, long floor_n)
+{
+    long best = 0;
+    for (long f : {2L, 3L, 5L}) {
+        long n = f;
+        while (n < 0.999 * target || n < floor_n || n % 2)
+            n *= 2;
+        if (best == 0 || n < best)
+            best = n;
+    }
+    return best;
+}
+
 // Relative L2 error of the 2-D type-2 NUFFT with this kernel at oversampling 2,
 // beta = 2.3 w, measured for w = 4..16 on random Fourier series.
 const double kEsError[17] = {0, 0, 0, 0, 7.8e-4, 8.8e-5, 9.7e-6, 1.2e-6, 1.5e-7,
@@ -235,8 +252,8 @@ void choose_sizes(gsht_plan *p)
     p->w = choose_w(p->eps, p->prec == GSHT_F64 ? 16 : 8);
     p->beta = 2.3 * p->w;
     const double sigma = 2.0;
-    p->n1 = (int)next_smooth_even(std::max<long>((long)ceil(sigma * (2 * p->lmax + 1)), 2 * p->w + 4));
-    p->n2 = (int)next_smooth_even(std::max<long>((long)ceil(sigma * (2 * p->mmax + 1)), 2 * p->w + 4));
+    p->n1 = (int)fft_size(sigma * (2 * p->lmax + 1), std::max(2 * p->w + 4, 2 * p->lmax + 2));
+    p->n2 = (int)fft_size(sigma * (2 * p->mmax + 1), std::max(2 * p->w + 4, 2 * p->mmax + 2));
     p->a_min = -(p->w / 2);
     p->nrows = p->n1 / 2 + p->w + 2;
     p->t1 = 32;
@@ -260,10 +277,15 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         return rc;
     if ((rc = dev_alloc(p, &p->acc, sizeof(double) * 2 * p->ncomp * (size_t)p->nalm)) != GSHT_OK)
         return rc;
+    p->leg_nchunk = (p->npairs + 64 * LEG_R - 1) / (64 * LEG_R);
+    if ((rc = dev_alloc(p, &p->leg.lfirst,
+                        sizeof(int32_t) * (size_t)(p->mmax + 1) * p->leg_nchunk)) != GSHT_OK)
+        return rc;
     std::vector<StartInfo> si = make_start_info(p->lmax, p->mmax, p->spin);
     HIP_TRY(hipMemcpyAsync(p->leg.start, si.data(), sizeof(StartInfo) * si.size(),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(launch_leg_tables(*p, s));
+    HIP_TRY(launch_leg_live(*p, s));
     if (with_deconv) {
         std::vector<double> k1 = deconv_table(p->lmax, p->n1, p->w, p->beta, 1.0 / p->nd);
         std::vector<double> k2 = deconv_table(p->mmax, p->n2, p->w, p->beta, 1.0);

@@ -31,7 +31,11 @@ struct LegendreTables {
     double2 *ab = nullptr;     // [nalm]  (a_l, b_l) at idx(l, m), valid for l0 <= l < lmax
     double *norm = nullptr;    // [nalm]  N_l
     StartInfo *start = nullptr;  // [mmax + 1]
+    int32_t *lfirst = nullptr;   // [(mmax + 1) * nchunk] first degree a chunk can matter at
 };
+
+// Ring pairs per lane of the Legendre kernels (R slices of 64 consecutive pairs).
+constexpr int LEG_R = 2;
 
 enum Stage {
     ST_PREP = 0,
@@ -76,6 +80,7 @@ struct gsht_plan {
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
     int64_t ntiles = 0, nchunks = 0;
     int ncol = 0, npairs = 0;
+    int leg_nchunk = 0;  // chunks of 64 * LEG_R ring pairs
     int64_t workspace_bytes = 0;
     // device tables
     gsht::LegendreTables leg;
@@ -110,6 +115,7 @@ namespace gsht {
 
 // ---- Legendre step (legendre.hip) ------------------------------------------
 hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s);
+hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s);
 hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, hipStream_t s);
 hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s);

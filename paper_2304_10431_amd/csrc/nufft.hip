@@ -27,6 +27,8 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int CHUNK = 512;
 constexpr int NUFFT_THREADS = 256;
+// Accepted |phi| (radians); beyond it the FP64 cell offsets would lose too much accuracy.
+constexpr double PHI_MAX = 1048576.0;
 
 // ---- keys ------------------------------------------------------------------------
 
@@ -35,10 +37,37 @@ struct KeyParams {
     int a_min, n2, t1, t2, nt2, nrows, w;
 };
 
-// Single-rounded products and differences (no FMA contraction), so that the keys
-// match a plain FP64 evaluation bit for bit.
-__device__ inline double mul_rn(double a, double b) { return __dmul_rn(a, b); }
-__device__ inline double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+// First kernel cell of a point.  u = theta c1 and v = phi c2 are single-rounded
+// products and u - w/2, v - w/2 single-rounded differences (contraction into an
+// FMA is switched off), so the cells match a plain FP64 evaluation bit for bit;
+// the column is reduced modulo n2 in exact integer arithmetic.  Used by both the
+// key computation and the interpolation/spreading kernels.
+struct Cell {
+    double u, v, a0, b0;  // a0, b0 integer valued
+    int r0, bi;           // kept-row offset (clamped) and column in [0, n2)
+};
+
+__device__ inline Cell point_cell(double th, double ph, double c1, double c2, double half,
+                                  int a_min, int n2, int nrows, int w)
+{
+#pragma clang fp contract(off)
+    Cell c;
+    c.u = th * c1;
+    c.v = ph * c2;
+    c.a0 = ceil(c.u - half);
+    c.b0 = ceil(c.v - half);
+    int64_t r0 = (int64_t)c.a0 - a_min;
+    r0 = r0 < 0 ? 0 : r0;
+    r0 = r0 > nrows - w ? nrows - w : r0;
+    c.r0 = (int)r0;
+    if (c.b0 >= 0.0 && c.b0 < (double)n2) {
+        c.bi = (int)c.b0;
+    } else {
+        int64_t b = (int64_t)c.b0 % n2;  // |b0| < 2^62 (|phi| is bounded on entry)
+        c.bi = (int)(b < 0 ? b + n2 : b);
+    }
+    return c;
+}
 
 __global__ void keys_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
                             int64_t npts, KeyParams kp, int32_t *__restrict__ keys,
@@ -49,27 +78,12 @@ __global__ void keys_kernel(const double *__restrict__ theta, const double *__re
         return;
     const double th = theta[i], ph = phi[i];
     int key = 0;
-    const bool ok = (th >= 0.0) && (th <= 3.141592653589793) && isfinite(ph);
+    const bool ok = (th >= 0.0) && (th <= 3.141592653589793) && (fabs(ph) <= PHI_MAX);
     if (!ok) {
         atomicAdd(n_invalid, 1ull);
     } else {
-        const double u = mul_rn(th, kp.c1);
-        const double v = mul_rn(ph, kp.c2);
-        const int64_t a0 = (int64_t)ceil(sub_rn(u, kp.half));
-        const double vb = ceil(sub_rn(v, kp.half));
-        int64_t r0 = a0 - kp.a_min;
-        if (r0 < 0)
-            r0 = 0;
-        if (r0 > kp.nrows - kp.w)
-            r0 = kp.nrows - kp.w;
-        // b0 mod n2 without overflowing for large |phi|
-        double bm = fmod(vb, (double)kp.n2);
-        if (bm < 0)
-            bm += kp.n2;
-        int bi = (int)bm;
-        if (bi >= kp.n2)
-            bi -= kp.n2;
-        key = (int)(r0 / kp.t1) * kp.nt2 + bi / kp.t2;
+        const Cell c = point_cell(th, ph, kp.c1, kp.c2, kp.half, kp.a_min, kp.n2, kp.nrows, kp.w);
+        key = (c.r0 / kp.t1) * kp.nt2 + c.bi / kp.t2;
     }
     keys[i] = key;
     vals[i] = (int32_t)i;
@@ -402,24 +416,10 @@ template <typename T, int W>
 __device__ inline void point_weights(double th, double ph, const GridGeom &g, int row0, int col0,
                                      T beta, int &lr, int &lc, T (&wx)[W], T (&wy)[W])
 {
-    const double u = __dmul_rn(th, g.c1);
-    const double v = __dmul_rn(ph, g.c2);
-    const double a0 = ceil(__dsub_rn(u, g.half));
-    const double b0 = ceil(__dsub_rn(v, g.half));
-    const double dx = u - a0, dy = v - b0;  // in (w/2 - 1, w/2]
-    double bm = fmod(b0, (double)g.n2);
-    if (bm < 0)
-        bm += g.n2;
-    int bi = (int)bm;
-    if (bi >= g.n2)
-        bi -= g.n2;
-    int r0 = (int)a0 - g.a_min;
-    if (r0 < 0)
-        r0 = 0;
-    if (r0 > g.nrows - W)
-        r0 = g.nrows - W;
-    lr = r0 - row0;
-    lc = bi - col0;
+    const Cell c = point_cell(th, ph, g.c1, g.c2, g.half, g.a_min, g.n2, g.nrows, W);
+    const double dx = c.u - c.a0, dy = c.v - c.b0;  // in (w/2 - 1, w/2]
+    lr = c.r0 - row0;
+    lc = c.bi - col0;
     const T sc = (T)(2.0 / W);
     const T fx = (T)dx, fy = (T)dy;
 #pragma unroll
@@ -504,7 +504,13 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
     for (int idx = threadIdx.x; idx < PR * PC * NC; idx += NUFFT_THREADS)
         patch[idx] = (T)0;
     __syncthreads();
-    for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
+    // Neighbouring sorted points have overlapping windows; visiting the chunk with a
+    // stride coprime to its length keeps the lanes of a wave on distant points, so
+    // that the LDS atomics of one instruction rarely hit the same cell.
+    const int n = ck.z - ck.y;
+    const int stride = (n % 97 == 0) ? 89 : 97;
+    for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
+        const int p = ck.y + (int)(((int64_t)k * stride) % n);
         T wx[W], wy[W];
         int lr, lc;
         point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
