@@ -277,9 +277,28 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         return rc;
     if ((rc = dev_alloc(p, &p->acc, sizeof(double) * 2 * p->ncomp * (size_t)p->nalm)) != GSHT_OK)
         return rc;
-    p->leg_nchunk = (p->npairs + 64 * LEG_R - 1) / (64 * LEG_R);
-    if ((rc = dev_alloc(p, &p->leg.lfirst,
-                        sizeof(int32_t) * (size_t)(p->mmax + 1) * p->leg_nchunk)) != GSHT_OK)
+    // Launch shapes of the Legendre kernels; GSHT_SYN_R, GSHT_ADJ_R and GSHT_ADJ_B
+    // override the defaults for tuning (synthesis R in {1, 2, 4}; adjoint (R, B) in
+    // {(1,8), (2,8), (2,4), (4,4)}).
+    {
+        const char *sr = getenv("GSHT_SYN_R"), *ar = getenv("GSHT_ADJ_R"), *ab = getenv("GSHT_ADJ_B");
+        const int r1 = sr ? atoi(sr) : p->syn_r;
+        const int r2 = ar ? atoi(ar) : p->adj_r, b = ab ? atoi(ab) : p->adj_b;
+        const int key = 100 * r2 + b;
+        if ((r1 != 1 && r1 != 2 && r1 != 4) || (key != 108 && key != 208 && key != 204 && key != 404))
+            return fail(GSHT_EINVAL, "unsupported Legendre launch shape syn_r=%d adj_r=%d adj_b=%d",
+                        r1, r2, b);
+        p->syn_r = r1;
+        p->adj_r = r2;
+        p->adj_b = b;
+    }
+    p->syn_nchunk = (p->npairs + 64 * p->syn_r - 1) / (64 * p->syn_r);
+    p->adj_nchunk = (p->npairs + 64 * p->adj_r - 1) / (64 * p->adj_r);
+    if ((rc = dev_alloc(p, &p->leg.lfirst_syn,
+                        sizeof(int32_t) * (size_t)(p->mmax + 1) * p->syn_nchunk)) != GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &p->leg.lfirst_adj,
+                        sizeof(int32_t) * (size_t)(p->mmax + 1) * p->adj_nchunk)) != GSHT_OK)
         return rc;
     std::vector<StartInfo> si = make_start_info(p->lmax, p->mmax, p->spin);
     HIP_TRY(hipMemcpyAsync(p->leg.start, si.data(), sizeof(StartInfo) * si.size(),

@@ -31,11 +31,9 @@ struct LegendreTables {
     double2 *ab = nullptr;     // [nalm]  (a_l, b_l) at idx(l, m), valid for l0 <= l < lmax
     double *norm = nullptr;    // [nalm]  N_l
     StartInfo *start = nullptr;  // [mmax + 1]
-    int32_t *lfirst = nullptr;   // [(mmax + 1) * nchunk] first degree a chunk can matter at
+    int32_t *lfirst_syn = nullptr;  // [(mmax + 1) * syn_nchunk] first degree a chunk can matter at
+    int32_t *lfirst_adj = nullptr;  // [(mmax + 1) * adj_nchunk] same for the adjoint's chunks
 };
-
-// Ring pairs per lane of the Legendre kernels (R slices of 64 consecutive pairs).
-constexpr int LEG_R = 2;
 
 enum Stage {
     ST_PREP = 0,
@@ -80,7 +78,11 @@ struct gsht_plan {
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
     int64_t ntiles = 0, nchunks = 0;
     int ncol = 0, npairs = 0;
-    int leg_nchunk = 0;  // chunks of 64 * LEG_R ring pairs
+    int syn_r = 1;       // ring pairs per lane, Legendre synthesis (slices of 64)
+    int adj_r = 2;       // ring pairs per lane, Legendre adjoint
+    int adj_b = 8;       // degrees per reduction block of the adjoint
+    int syn_nchunk = 0;  // chunks of 64 * syn_r ring pairs
+    int adj_nchunk = 0;  // chunks of 64 * adj_r ring pairs
     int64_t workspace_bytes = 0;
     // device tables
     gsht::LegendreTables leg;

@@ -1,0 +1,711 @@
+// Legendre recurrence kernels of the general SHT on gfx950: the "synthesis" and
+// "doubling" steps of Sect. 3 and their adjoints ("undoubling" and "adjoint
+// synthesis"), FP64 throughout.
+//
+// For each m and each ring pair (theta_q, pi - theta_q) of the equidistant grid
+// theta_q = pi q / (ntheta - 1), one lane runs the three-term recurrence in l of
+// the spin-weighted harmonic, normalised as p_l = sY_lm / N_l so that
+//     p_{l+1} = (a_l cos(theta) + sigma b_l) p_l - p_{l-1},
+// for both channels sigma = +s (a) and sigma = -s (b).  The south ring reuses the
+// north recurrence through sY_lm(pi - theta) = (-1)^(l+m) (-s)Y_lm(theta), and the
+// column -m of a spin-s field through sY_{l,-m} = (-1)^(s+m) (-s)Y_lm.
+//
+// Start values at l0 = max(m, s) can lie far below the double range: each channel
+// carries an exponent offset (a non-positive multiple of 512) and is accumulated
+// only once that offset is 0; anything smaller than 2^-204 relative is dropped.
+//
+// Work decomposition: one wave per (m, chunk); a chunk is R slices of 64
+// consecutive ring pairs, lane L of slice r owning pair 64 (R chunk + r) + L.
+// Degrees advance in blocks of 8.  A block runs "masked" (per-lane in-range
+// masks, rescaling, phase update at its end) until every slice of the wave is in
+// range; from then on blocks run without masks or checks.  Chunks whose most
+// equatorial ring stays below 2^-900 up to lmax are skipped outright.
+#include "gsht_internal.hpp"
+
+namespace gsht {
+
+template <typename T> struct cplxk;
+template <> struct cplxk<float> { using type = float2; };
+template <> struct cplxk<double> { using type = double2; };
+
+// ---- start values -----------------------------------------------------------------
+
+struct XD {
+    double m;
+    int e;
+};
+
+__device__ inline void xnorm(XD &x)
+{
+    int k;
+    x.m = frexp(x.m, &k);
+    x.e += k;
+}
+
+// base^n (base >= 0, n >= 0) with a separate binary exponent; 0^0 = 1.
+__device__ inline XD xpow(double base, int n)
+{
+    XD r{1.0, 0};
+    if (n == 0)
+        return r;
+    if (base == 0.0)
+        return XD{0.0, 0};
+    XD b{base, 0};
+    xnorm(b);
+    while (n) {
+        if (n & 1) {
+            r.m *= b.m;
+            r.e += b.e;
+            xnorm(r);
+        }
+        b.m *= b.m;
+        b.e *= 2;
+        xnorm(b);
+        n >>= 1;
+    }
+    return r;
+}
+
+// One channel's value at l0: mant 2^ex0 sin(theta/2)^a cos(theta/2)^b.
+__device__ inline XD start_value(double mant, int ex0, int a, int b, double sh, double ch)
+{
+    XD v{mant, ex0};
+    const XD ps = xpow(sh, a), pc = xpow(ch, b);
+    v.m *= ps.m;
+    v.e += ps.e;
+    xnorm(v);
+    v.m *= pc.m;
+    v.e += pc.e;
+    xnorm(v);
+    return v;
+}
+
+constexpr double TWO_P256 = 0x1p256;
+constexpr double TWO_M512 = 0x1p-512;
+
+// true value = p 2^ex, ex a non-positive multiple of 512, ex == 0 <=> in range.
+__device__ inline void to_scaled(const XD &v, double &p, int &ex)
+{
+    if (v.m == 0.0) {
+        p = 0.0;
+        ex = 0;
+    } else if (v.e >= -256) {
+        p = ldexp(v.m, v.e);
+        ex = 0;
+    } else {
+        const int t = v.e + 256;              // < 0
+        ex = 512 * (-((-t + 511) / 512));     // 512 floor(t / 512)
+        p = ldexp(v.m, v.e - ex);
+    }
+}
+
+__device__ inline void ring_geom(int q, int ntheta, double &x, double &sh, double &ch)
+{
+    const double t = (double)q / (double)(ntheta - 1);
+    x = cospi(t);
+    sh = sinpi(0.5 * t);
+    ch = cospi(0.5 * t);
+}
+
+// ---- live-chunk table -------------------------------------------------------------
+
+// For each (m, chunk): the first degree at which the chunk's most equatorial ring
+// reaches 2^-900 in either channel (lmax + 1 if never).  The other rings of the
+// chunk are smaller there, so a chunk whose entry exceeds lmax has nothing above
+// the accumulation threshold and is skipped.
+template <bool SPIN>
+__global__ void leg_live_kernel(const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
+                                int lmax, int mmax, int ntheta, int npairs, int chunk_pairs,
+                                int nchunk, int32_t *__restrict__ lfirst)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)(mmax + 1) * nchunk)
+        return;
+    const int m = (int)(id / nchunk), c = (int)(id - (int64_t)(id / nchunk) * nchunk);
+    const StartInfo si = st[m];
+    const int l0 = si.l0;
+    if (l0 > lmax) {
+        lfirst[id] = lmax + 1;
+        return;
+    }
+    int q = c * chunk_pairs + chunk_pairs - 1;
+    if (q > npairs - 1)
+        q = npairs - 1;
+    double x, sh, ch;
+    ring_geom(q, ntheta, x, sh, ch);
+    const XD va = start_value(si.mant_p, si.ex_p, si.a_p, si.b_p, sh, ch);
+    const XD vb = SPIN ? start_value(si.mant_m, si.ex_m, si.a_m, si.b_m, sh, ch) : XD{0.0, 0};
+    double a0 = 0, a1 = va.m, b0 = 0, b1 = vb.m;
+    int ea = va.e, eb = vb.e;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    int res = lmax + 1;
+    for (int l = l0; l <= lmax; ++l) {
+        int k;
+        const bool ha = a1 != 0.0 && (frexp(a1, &k), k + ea >= -900);
+        const bool hb = SPIN && b1 != 0.0 && (frexp(b1, &k), k + eb >= -900);
+        if (ha || hb) {
+            res = l;
+            break;
+        }
+        if (l == lmax)
+            break;
+        const double2 cf = ab[base + l];
+        const double na = fma(fma(cf.x, x, cf.y), a1, -a0);
+        a0 = a1;
+        a1 = na;
+        if (fabs(a1) > 0x1p64 || (a1 != 0.0 && fabs(a1) < 0x1p-64)) {
+            frexp(a1, &k);
+            a0 = ldexp(a0, -k);
+            a1 = ldexp(a1, -k);
+            ea += k;
+        }
+        if (SPIN) {
+            const double nb = fma(fma(cf.x, x, -cf.y), b1, -b0);
+            b0 = b1;
+            b1 = nb;
+            if (fabs(b1) > 0x1p64 || (b1 != 0.0 && fabs(b1) < 0x1p-64)) {
+                frexp(b1, &k);
+                b0 = ldexp(b0, -k);
+                b1 = ldexp(b1, -k);
+                eb += k;
+            }
+        }
+    }
+    lfirst[id] = res;
+}
+
+static void live_launch(const gsht_plan &p, int r, int nchunk, int32_t *lfirst, hipStream_t s)
+{
+    const int64_t n = (int64_t)(p.mmax + 1) * nchunk;
+    dim3 blk(64), grd((unsigned)((n + 63) / 64));
+    if (p.spin)
+        hipLaunchKernelGGL(leg_live_kernel<true>, grd, blk, 0, s, p.leg.ab, p.leg.start, p.lmax,
+                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, lfirst);
+    else
+        hipLaunchKernelGGL(leg_live_kernel<false>, grd, blk, 0, s, p.leg.ab, p.leg.start, p.lmax,
+                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, lfirst);
+}
+
+hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s)
+{
+    live_launch(p, p.syn_r, p.syn_nchunk, p.leg.lfirst_syn, s);
+    live_launch(p, p.adj_r, p.adj_nchunk, p.leg.lfirst_adj, s);
+    return hipGetLastError();
+}
+
+// ---- per-ring recurrence state ------------------------------------------------------
+
+struct Ring {
+    double x;
+    double a0, a1, b0, b1;  // p_{l-1}, p_l of channels +s and -s
+    int ea, eb;             // exponent offsets
+};
+
+__device__ inline Ring ring_init(const StartInfo &si, int q, int ntheta, bool active, bool spin)
+{
+    Ring r;
+    double sh, ch;
+    ring_geom(active ? q : 0, ntheta, r.x, sh, ch);
+    r.a0 = r.b0 = 0.0;
+    to_scaled(start_value(si.mant_p, si.ex_p, si.a_p, si.b_p, sh, ch), r.a1, r.ea);
+    if (spin)
+        to_scaled(start_value(si.mant_m, si.ex_m, si.a_m, si.b_m, sh, ch), r.b1, r.eb);
+    else {
+        r.b1 = 0.0;
+        r.eb = 0;
+    }
+    if (!active) {
+        r.a1 = r.b1 = 0.0;
+        r.ea = r.eb = 0;
+    }
+    return r;
+}
+
+template <bool SPIN>
+__device__ inline void ring_advance(Ring &r, double a, double b)
+{
+    const double ta = fma(a, r.x, b);
+    const double na = fma(ta, r.a1, -r.a0);
+    r.a0 = r.a1;
+    r.a1 = na;
+    if (SPIN) {
+        const double tb = fma(a, r.x, -b);
+        const double nb = fma(tb, r.b1, -r.b0);
+        r.b0 = r.b1;
+        r.b1 = nb;
+    }
+}
+
+template <bool SPIN>
+__device__ inline void ring_rescale(Ring &r)
+{
+    if (r.ea < 0 && fabs(r.a1) >= TWO_P256) {
+        r.a0 *= TWO_M512;
+        r.a1 *= TWO_M512;
+        r.ea += 512;
+    }
+    if (SPIN && r.eb < 0 && fabs(r.b1) >= TWO_P256) {
+        r.b0 *= TWO_M512;
+        r.b1 *= TWO_M512;
+        r.eb += 512;
+    }
+}
+
+// Wave-uniform slice state: 0 = no lane in range, 1 = some, 2 = all.
+template <bool SPIN>
+__device__ inline int slice_phase(const Ring &r)
+{
+    const bool in = (r.ea == 0) && (!SPIN || r.eb == 0);
+    const bool some = (r.ea == 0 && r.a1 != 0.0) || (SPIN && r.eb == 0 && r.b1 != 0.0);
+    if (__all(in))
+        return 2;
+    return __any(some) ? 1 : 0;
+}
+
+__device__ inline double mask_a(const Ring &r) { return r.ea == 0 ? r.a1 : 0.0; }
+__device__ inline double mask_b(const Ring &r) { return r.eb == 0 ? r.b1 : 0.0; }
+
+// ---- synthesis -------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void store_c(typename cplxk<T>::type *p, double re, double im)
+{
+    typename cplxk<T>::type v;
+    v.x = (T)re;
+    v.y = (T)im;
+    *p = v;
+}
+
+// Ring value and, for interior rings, its doubled mirror with sign ms.
+template <typename T>
+__device__ inline void put_ring(typename cplxk<T>::type *col, int j, int ntheta, int nd, double ms,
+                                double re, double im)
+{
+    store_c<T>(col + j, re, im);
+    if (j > 0 && j < ntheta - 1)
+        store_c<T>(col + (nd - j), ms * re, ms * im);
+}
+
+// Accumulators of one ring pair: spin s -> N+ (0,1), S+ (2,3), N- (4,5), S- (6,7);
+// spin 0 -> N (0,1), S (2,3).  SG = (-1)^(l - l0).
+template <bool SPIN, int SG>
+__device__ inline void synth_acc(double (&c)[8], double va, double vb, const double *u)
+{
+    c[0] = fma(u[0], va, c[0]);
+    c[1] = fma(u[1], va, c[1]);
+    if (SPIN) {
+        c[2] = fma(SG * u[0], vb, c[2]);
+        c[3] = fma(SG * u[1], vb, c[3]);
+        c[4] = fma(u[2], vb, c[4]);
+        c[5] = fma(u[3], vb, c[5]);
+        c[6] = fma(SG * u[2], va, c[6]);
+        c[7] = fma(SG * u[3], va, c[7]);
+    } else {
+        c[2] = fma(SG * u[0], va, c[2]);
+        c[3] = fma(SG * u[1], va, c[3]);
+    }
+}
+
+constexpr int LB = 8;  // degrees per block
+
+template <typename T, bool SPIN, int R>
+__global__ __launch_bounds__(64) void leg_synth_kernel(
+    const double2 *__restrict__ ab, const double *__restrict__ u, const StartInfo *__restrict__ st,
+    const int32_t *__restrict__ lfirst, int lmax, int mmax, int s, int ntheta, int nd, int npairs,
+    int nchunk, typename cplxk<T>::type *__restrict__ D)
+{
+    constexpr int US = SPIN ? 4 : 2;
+    const int m = blockIdx.x / nchunk;
+    const int chunk = blockIdx.x - m * nchunk;
+    const int lane = threadIdx.x;
+    const StartInfo si = st[m];
+    const int l0 = si.l0;
+    const bool live = (l0 <= lmax) && (lfirst[blockIdx.x] <= lmax);
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+
+    Ring rg[R];
+    double c[R][8];
+    bool all_in = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = chunk * 64 * R + 64 * r + lane;
+        rg[r] = ring_init(si, q, ntheta, live && q < npairs, SPIN);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            c[r][k] = 0.0;
+        all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+    }
+    if (live) {
+        for (int lb = l0; lb <= lmax; lb += LB) {
+            const double2 *abl = ab + base + lb;
+            const double *ul = u + US * (base + lb);
+            if (all_in && lb + LB - 1 <= lmax) {
+                // every lane in range: no masks, no rescaling
+#pragma unroll
+                for (int b = 0; b < LB; b += 2) {
+                    const double2 c0 = abl[b], c1 = abl[b + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, ul + US * b);
+                        ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                        synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
+                        ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < LB; b += 2) {
+                    const int l = lb + b;
+                    if (l > lmax)
+                        break;
+                    const double2 c0 = abl[b];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        synth_acc<SPIN, 1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * b);
+                        ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                    }
+                    if (l + 1 > lmax)
+                        break;
+                    const double2 c1 = abl[b + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        synth_acc<SPIN, -1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * (b + 1));
+                        ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                    }
+                }
+                all_in = true;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    ring_rescale<SPIN>(rg[r]);
+                    all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+                }
+            }
+        }
+    }
+    // south values carry (-1)^(l+m) = (-1)^(l0+m) (-1)^(l-l0)
+    const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
+    const double ms = ((s + m) & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = chunk * 64 * R + 64 * r + lane;
+        if (q >= npairs)
+            continue;
+        const int jn = q, js = ntheta - 1 - q;
+        typename cplxk<T>::type *colp = D + (size_t)(SPIN ? m + mmax : m) * nd;
+        put_ring<T>(colp, jn, ntheta, nd, ms, c[r][0], c[r][1]);
+        if (js != jn)
+            put_ring<T>(colp, js, ntheta, nd, ms, sfix * c[r][2], sfix * c[r][3]);
+        if (SPIN && m > 0) {
+            typename cplxk<T>::type *colm = D + (size_t)(mmax - m) * nd;
+            put_ring<T>(colm, jn, ntheta, nd, ms, c[r][4], c[r][5]);
+            if (js != jn)
+                put_ring<T>(colm, js, ntheta, nd, ms, sfix * c[r][6], sfix * c[r][7]);
+        }
+    }
+}
+
+template <int R>
+static void synth_launch(const gsht_plan &p, void *Dout, hipStream_t s)
+{
+    dim3 blk(64), grd((unsigned)((p.mmax + 1) * p.syn_nchunk));
+#define GSHT_LEG_SYNTH(T, SP, C)                                                                 \
+    hipLaunchKernelGGL((leg_synth_kernel<T, SP, R>), grd, blk, 0, s, p.leg.ab, p.uprep,          \
+                       p.leg.start, p.leg.lfirst_syn, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,     \
+                       p.npairs, p.syn_nchunk, (C *)Dout)
+    if (p.prec == GSHT_F64) {
+        if (p.spin) GSHT_LEG_SYNTH(double, true, double2);
+        else GSHT_LEG_SYNTH(double, false, double2);
+    } else {
+        if (p.spin) GSHT_LEG_SYNTH(float, true, float2);
+        else GSHT_LEG_SYNTH(float, false, float2);
+    }
+#undef GSHT_LEG_SYNTH
+}
+
+hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s)
+{
+    switch (p.syn_r) {
+    case 1: synth_launch<1>(p, Dout, s); break;
+    case 2: synth_launch<2>(p, Dout, s); break;
+    case 4: synth_launch<4>(p, Dout, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---- adjoint -----------------------------------------------------------------------
+
+template <typename T>
+__device__ inline double2 ld_c(const typename cplxk<T>::type *p)
+{
+    const typename cplxk<T>::type v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+
+// Undoubled ring value H(j) from the doubled column.
+template <typename T>
+__device__ inline double2 ring_in(const typename cplxk<T>::type *col, int j, int ntheta, int nd,
+                                  double ms)
+{
+    double2 v = ld_c<T>(col + j);
+    if (j > 0 && j < ntheta - 1) {
+        const double2 w = ld_c<T>(col + (nd - j));
+        v.x += ms * w.x;
+        v.y += ms * w.y;
+    }
+    return v;
+}
+
+// Per-ring adjoint inputs.  Spin 0: e = F(N) + F(S'), o = F(N) - F(S') (even / odd
+// l - l0).  Spin s: F+(N), F+(S'), conj F-(N), conj F-(S'), S' = (-1)^(l0+m) S.
+struct RingIn {
+    double v[8];
+};
+
+// One ring's contribution to the per-degree sums cb[0..NC-1]:
+//   spin s: S+ += a F+(N) + SG b F+(S'),  S- += b cF-(N) + SG a cF-(S')
+//   spin 0: b_l += a (SG > 0 ? e : o)
+template <bool SPIN, int SG>
+__device__ inline void adj_acc(double *cb, const RingIn &in, double va, double vb)
+{
+    if (SPIN) {
+        cb[0] = fma(va, in.v[0], cb[0]);
+        cb[1] = fma(va, in.v[1], cb[1]);
+        cb[0] = fma(SG * vb, in.v[2], cb[0]);
+        cb[1] = fma(SG * vb, in.v[3], cb[1]);
+        cb[2] = fma(vb, in.v[4], cb[2]);
+        cb[3] = fma(vb, in.v[5], cb[3]);
+        cb[2] = fma(SG * va, in.v[6], cb[2]);
+        cb[3] = fma(SG * va, in.v[7], cb[3]);
+    } else {
+        cb[0] = fma(va, in.v[SG > 0 ? 0 : 2], cb[0]);
+        cb[1] = fma(va, in.v[SG > 0 ? 1 : 3], cb[1]);
+    }
+}
+
+// a' = [a(0..31), b(0..31)], b' = [a(32..63), b(32..63)] (v_permlane32_swap on both
+// halves of the doubles); returns a' + b': lanes 0..31 hold a summed over lanes L
+// and L + 32, lanes 32..63 hold b summed likewise.
+__device__ inline double swap_add32(double a, double b)
+{
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32),
+                                                     false, false);
+    const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return a2 + b2;
+}
+
+// Same with v_permlane16_swap (odd rows of a <-> even rows of b): rows 0 and 2 end
+// with a summed over rows (0,1) resp. (2,3), rows 1 and 3 with b likewise.
+__device__ inline double swap_add16(double a, double b)
+{
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32),
+                                                     false, false);
+    const double a2 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double b2 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return a2 + b2;
+}
+
+// One wave per (m, chunk).  Per block of B degrees the V = B NC per-lane sums are
+// reduced over the 64 lanes: two swap-add stages in registers leave V/4 values per
+// lane, each value spread over the 16 lanes of one row; these go through LDS
+// (rotated slots, conflict free) and are summed by V groups of 64/V lanes.  The
+// results are added to acc[idx][0..NC-1] with one coalesced FP64 atomic per
+// (degree, component).
+template <typename T, bool SPIN, int R, int B>
+__global__ __launch_bounds__(64) void leg_adjoint_kernel(
+    const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
+    const int32_t *__restrict__ lfirst, const typename cplxk<T>::type *__restrict__ D, int lmax,
+    int mmax, int s, int ntheta, int nd, int npairs, int nchunk, double *__restrict__ acc)
+{
+    constexpr int NC = SPIN ? 4 : 2;
+    constexpr int V = B * NC;
+    static_assert(64 % V == 0 && V >= 8, "block values must divide the wave");
+    __shared__ double red[V * 16];
+    const int m = blockIdx.x / nchunk;
+    const int chunk = blockIdx.x - m * nchunk;
+    const int lane = threadIdx.x;
+    const StartInfo si = st[m];
+    const int l0 = si.l0;
+    if (l0 > lmax || lfirst[blockIdx.x] > lmax)
+        return;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double ms = ((s + m) & 1) ? -1.0 : 1.0;
+    const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
+
+    Ring rg[R];
+    RingIn in[R];
+    int ph[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = chunk * 64 * R + 64 * r + lane;
+        const bool active = q < npairs;
+        rg[r] = ring_init(si, q, ntheta, active, SPIN);
+        ph[r] = slice_phase<SPIN>(rg[r]);
+        double2 fpn = make_double2(0, 0), fps = fpn, fmn = fpn, fms = fpn;
+        if (active) {
+            const int jn = q, js = ntheta - 1 - q;
+            const typename cplxk<T>::type *colp = D + (size_t)(SPIN ? m + mmax : m) * nd;
+            fpn = ring_in<T>(colp, jn, ntheta, nd, ms);
+            if (js != jn) {
+                fps = ring_in<T>(colp, js, ntheta, nd, ms);
+                fps.x *= sfix;
+                fps.y *= sfix;
+            }
+            if (SPIN) {
+                const typename cplxk<T>::type *colm = D + (size_t)(mmax - m) * nd;
+                fmn = ring_in<T>(colm, jn, ntheta, nd, ms);
+                if (js != jn) {
+                    fms = ring_in<T>(colm, js, ntheta, nd, ms);
+                    fms.x *= sfix;
+                    fms.y *= sfix;
+                }
+            }
+        }
+        if (SPIN) {
+            in[r].v[0] = fpn.x; in[r].v[1] = fpn.y;
+            in[r].v[2] = fps.x; in[r].v[3] = fps.y;
+            in[r].v[4] = fmn.x; in[r].v[5] = -fmn.y;
+            in[r].v[6] = fms.x; in[r].v[7] = -fms.y;
+        } else {
+            in[r].v[0] = fpn.x + fps.x; in[r].v[1] = fpn.y + fps.y;
+            in[r].v[2] = fpn.x - fps.x; in[r].v[3] = fpn.y - fps.y;
+            in[r].v[4] = in[r].v[5] = in[r].v[6] = in[r].v[7] = 0.0;
+        }
+    }
+    bool all_in = true, some_in = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        all_in = all_in && ph[r] == 2;
+        some_in = some_in || ph[r] != 0;
+    }
+
+    for (int lb = l0; lb <= lmax; lb += B) {
+        double cb[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            cb[k] = 0.0;
+        const double2 *abl = ab + base + lb;
+        const bool had_some = some_in;
+        if (all_in && lb + B - 1 <= lmax) {
+#pragma unroll
+            for (int b = 0; b < B; b += 2) {
+                const double2 c0 = abl[b], c1 = abl[b + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
+                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
+                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < B; b += 2) {
+                const int l = lb + b;
+                if (l > lmax)
+                    break;
+                const double2 c0 = abl[b];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    adj_acc<SPIN, 1>(cb + b * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                }
+                if (l + 1 > lmax)
+                    break;
+                const double2 c1 = abl[b + 1];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                }
+            }
+            all_in = true;
+            some_in = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ring_rescale<SPIN>(rg[r]);
+                const int p = slice_phase<SPIN>(rg[r]);
+                all_in = all_in && p == 2;
+                some_in = some_in || p != 0;
+            }
+        }
+        if (!had_some)
+            continue;  // every lane was below range for this whole block
+        // stage 1: lanes L, L + 32 -> V/2 values; value k + (L / 32) V/2 in slot k
+        double c1[V / 2];
+#pragma unroll
+        for (int k = 0; k < V / 2; ++k)
+            c1[k] = swap_add32(cb[k], cb[k + V / 2]);
+        // stage 2: rows (0,1), (2,3) -> V/4 values per lane; slot k of row g holds value
+        // k + (g & 1) V/4 + (g >> 1) V/2, partially summed over 4 lanes
+        double c2[V / 4];
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k)
+            c2[k] = swap_add16(c1[k], c1[k + V / 4]);
+        const int g = lane >> 4, li = lane & 15;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < V / 4; ++k) {
+            const int vv = k + (g & 1) * (V / 4) + (g >> 1) * (V / 2);
+            red[vv * 16 + ((li + vv) & 15)] = c2[k];
+        }
+        __syncthreads();
+        constexpr int H = 64 / V;       // lanes per value
+        constexpr int SPAN = 16 / H;    // row partials summed per lane
+        const int v = lane % V, h = lane / V;
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < SPAN; ++i)
+            sum += red[v * 16 + ((h * SPAN + i + v) & 15)];
+#pragma unroll
+        for (int d = V; d < 64; d <<= 1)
+            sum += __shfl_xor(sum, d, 64);
+        if (lane < V && lb + lane / NC <= lmax)
+            unsafeAtomicAdd(acc + (base + lb) * NC + lane, sum);
+    }
+}
+
+template <int R, int B>
+static void adj_launch(const gsht_plan &p, const void *Din, hipStream_t s)
+{
+    dim3 blk(64), grd((unsigned)((p.mmax + 1) * p.adj_nchunk));
+#define GSHT_LEG_ADJ(T, SP, C)                                                                   \
+    hipLaunchKernelGGL((leg_adjoint_kernel<T, SP, R, B>), grd, blk, 0, s, p.leg.ab, p.leg.start, \
+                       p.leg.lfirst_adj, (const C *)Din, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,  \
+                       p.npairs, p.adj_nchunk, p.acc)
+    if (p.prec == GSHT_F64) {
+        if (p.spin) GSHT_LEG_ADJ(double, true, double2);
+        else GSHT_LEG_ADJ(double, false, double2);
+    } else {
+        if (p.spin) GSHT_LEG_ADJ(float, true, float2);
+        else GSHT_LEG_ADJ(float, false, float2);
+    }
+#undef GSHT_LEG_ADJ
+}
+
+hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
+
+hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s)
+{
+    hipError_t e = launch_zero(p.acc, sizeof(double) * (size_t)p.nalm * 2 * p.ncomp, s);
+    if (e != hipSuccess)
+        return e;
+    const int key = p.adj_r * 100 + p.adj_b;
+    switch (key) {
+    case 108: adj_launch<1, 8>(p, Din, s); break;
+    case 208: adj_launch<2, 8>(p, Din, s); break;
+    case 204: adj_launch<2, 4>(p, Din, s); break;
+    case 404: adj_launch<4, 4>(p, Din, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gsht

@@ -494,15 +494,17 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
     const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
     T *__restrict__ grid)
 {
+    // The LDS patch accumulates in FP64 for both precisions: on gfx950 FP64 LDS
+    // atomic adds run several times faster than FP32 ones (and round less).
     extern __shared__ unsigned char smem_raw[];
-    T *patch = reinterpret_cast<T *>(smem_raw);  // interleaved (re, im) when CPLX
+    double *patch = reinterpret_cast<double *>(smem_raw);  // interleaved (re, im) when CPLX
     constexpr int NC = CPLX ? 2 : 1;
     const int4 ck = chunks[blockIdx.x];
     const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
     const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
     for (int idx = threadIdx.x; idx < PR * PC * NC; idx += NUFFT_THREADS)
-        patch[idx] = (T)0;
+        patch[idx] = 0.0;
     __syncthreads();
     // Neighbouring sorted points have overlapping windows; visiting the chunk with a
     // stride coprime to its length keeps the lanes of a wave on distant points, so
@@ -522,12 +524,12 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             const T fr = wx[i] * yr, fi = wx[i] * yi;
-            T *rowp = patch + ((lr + i) * PC + lc) * NC;
+            double *rowp = patch + ((lr + i) * PC + lc) * NC;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(rowp + NC * j, fr * wy[j]);
+                atomicAdd(rowp + NC * j, (double)(fr * wy[j]));
                 if constexpr (CPLX)
-                    atomicAdd(rowp + NC * j + 1, fi * wy[j]);
+                    atomicAdd(rowp + NC * j + 1, (double)(fi * wy[j]));
             }
         }
     }
@@ -541,11 +543,11 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
         if (c >= g.n2)
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
-        const T vr = patch[idx * NC];
+        const T vr = (T)patch[idx * NC];
         if (vr != (T)0)
             unsafeAtomicAdd(dst, vr);
         if constexpr (CPLX) {
-            const T vi = patch[idx * NC + 1];
+            const T vi = (T)patch[idx * NC + 1];
             if (vi != (T)0)
                 unsafeAtomicAdd(dst + 1, vi);
         }
@@ -594,12 +596,12 @@ static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
     const GridGeom g = make_geom(p);
     const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
     if (p.spin) {
-        const size_t sm = (size_t)PR * PC * 2 * sizeof(T);
+        const size_t sm = (size_t)PR * PC * 2 * sizeof(double);
         hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.G);
     } else {
-        const size_t sm = (size_t)PR * PC * sizeof(T);
+        const size_t sm = (size_t)PR * PC * sizeof(double);
         hipLaunchKernelGGL((spread_kernel<T, W, false>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.g);
