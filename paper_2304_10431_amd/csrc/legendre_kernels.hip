@@ -335,52 +335,60 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
             c[r][k] = 0.0;
         all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
     }
+    // Masked block: per-lane in-range masks, then rescaling and the slice phases.
+    auto masked_block = [&](int lb) {
+        const double2 *abl = ab + base + lb;
+        const double *ul = u + US * (base + lb);
+#pragma unroll
+        for (int b = 0; b < LB; b += 2) {
+            const int l = lb + b;
+            if (l > lmax)
+                break;
+            const double2 c0 = abl[b];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                synth_acc<SPIN, 1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * b);
+                ring_advance<SPIN>(rg[r], c0.x, c0.y);
+            }
+            if (l + 1 > lmax)
+                break;
+            const double2 c1 = abl[b + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                synth_acc<SPIN, -1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * (b + 1));
+                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+            }
+        }
+        all_in = true;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ring_rescale<SPIN>(rg[r]);
+            all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+        }
+    };
     if (live) {
-        for (int lb = l0; lb <= lmax; lb += LB) {
+        // Three sequential loops (no loop-carried value crosses a branch merge):
+        // masked blocks until every lane is in range, full unmasked blocks, masked tail.
+        int lb = l0;
+        for (; lb <= lmax && !all_in; lb += LB)
+            masked_block(lb);
+        for (; lb + LB - 1 <= lmax; lb += LB) {
             const double2 *abl = ab + base + lb;
             const double *ul = u + US * (base + lb);
-            if (all_in && lb + LB - 1 <= lmax) {
-                // every lane in range: no masks, no rescaling
 #pragma unroll
-                for (int b = 0; b < LB; b += 2) {
-                    const double2 c0 = abl[b], c1 = abl[b + 1];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, ul + US * b);
-                        ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                        synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
-                        ring_advance<SPIN>(rg[r], c1.x, c1.y);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int b = 0; b < LB; b += 2) {
-                    const int l = lb + b;
-                    if (l > lmax)
-                        break;
-                    const double2 c0 = abl[b];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        synth_acc<SPIN, 1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * b);
-                        ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                    }
-                    if (l + 1 > lmax)
-                        break;
-                    const double2 c1 = abl[b + 1];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        synth_acc<SPIN, -1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * (b + 1));
-                        ring_advance<SPIN>(rg[r], c1.x, c1.y);
-                    }
-                }
-                all_in = true;
+            for (int b = 0; b < LB; b += 2) {
+                const double2 c0 = abl[b], c1 = abl[b + 1];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    ring_rescale<SPIN>(rg[r]);
-                    all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+                    synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, ul + US * b);
+                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                    synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
+                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
                 }
             }
         }
+        if (lb <= lmax)
+            masked_block(lb);
     }
     // south values carry (-1)^(l+m) = (-1)^(l0+m) (-1)^(l-l0)
     const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
@@ -586,65 +594,15 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
         some_in = some_in || ph[r] != 0;
     }
 
-    for (int lb = l0; lb <= lmax; lb += B) {
-        double cb[V];
-#pragma unroll
-        for (int k = 0; k < V; ++k)
-            cb[k] = 0.0;
-        const double2 *abl = ab + base + lb;
-        const bool had_some = some_in;
-        if (all_in && lb + B - 1 <= lmax) {
-#pragma unroll
-            for (int b = 0; b < B; b += 2) {
-                const double2 c0 = abl[b], c1 = abl[b + 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
-                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
-                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < B; b += 2) {
-                const int l = lb + b;
-                if (l > lmax)
-                    break;
-                const double2 c0 = abl[b];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    adj_acc<SPIN, 1>(cb + b * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
-                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                }
-                if (l + 1 > lmax)
-                    break;
-                const double2 c1 = abl[b + 1];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
-                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
-                }
-            }
-            all_in = true;
-            some_in = false;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                ring_rescale<SPIN>(rg[r]);
-                const int p = slice_phase<SPIN>(rg[r]);
-                all_in = all_in && p == 2;
-                some_in = some_in || p != 0;
-            }
-        }
-        if (!had_some)
-            continue;  // every lane was below range for this whole block
+    // Reduce the block sums cb over the wave and add them to acc (degrees lb..).
+    auto reduce_add = [&](double (&cb)[V], int lb) {
         // stage 1: lanes L, L + 32 -> V/2 values; value k + (L / 32) V/2 in slot k
         double c1[V / 2];
 #pragma unroll
         for (int k = 0; k < V / 2; ++k)
             c1[k] = swap_add32(cb[k], cb[k + V / 2]);
-        // stage 2: rows (0,1), (2,3) -> V/4 values per lane; slot k of row g holds value
-        // k + (g & 1) V/4 + (g >> 1) V/2, partially summed over 4 lanes
+        // stage 2: rows (0,1), (2,3) -> V/4 values per lane; slot k of row g holds
+        // value k + (g & 1) V/4 + (g >> 1) V/2, partially summed over 4 lanes
         double c2[V / 4];
 #pragma unroll
         for (int k = 0; k < V / 4; ++k)
@@ -669,7 +627,73 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             sum += __shfl_xor(sum, d, 64);
         if (lane < V && lb + lane / NC <= lmax)
             unsafeAtomicAdd(acc + (base + lb) * NC + lane, sum);
+    };
+    // Masked block: per-lane in-range masks, rescaling and phase update at its end.
+    auto masked_block = [&](int lb) {
+        double cb[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            cb[k] = 0.0;
+        const double2 *abl = ab + base + lb;
+        const bool had_some = some_in;
+#pragma unroll
+        for (int b = 0; b < B; b += 2) {
+            const int l = lb + b;
+            if (l > lmax)
+                break;
+            const double2 c0 = abl[b];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                adj_acc<SPIN, 1>(cb + b * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                ring_advance<SPIN>(rg[r], c0.x, c0.y);
+            }
+            if (l + 1 > lmax)
+                break;
+            const double2 c1 = abl[b + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+            }
+        }
+        all_in = true;
+        some_in = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ring_rescale<SPIN>(rg[r]);
+            const int p = slice_phase<SPIN>(rg[r]);
+            all_in = all_in && p == 2;
+            some_in = some_in || p != 0;
+        }
+        if (had_some)  // otherwise every lane was below range for the whole block
+            reduce_add(cb, lb);
+    };
+    // Three sequential loops (no loop-carried value crosses a branch merge):
+    // masked blocks until every lane is in range, full unmasked blocks, masked tail.
+    int lb = l0;
+    for (; lb <= lmax && !all_in; lb += B)
+        masked_block(lb);
+    for (; lb + B - 1 <= lmax; lb += B) {
+        double cb[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            cb[k] = 0.0;
+        const double2 *abl = ab + base + lb;
+#pragma unroll
+        for (int b = 0; b < B; b += 2) {
+            const double2 c0 = abl[b], c1 = abl[b + 1];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
+                ring_advance<SPIN>(rg[r], c0.x, c0.y);
+                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
+                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+            }
+        }
+        reduce_add(cb, lb);
     }
+    if (lb <= lmax)
+        masked_block(lb);
 }
 
 template <int R, int B>
