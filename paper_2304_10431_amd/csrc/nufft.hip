@@ -12,7 +12,7 @@
 // Points are processed in tile order: every work item ("chunk") holds at most
 // CHUNK consecutive sorted points of one tile, and stages that tile's grid patch
 // (tile plus a w - 1 halo) in LDS.  Spreading accumulates into the LDS patch with
-// LDS atomics and then flushes the patch to the grid with global atomics.
+// fixed-point integer LDS atomics and then flushes it to the grid with global atomics.
 #include "gsht_internal.hpp"
 
 #include <algorithm>
@@ -488,28 +488,71 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
     }
 }
 
+// Fixed-point accumulator of the spreading patch: on gfx950 integer LDS atomic adds
+// run 3.6x (u32) / 2x (u64) faster than FP64 ones and 26x faster than FP32 ones.
+template <typename T> struct SpreadAcc;
+template <> struct SpreadAcc<float> {
+    using U = unsigned int;
+    using S = int;
+    static constexpr double RANGE = 0x1p31;
+    __device__ static U quant(double q) { return (U)__double2int_rn(q); }
+};
+template <> struct SpreadAcc<double> {
+    using U = unsigned long long;
+    using S = long long;
+    static constexpr double RANGE = 0x1p63;
+    __device__ static U quant(double q) { return (U)__double2ll_rn(q); }
+};
+
+// Type-1 spreading of one chunk.  The chunk's patch accumulates in fixed point:
+// every contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with
+// S = sum over the chunk's points of |Re y| + |Im y|, which bounds every cell sum,
+// so the two's-complement integer adds never wrap; the quantisation step is
+// S / RANGE (2^-31 S for FP32, 2^-63 S for FP64).  Non-zero cells are flushed to the
+// grid with global atomics.
 template <typename T, int W, bool CPLX>
 __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
     const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
     const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
     T *__restrict__ grid)
 {
-    // The LDS patch accumulates in FP64 for both precisions: on gfx950 FP64 LDS
-    // atomic adds run several times faster than FP32 ones (and round less).
+    using A = SpreadAcc<T>;
+    using U = typename A::U;
     extern __shared__ unsigned char smem_raw[];
-    double *patch = reinterpret_cast<double *>(smem_raw);  // interleaved (re, im) when CPLX
+    U *patch = reinterpret_cast<U *>(smem_raw);  // interleaved (re, im) when CPLX
+    __shared__ double wsum[NUFFT_THREADS / 64];
     constexpr int NC = CPLX ? 2 : 1;
     const int4 ck = chunks[blockIdx.x];
     const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
     const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    const int n = ck.z - ck.y;
     for (int idx = threadIdx.x; idx < PR * PC * NC; idx += NUFFT_THREADS)
-        patch[idx] = 0.0;
+        patch[idx] = 0;
+    // bound S of every cell sum
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
+        const int32_t src = perm[ck.y + k];
+        s += fabs((double)in[src]);
+        if constexpr (CPLX)
+            s += fabs((double)in[g.npts + src]);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0)
+        wsum[threadIdx.x >> 6] = s;
     __syncthreads();
+    double S = 0.0;
+#pragma unroll
+    for (int w = 0; w < NUFFT_THREADS / 64; ++w)
+        S += wsum[w];
+    if (!(S > 0.0) || !isfinite(S))
+        return;  // nothing (finite) to spread; uniform over the block
+    const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
     // Neighbouring sorted points have overlapping windows; visiting the chunk with a
     // stride coprime to its length keeps the lanes of a wave on distant points, so
     // that the LDS atomics of one instruction rarely hit the same cell.
-    const int n = ck.z - ck.y;
     const int stride = (n % 97 == 0) ? 89 : 97;
     for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
         const int p = ck.y + (int)(((int64_t)k * stride) % n);
@@ -519,21 +562,26 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
         if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
             continue;  // cannot happen for points sorted by the same arithmetic
         const int32_t src = perm[p];
-        const T yr = in[src];
-        const T yi = CPLX ? in[g.npts + src] : (T)0;
+        const double yr = (double)in[src] * scale;
+        const double yi = CPLX ? (double)in[g.npts + src] * scale : 0.0;
+        double dy[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            dy[j] = (double)wy[j];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const T fr = wx[i] * yr, fi = wx[i] * yi;
-            double *rowp = patch + ((lr + i) * PC + lc) * NC;
+            const double fr = (double)wx[i] * yr, fi = (double)wx[i] * yi;
+            U *rowp = patch + ((lr + i) * PC + lc) * NC;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(rowp + NC * j, (double)(fr * wy[j]));
+                atomicAdd(rowp + NC * j, A::quant(fr * dy[j]));
                 if constexpr (CPLX)
-                    atomicAdd(rowp + NC * j + 1, (double)(fi * wy[j]));
+                    atomicAdd(rowp + NC * j + 1, A::quant(fi * dy[j]));
             }
         }
     }
     __syncthreads();
+    const double inv = 1.0 / scale;
     for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
         const int pr = idx / PC, pc = idx - (idx / PC) * PC;
         const int r = row0 + pr;
@@ -543,13 +591,13 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
         if (c >= g.n2)
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
-        const T vr = (T)patch[idx * NC];
-        if (vr != (T)0)
-            unsafeAtomicAdd(dst, vr);
+        const typename A::S qr = (typename A::S)patch[idx * NC];
+        if (qr != 0)
+            unsafeAtomicAdd(dst, (T)((double)qr * inv));
         if constexpr (CPLX) {
-            const T vi = (T)patch[idx * NC + 1];
-            if (vi != (T)0)
-                unsafeAtomicAdd(dst + 1, vi);
+            const typename A::S qi = (typename A::S)patch[idx * NC + 1];
+            if (qi != 0)
+                unsafeAtomicAdd(dst + 1, (T)((double)qi * inv));
         }
     }
 }
@@ -596,12 +644,12 @@ static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
     const GridGeom g = make_geom(p);
     const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
     if (p.spin) {
-        const size_t sm = (size_t)PR * PC * 2 * sizeof(double);
+        const size_t sm = (size_t)PR * PC * 2 * sizeof(typename SpreadAcc<T>::U);
         hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.G);
     } else {
-        const size_t sm = (size_t)PR * PC * sizeof(double);
+        const size_t sm = (size_t)PR * PC * sizeof(typename SpreadAcc<T>::U);
         hipLaunchKernelGGL((spread_kernel<T, W, false>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.g);
