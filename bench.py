@@ -37,6 +37,23 @@ sys.path.insert(0, ROOT)
 METRIC = "synth+adjoint s @ lmax4096 spin2 ~50M pts: FP32 eps1e-5 vs FP64 eps1e-10; %roof"
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 HBM_PEAK_GBS = 8000.0
+CALIB_BYTES = 1 << 30            # plain copy used to calibrate the HBM byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_legendre_synth_pollens_thin6144.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_10431_amd", "csrc", "legendre_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the Legendre synthesis from the committed counter
+    runs, or None if they were taken on a different version of the kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def log(*a):
@@ -118,6 +135,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
@@ -130,6 +149,12 @@ def main():
 
     spec = wl.WORKLOADS[args.workload]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    if args.copy_calib:
+        src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     if spec["points"] == "thin":
         th0, ph0 = wl.thinned_gl_grid(spec["nring"])
@@ -196,7 +221,7 @@ def main():
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_launch": flops, "avg_launch_ms": leg_avg_s * 1e3,
                      "legendre_adj_frac": flops / adj_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
     }

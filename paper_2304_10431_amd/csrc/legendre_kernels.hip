@@ -193,6 +193,27 @@ hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---- work mapping -------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the MI355X's 8 XCDs.  All chunks of one
+// m are kept on one XCD, so that XCD's L2 serves the m's coefficient stream to all of
+// them (spread over every XCD, each 4 MB L2 would hold dozens of streams and thrash),
+// and the m values are dealt to the XCDs round-robin, largest work first on each.
+constexpr int NXCD = 8;
+
+__device__ inline void xcd_map(int nchunk, int &m, int &chunk)
+{
+    const int x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
+    const int g = k / nchunk;
+    chunk = k - g * nchunk;
+    m = x + NXCD * g;
+}
+
+static unsigned xcd_grid(int mmax, int nchunk)
+{
+    return (unsigned)(NXCD * ((mmax + NXCD) / NXCD) * nchunk);
+}
+
 // ---- per-ring recurrence state ------------------------------------------------------
 
 struct Ring {
@@ -315,12 +336,14 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
     int nchunk, typename cplxk<T>::type *__restrict__ D)
 {
     constexpr int US = SPIN ? 4 : 2;
-    const int m = blockIdx.x / nchunk;
-    const int chunk = blockIdx.x - m * nchunk;
+    int m, chunk;
+    xcd_map(nchunk, m, chunk);
+    if (m > mmax)
+        return;
     const int lane = threadIdx.x;
     const StartInfo si = st[m];
     const int l0 = si.l0;
-    const bool live = (l0 <= lmax) && (lfirst[blockIdx.x] <= lmax);
+    const bool live = (l0 <= lmax) && (lfirst[m * nchunk + chunk] <= lmax);
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
 
     Ring rg[R];
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
 template <int R>
 static void synth_launch(const gsht_plan &p, void *Dout, hipStream_t s)
 {
-    dim3 blk(64), grd((unsigned)((p.mmax + 1) * p.syn_nchunk));
+    dim3 blk(64), grd(xcd_grid(p.mmax, p.syn_nchunk));
 #define GSHT_LEG_SYNTH(T, SP, C)                                                                 \
     hipLaunchKernelGGL((leg_synth_kernel<T, SP, R>), grd, blk, 0, s, p.leg.ab, p.uprep,          \
                        p.leg.start, p.leg.lfirst_syn, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,     \
@@ -536,12 +559,14 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     constexpr int V = B * NC;
     static_assert(64 % V == 0 && V >= 8, "block values must divide the wave");
     __shared__ double red[V * 16];
-    const int m = blockIdx.x / nchunk;
-    const int chunk = blockIdx.x - m * nchunk;
+    int m, chunk;
+    xcd_map(nchunk, m, chunk);
+    if (m > mmax)
+        return;
     const int lane = threadIdx.x;
     const StartInfo si = st[m];
     const int l0 = si.l0;
-    if (l0 > lmax || lfirst[blockIdx.x] > lmax)
+    if (l0 > lmax || lfirst[m * nchunk + chunk] > lmax)
         return;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double ms = ((s + m) & 1) ? -1.0 : 1.0;
@@ -699,7 +724,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
 template <int R, int B>
 static void adj_launch(const gsht_plan &p, const void *Din, hipStream_t s)
 {
-    dim3 blk(64), grd((unsigned)((p.mmax + 1) * p.adj_nchunk));
+    dim3 blk(64), grd(xcd_grid(p.mmax, p.adj_nchunk));
 #define GSHT_LEG_ADJ(T, SP, C)                                                                   \
     hipLaunchKernelGGL((leg_adjoint_kernel<T, SP, R, B>), grd, blk, 0, s, p.leg.ab, p.leg.start, \
                        p.leg.lfirst_adj, (const C *)Din, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,  \
