@@ -143,6 +143,7 @@ def main():
               "(the multi-GPU sharding is described, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    log("importing torch")
     import torch
     from paper_2304_10431_amd import gsht
     from paper_2304_10431_amd import workloads as wl
@@ -156,6 +157,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t0 = time.time()
+    log("generating %s points" % args.workload)
     if spec["points"] == "thin":
         th0, ph0 = wl.thinned_gl_grid(spec["nring"])
     elif spec["points"] == "gl":
@@ -179,6 +181,7 @@ def main():
     results = {}
     maps = {}
     for prec, eps in forms:
+        log("timing %s eps %.0e" % (prec, eps))
         plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup)
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
