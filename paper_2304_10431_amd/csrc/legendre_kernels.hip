@@ -11,15 +11,18 @@
 // column -m of a spin-s field through sY_{l,-m} = (-1)^(s+m) (-s)Y_lm.
 //
 // Start values at l0 = max(m, s) can lie far below the double range: each channel
-// carries an exponent offset (a non-positive multiple of 512) and is accumulated
-// only once that offset is 0; anything smaller than 2^-204 relative is dropped.
+// carries an exponent offset e (a non-positive multiple of 512), the true value
+// being p 2^e, and contributes only while e = 0; anything smaller than about
+// 2^-256 relative is dropped.
 //
 // Work decomposition: one wave per (m, chunk); a chunk is R slices of 64
 // consecutive ring pairs, lane L of slice r owning pair 64 (R chunk + r) + L.
-// Degrees advance in blocks of 8.  A block runs "masked" (per-lane in-range
-// masks, rescaling, phase update at its end) until every slice of the wave is in
-// range; from then on blocks run without masks or checks.  Chunks whose most
-// equatorial ring stays below 2^-900 up to lmax are skipped outright.
+// Degrees advance in blocks of 8; offsets change only at block ends.  A block runs
+// "masked" (out-of-range channels excluded for the whole block, rescaling and
+// phase update at its end) until every lane of the wave is in range; from then on
+// blocks run without masks or checks, and only a final partial block checks the
+// degree bound.  Chunks whose most equatorial ring stays below 2^-900 up to lmax
+// are skipped outright.
 #include "gsht_internal.hpp"
 
 namespace gsht {
@@ -283,8 +286,8 @@ __device__ inline int slice_phase(const Ring &r)
     return __any(some) ? 1 : 0;
 }
 
-__device__ inline double mask_a(const Ring &r) { return r.ea == 0 ? r.a1 : 0.0; }
-__device__ inline double mask_b(const Ring &r) { return r.eb == 0 ? r.b1 : 0.0; }
+template <bool B>
+using flag = std::integral_constant<bool, B>;
 
 // ---- synthesis -------------------------------------------------------------------
 
@@ -327,6 +330,20 @@ __device__ inline void synth_acc(double (&c)[8], double va, double vb, const dou
     }
 }
 
+// Add a masked block's sums t to c for the channels in range (the offsets are
+// those the block ran with: rescaling happens after the fold).  Channel +s feeds
+// c[0,1,6,7], channel -s c[2..5]; spin 0 has channel +s only.
+template <bool SPIN>
+__device__ inline void synth_fold(double (&c)[8], const double (&t)[8], const Ring &r)
+{
+    const bool ia = r.ea == 0, ib = SPIN && r.eb == 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const bool in = (!SPIN || k < 2 || k > 5) ? ia : ib;
+        c[k] += in ? t[k] : 0.0;
+    }
+}
+
 constexpr int LB = 8;  // degrees per block
 
 template <typename T, bool SPIN, int R>
@@ -358,30 +375,46 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
             c[r][k] = 0.0;
         all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
     }
-    // Masked block: per-lane in-range masks, then rescaling and the slice phases.
-    auto masked_block = [&](int lb) {
+    // Masked block: the block's terms are summed separately and added only for
+    // channels in range (offset 0, constant inside a block); then rescaling and the
+    // slice phases.  Only the final partial block (TAIL) checks the degree bound.
+    auto masked_block = [&](int lb, auto tail) {
+        constexpr bool TAIL = decltype(tail)::value;
         const double2 *abl = ab + base + lb;
         const double *ul = u + US * (base + lb);
+        double t[R][8];
 #pragma unroll
-        for (int b = 0; b < LB; b += 2) {
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                t[r][k] = 0.0;
+        // two rolled halves: a fully unrolled block would load all its scalar
+        // coefficients at once and run out of scalar registers
+#pragma unroll 1
+        for (int h = 0; h < LB; h += LB / 2)
+#pragma unroll
+        for (int b = h; b < h + LB / 2; b += 2) {
             const int l = lb + b;
-            if (l > lmax)
+            if (TAIL && l > lmax)
                 break;
             const double2 c0 = abl[b];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                synth_acc<SPIN, 1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * b);
+                synth_acc<SPIN, 1>(t[r], rg[r].a1, rg[r].b1, ul + US * b);
                 ring_advance<SPIN>(rg[r], c0.x, c0.y);
             }
-            if (l + 1 > lmax)
+            if (TAIL && l + 1 > lmax)
                 break;
             const double2 c1 = abl[b + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                synth_acc<SPIN, -1>(c[r], mask_a(rg[r]), mask_b(rg[r]), ul + US * (b + 1));
+                synth_acc<SPIN, -1>(t[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
                 ring_advance<SPIN>(rg[r], c1.x, c1.y);
             }
         }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            synth_fold<SPIN>(c[r], t[r], rg[r]);
         all_in = true;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -391,10 +424,11 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
     };
     if (live) {
         // Three sequential loops (no loop-carried value crosses a branch merge):
-        // masked blocks until every lane is in range, full unmasked blocks, masked tail.
+        // masked full blocks until every lane is in range, full plain blocks, and
+        // a masked partial tail.
         int lb = l0;
-        for (; lb <= lmax && !all_in; lb += LB)
-            masked_block(lb);
+        for (; lb + LB - 1 <= lmax && !all_in; lb += LB)
+            masked_block(lb, flag<false>());
         for (; lb + LB - 1 <= lmax; lb += LB) {
             const double2 *abl = ab + base + lb;
             const double *ul = u + US * (base + lb);
@@ -411,7 +445,7 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
             }
         }
         if (lb <= lmax)
-            masked_block(lb);
+            masked_block(lb, flag<true>());
     }
     // south values carry (-1)^(l+m) = (-1)^(l0+m) (-1)^(l-l0)
     const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
@@ -653,31 +687,41 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
         if (lane < V && lb + lane / NC <= lmax)
             unsafeAtomicAdd(acc + (base + lb) * NC + lane, sum);
     };
-    // Masked block: per-lane in-range masks, rescaling and phase update at its end.
-    auto masked_block = [&](int lb) {
+    // Masked block: channels out of range (offset < 0, constant inside a block) get
+    // the weight 0 for the block; rescaling and phase update at its end.  Only the
+    // final partial block (TAIL) checks the degree bound.
+    auto masked_block = [&](int lb, auto tail) {
+        constexpr bool TAIL = decltype(tail)::value;
         double cb[V];
 #pragma unroll
         for (int k = 0; k < V; ++k)
             cb[k] = 0.0;
         const double2 *abl = ab + base + lb;
         const bool had_some = some_in;
+        double wa[R], wb[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            wa[r] = rg[r].ea == 0 ? 1.0 : 0.0;
+            wb[r] = (SPIN && rg[r].eb == 0) ? 1.0 : 0.0;
+        }
 #pragma unroll
         for (int b = 0; b < B; b += 2) {
             const int l = lb + b;
-            if (l > lmax)
+            if (TAIL && l > lmax)
                 break;
             const double2 c0 = abl[b];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                adj_acc<SPIN, 1>(cb + b * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1 * wa[r], rg[r].b1 * wb[r]);
                 ring_advance<SPIN>(rg[r], c0.x, c0.y);
             }
-            if (l + 1 > lmax)
+            if (TAIL && l + 1 > lmax)
                 break;
             const double2 c1 = abl[b + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], mask_a(rg[r]), mask_b(rg[r]));
+                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1 * wa[r],
+                                  rg[r].b1 * wb[r]);
                 ring_advance<SPIN>(rg[r], c1.x, c1.y);
             }
         }
@@ -690,14 +734,15 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             all_in = all_in && p == 2;
             some_in = some_in || p != 0;
         }
-        if (had_some)  // otherwise every lane was below range for the whole block
+        if (had_some)  // otherwise every lane was out of range for the whole block
             reduce_add(cb, lb);
     };
     // Three sequential loops (no loop-carried value crosses a branch merge):
-    // masked blocks until every lane is in range, full unmasked blocks, masked tail.
+    // masked full blocks until every lane is in range, full plain blocks, and a
+    // masked partial tail.
     int lb = l0;
-    for (; lb <= lmax && !all_in; lb += B)
-        masked_block(lb);
+    for (; lb + B - 1 <= lmax && !all_in; lb += B)
+        masked_block(lb, flag<false>());
     for (; lb + B - 1 <= lmax; lb += B) {
         double cb[V];
 #pragma unroll
@@ -718,7 +763,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
         reduce_add(cb, lb);
     }
     if (lb <= lmax)
-        masked_block(lb);
+        masked_block(lb, flag<true>());
 }
 
 template <int R, int B>
