@@ -220,6 +220,7 @@ def main():
                    "npts": npts, "lmax": lmax, "mmax": mmax, "spin": spin},
         "forms": {k: {"s_per_step": v["s_per_step"], "plan_s": v["plan_s"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
+                      "column_mode": v["info"]["column_mode"],
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",

@@ -140,6 +140,10 @@ typedef struct {
     int ntile1, ntile2; /* tiles per dimension; tile key = (row / tile1) * ntile2 + col / tile2 */
     int64_t nchunks;    /* work items of the interpolation / spreading kernels */
     int64_t workspace_bytes;
+    int column_mode;    /* per-column FFT stage: 2 = doubled FFT, deconvolution and theta
+                           FFT in one kernel per column (column in LDS), 1 = doubled FFT and
+                           deconvolution fused with a separate theta FFT, 0 = separate
+                           library FFTs; chosen from the LDS size per workgroup */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */

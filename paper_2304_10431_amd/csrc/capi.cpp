@@ -322,6 +322,110 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
 
 size_t csize(int prec) { return prec == GSHT_F64 ? 16 : 8; }
 
+// Radices of an in-LDS transform of length n (largest first), or false if n has a
+// prime factor above 7 or needs more than COL_MAXP passes.
+bool col_radices(int n, std::vector<int> &rad)
+{
+    rad.clear();
+    int m = n;
+    for (int f : {7, 5, 3})
+        while (m % f == 0) {
+            rad.push_back(f);
+            m /= f;
+        }
+    while (m % 16 == 0) {
+        rad.push_back(16);
+        m /= 16;
+    }
+    for (int f : {8, 4, 2})
+        if (m % f == 0) {
+            rad.push_back(f);
+            m /= f;
+        }
+    if (m != 1 || rad.empty() || (int)rad.size() > COL_MAXP)
+        return false;
+    std::sort(rad.begin(), rad.end(), [](int a, int b) { return a > b; });
+    return true;
+}
+
+// Twiddle table w_n^k = exp(-2 pi i k / n) and the position of every frequency after
+// the decimation-in-frequency passes (frequency k = q0 + r0 (q1 + r1 (q2 + ...)) sits
+// at sum_i q_i s_i, s_i = n / (r0 ... ri)).
+int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
+{
+    std::vector<int> rad;
+    if (!col_radices(n, rad))
+        return fail(GSHT_EINVAL, "length %d cannot run as an in-LDS transform", n);
+    f.n = n;
+    f.npass = (int)rad.size();
+    for (int i = 0; i < f.npass; ++i)
+        f.radix[i] = rad[i];
+    std::vector<double2> tw((size_t)n);
+    std::vector<int32_t> perm((size_t)n);
+    const long double twopi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < n; ++k) {
+        const long double ang = twopi * (long double)k / (long double)n;
+        tw[(size_t)k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+    }
+    for (int k = 0; k < n; ++k) {
+        long rest = k, stride = n, pos = 0;
+        for (int i = 0; i < f.npass; ++i) {
+            stride /= rad[i];
+            pos += (rest % rad[i]) * stride;
+            rest /= rad[i];
+        }
+        perm[(size_t)k] = (int32_t)pos;
+    }
+    int rc;
+    double2 *dtw = nullptr;
+    int32_t *dperm = nullptr;
+    if ((rc = dev_alloc(p, &dtw, sizeof(double2) * (size_t)n)) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &dperm, sizeof(int32_t) * (size_t)n)) != GSHT_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(dtw, tw.data(), sizeof(double2) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    f.tw = dtw;
+    f.perm = dperm;
+    return GSHT_OK;
+}
+
+// Per-column FFT stage: fuse as much as fits in one workgroup's LDS.  The
+// environment variable GSHT_COLUMN_MODE (0, 1, 2) forces a mode for testing.
+int setup_columns(gsht_plan *p, hipStream_t s)
+{
+    int dev = 0, maxsh = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lim = std::min((size_t)maxsh, COL_MAX_BYTES), cs = csize(p->prec);
+    std::vector<int> rad;
+    const bool fit_d = (size_t)p->nd * cs <= lim && col_radices(p->nd, rad);
+    const bool fit_1 = fit_d && (size_t)p->n1 * cs <= lim && p->n1 <= COL_MAX_N &&
+                       col_radices(p->n1, rad);
+    int mode = fit_1 ? 2 : fit_d ? 1 : 0;
+    const char *e = getenv("GSHT_COLUMN_MODE");
+    if (e) {
+        const int want = atoi(e);
+        if (want < 0 || want > 2 || (want == 2 && !fit_1) || (want == 1 && !fit_d))
+            return fail(GSHT_EINVAL, "GSHT_COLUMN_MODE=%s is not possible for this plan", e);
+        mode = want;
+    }
+    // the runtime may refuse the LDS size: then fall back to the next mode
+    for (; mode > 0; --mode) {
+        p->colmode = mode;
+        const hipError_t he = column_set_lds(*p);
+        if (he == hipSuccess)
+            break;
+        (void)hipGetLastError();
+        if (e)
+            return fail(GSHT_EHIP, "column stage LDS size refused: %s", hipGetErrorString(he));
+    }
+    p->colmode = mode;
+    int rc;
+    if (mode >= 1 && (rc = setup_colfft(p, p->cf_d, p->nd, s)) != GSHT_OK) return rc;
+    if (mode == 2 && (rc = setup_colfft(p, p->cf_1, p->n1, s)) != GSHT_OK) return rc;
+    return GSHT_OK;
+}
+
 int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double *theta,
                      const double *phi, int64_t npts, double eps, int prec, hipStream_t s)
 {
@@ -371,12 +475,18 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
                         (long long)ninv);
         }
     }
-    // FFT plans
+    // per-column stage, then the rocFFT plans it leaves to rocFFT
+    if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
     const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;
-    rc = make_fft(p->fD_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, nd, p->ncol);
-    if (rc == GSHT_OK) rc = make_fft(p->fD_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, nd, p->ncol);
-    if (rc == GSHT_OK) rc = make_fft(p->fT_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n1, p->ncol);
-    if (rc == GSHT_OK) rc = make_fft(p->fT_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n1, p->ncol);
+    rc = GSHT_OK;
+    if (p->colmode == 0) {
+        rc = make_fft(p->fD_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, nd, p->ncol);
+        if (rc == GSHT_OK) rc = make_fft(p->fD_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, nd, p->ncol);
+    }
+    if (rc == GSHT_OK && p->colmode < 2) {
+        rc = make_fft(p->fT_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n1, p->ncol);
+        if (rc == GSHT_OK) rc = make_fft(p->fT_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n1, p->ncol);
+    }
     if (rc == GSHT_OK) {
         if (spin) {
             rc = make_fft(p->fP_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n2, p->nrows);
@@ -461,9 +571,14 @@ int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s)
 {
     RUN(ST_PREP, launch_prep_alm(*p, alm, s));
     RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, s));
-    RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
-    RUN(ST_DECONV_FWD, launch_deconv_fwd(*p, s));
-    RUNFFT(ST_FFT_THETA_INV, run_fft(p->fT_inv, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
+    if (p->colmode == 0) {
+        RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
+        RUN(ST_DECONV_FWD, launch_deconv_fwd(*p, s));
+    } else {
+        RUN(ST_COLUMN_FWD, launch_column_fwd(*p, s));
+    }
+    if (p->colmode < 2)
+        RUNFFT(ST_FFT_THETA_INV, run_fft(p->fT_inv, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
     RUN(ST_TRANSPOSE_FWD, launch_transpose_fwd(*p, s));
     if (p->spin)
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
@@ -486,9 +601,14 @@ int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s)
     else
         RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->g, p->G, p->fftwork, p->fftwork_bytes, s));
     RUN(ST_TRANSPOSE_ADJ, launch_transpose_adj(*p, s));
-    RUNFFT(ST_FFT_THETA_FWD, run_fft(p->fT_fwd, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
-    RUN(ST_DECONV_ADJ, launch_deconv_adj(*p, s));
-    RUNFFT(ST_FFT_D_INV, run_fft(p->fD_inv, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
+    if (p->colmode < 2)
+        RUNFFT(ST_FFT_THETA_FWD, run_fft(p->fT_fwd, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
+    if (p->colmode == 0) {
+        RUN(ST_DECONV_ADJ, launch_deconv_adj(*p, s));
+        RUNFFT(ST_FFT_D_INV, run_fft(p->fD_inv, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
+    } else {
+        RUN(ST_COLUMN_ADJ, launch_column_adj(*p, s));
+    }
     RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, s));
     RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, s));
     return ok();
@@ -498,7 +618,7 @@ const char *kStageNames[ST_COUNT] = {
     "prep_alm",     "legendre_synth", "fft_doubled_fwd", "deconv_fwd", "fft_theta_inv",
     "transpose_fwd", "fft_phi_inv",   "interp",          "zero_grid",  "spread",
     "fft_phi_fwd",  "transpose_adj",  "fft_theta_fwd",   "deconv_adj", "fft_doubled_inv",
-    "legendre_adj", "finalize"};
+    "legendre_adj", "finalize",       "column_fwd",      "column_adj"};
 
 }  // namespace
 
@@ -597,6 +717,7 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->ntile2 = p->nt2;
     info->nchunks = p->nchunks;
     info->workspace_bytes = p->workspace_bytes;
+    info->column_mode = p->colmode;
     return ok();
 }
 

@@ -35,6 +35,21 @@ struct LegendreTables {
     int32_t *lfirst_adj = nullptr;  // [(mmax + 1) * adj_nchunk] same for the adjoint's chunks
 };
 
+// One in-LDS FFT of length n (per-column stage): decimation-in-frequency passes of
+// the given radices, twiddle table tw[k] = exp(-2 pi i k / n) (FP64), and perm[k] =
+// LDS position of frequency k after the last pass (digit reversal).
+constexpr int COL_MAXP = 16;
+struct ColFFT {
+    int n = 0, npass = 0;
+    int radix[COL_MAXP] = {};
+    const double2 *tw = nullptr;
+    const int32_t *perm = nullptr;
+};
+// Largest LDS buffer a column workgroup may use, and the resulting length limit
+// (the kernels keep up to COL_MAX_N / 1024 deconvolved values per thread).
+constexpr size_t COL_MAX_BYTES = 163840;
+constexpr int COL_MAX_N = 20480;
+
 enum Stage {
     ST_PREP = 0,
     ST_LEG_SYNTH,
@@ -53,6 +68,8 @@ enum Stage {
     ST_FFT_D_INV,
     ST_LEG_ADJ,
     ST_FINALIZE,
+    ST_COLUMN_FWD,
+    ST_COLUMN_ADJ,
     ST_COUNT
 };
 
@@ -100,6 +117,11 @@ struct gsht_plan {
     void *G = nullptr;     // complex grid [nrows][n2] (spin > 0) or half spectrum [nrows][n2/2+1]
     void *g = nullptr;     // real grid [nrows][n2] (spin 0 only)
     double *acc = nullptr; // adjoint accumulators [nalm][2 * ncomp]
+    // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
+    // transform and deconvolution in one kernel (theta transform by rocFFT),
+    // 2 = doubled transform, deconvolution and theta transform in one kernel
+    int colmode = 0;
+    gsht::ColFFT cf_d, cf_1;  // lengths nd and n1
     // FFT plans
     gsht::FFTPlan fD_fwd, fD_inv, fT_inv, fT_fwd, fP_inv, fP_fwd;
     void *fftwork = nullptr;
@@ -126,9 +148,15 @@ hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, hipStream_t s);
 // ---- staging (staging.hip) -------------------------------------------------
 hipError_t launch_deconv_fwd(const gsht_plan &p, hipStream_t s);     // D -> E
 hipError_t launch_transpose_fwd(const gsht_plan &p, hipStream_t s);  // E -> G
-hipError_t launch_transpose_adj(const gsht_plan &p, hipStream_t s);  // G -> E
+hipError_t launch_transpose_adj(const gsht_plan &p, hipStream_t s);  // G -> E (all rows,
+                                                                     // kept rows only if colmode 2)
 hipError_t launch_deconv_adj(const gsht_plan &p, hipStream_t s);     // E -> D
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
+
+// ---- per-column FFT stage (colfft.hip) ------------------------------------
+hipError_t column_set_lds(const gsht_plan &p);                    // once per plan
+hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s);  // D -> E
+hipError_t launch_column_adj(const gsht_plan &p, hipStream_t s);  // E -> D
 
 // ---- points (nufft.hip) ----------------------------------------------------
 // Bin sort; returns the number of invalid coordinates through *n_invalid (host)

@@ -168,11 +168,14 @@ __global__ void transpose_fwd_kernel(const typename cplx2<T>::type *__restrict__
     }
 }
 
-// Adjoint: E[col][a] = G[(a - a_min) mod n1][b(col)] if that row is kept, else 0.
+// Adjoint: E[col][a] = G[(a - a_min) mod n1][b(col)] if that row is kept, else 0
+// (with all_rows == 0 the rows that are not kept are left untouched: the fused
+// column stage reads kept rows only).
 template <typename T>
 __global__ void transpose_adj_kernel(const typename cplx2<T>::type *__restrict__ G, int mmax,
                                      int spin, int n1, int n2, int gcols, int nrows, int a_min,
-                                     int ncol, typename cplx2<T>::type *__restrict__ E)
+                                     int ncol, int all_rows,
+                                     typename cplx2<T>::type *__restrict__ E)
 {
     __shared__ typename cplx2<T>::type tile[TT][TT + 1];
     const int c0 = blockIdx.x * TT, a0 = blockIdx.y * TT;
@@ -197,8 +200,16 @@ __global__ void transpose_adj_kernel(const typename cplx2<T>::type *__restrict__
     __syncthreads();
     for (int yy = ty; yy < TT; yy += TR) {
         const int col = c0 + yy, a = a0 + tx;
-        if (col < ncol && a < n1)
+        if (col < ncol && a < n1) {
+            if (!all_rows) {
+                int r = (a - a_min) % n1;
+                if (r < 0)
+                    r += n1;
+                if (r >= nrows)
+                    continue;
+            }
             E[(size_t)col * n1 + a] = tile[tx][yy];
+        }
     }
 }
 
@@ -221,13 +232,14 @@ hipError_t launch_transpose_adj(const gsht_plan &p, hipStream_t s)
 {
     const int gc = grid_cols(p);
     dim3 blk(TT, TR), grd((p.ncol + TT - 1) / TT, (p.n1 + TT - 1) / TT);
+    const int all_rows = p.colmode == 2 ? 0 : 1;
     if (p.prec == GSHT_F64)
         hipLaunchKernelGGL(transpose_adj_kernel<double>, grd, blk, 0, s, (const double2 *)p.G,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.ncol,
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.ncol, all_rows,
                            (double2 *)p.E);
     else
         hipLaunchKernelGGL(transpose_adj_kernel<float>, grd, blk, 0, s, (const float2 *)p.G,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.ncol,
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.ncol, all_rows,
                            (float2 *)p.E);
     return hipGetLastError();
 }

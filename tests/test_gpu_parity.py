@@ -252,3 +252,36 @@ def test_plan_reuse_and_repeatability(G):
         assert torch.equal(m1, m2)
         ref = oracle.synth(a, lmax, lmax, spin, th[:500], ph[:500])
         assert oracle.eps_eff(m1[:, :500].cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("lmax,spin,prec,eps", [(130, 2, "f64", 1e-11), (130, 0, "f32", 1e-5),
+                                                (269, 1, "f64", 1e-9), (47, 3, "f32", 1e-4)])
+def test_column_stage_modes_agree(G, monkeypatch, lmax, spin, prec, eps):
+    """The fused per-column FFT stage (modes 2 and 1) against the separate library
+    FFTs (mode 0) and against the oracle, synthesis and adjoint."""
+    say("column modes", lmax, spin, prec, eps)
+    rng = np.random.default_rng(400 + lmax)
+    th, ph = wl.uniform_sphere(6000, rng)
+    a = wl.gaussian_alm(lmax, lmax, spin, rng)
+    y = rng.standard_normal((oracle.ncomp(spin), th.size))
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    ref_m = oracle.synth(a, lmax, lmax, spin, th, ph)
+    ref_a = oracle.adjoint(y, lmax, lmax, spin, th, ph)
+    w = np.sqrt(oracle.alm_weights(lmax, lmax))[None, :]
+    outs = {}
+    for mode in (0, 1, 2):
+        monkeypatch.setenv("GSHT_COLUMN_MODE", str(mode))
+        plan = G.Plan(dev(th), dev(ph), lmax, lmax, spin, eps, prec)
+        assert plan.info()["column_mode"] == mode
+        m = plan.synth(dev(a).to(cdt)).cpu().numpy().astype(np.float64)
+        b = plan.adjoint(dev(y).to(rdt)).cpu().numpy().astype(np.complex128)
+        plan.close()
+        em, ea = oracle.eps_eff(m, ref_m), oracle.eps_eff(b * w, ref_a * w)
+        say("  mode", mode, "synth", em, "adjoint", ea)
+        assert em <= eps and ea <= eps, (mode, em, ea)
+        outs[mode] = (m, b)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for mode in (1, 2):
+        assert rel_l2(outs[mode][0], outs[0][0]) <= tol
+        assert rel_l2(outs[mode][1] * w, outs[0][1] * w) <= tol
