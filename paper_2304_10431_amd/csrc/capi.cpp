@@ -279,13 +279,14 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         return rc;
     // Launch shapes of the Legendre kernels; GSHT_SYN_R, GSHT_ADJ_R and GSHT_ADJ_B
     // override the defaults for tuning (synthesis R in {1, 2, 4}; adjoint (R, B) in
-    // {(1,8), (2,8), (2,4), (4,4)}).
+    // {(1,8), (2,8), (2,4), (4,4), (3,8), (4,8)}).
     {
         const char *sr = getenv("GSHT_SYN_R"), *ar = getenv("GSHT_ADJ_R"), *ab = getenv("GSHT_ADJ_B");
         const int r1 = sr ? atoi(sr) : p->syn_r;
         const int r2 = ar ? atoi(ar) : p->adj_r, b = ab ? atoi(ab) : p->adj_b;
         const int key = 100 * r2 + b;
-        if ((r1 != 1 && r1 != 2 && r1 != 4) || (key != 108 && key != 208 && key != 204 && key != 404))
+        if ((r1 != 1 && r1 != 2 && r1 != 4) ||
+            (key != 108 && key != 208 && key != 204 && key != 404 && key != 308 && key != 408))
             return fail(GSHT_EINVAL, "unsupported Legendre launch shape syn_r=%d adj_r=%d adj_b=%d",
                         r1, r2, b);
         p->syn_r = r1;

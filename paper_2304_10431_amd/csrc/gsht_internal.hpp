@@ -95,8 +95,8 @@ struct gsht_plan {
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
     int64_t ntiles = 0, nchunks = 0;
     int ncol = 0, npairs = 0;
-    int syn_r = 1;       // ring pairs per lane, Legendre synthesis (slices of 64)
-    int adj_r = 2;       // ring pairs per lane, Legendre adjoint
+    int syn_r = 2;       // ring pairs per lane, Legendre synthesis (slices of 64)
+    int adj_r = 3;       // ring pairs per lane, Legendre adjoint
     int adj_b = 8;       // degrees per reduction block of the adjoint
     int syn_nchunk = 0;  // chunks of 64 * syn_r ring pairs
     int adj_nchunk = 0;  // chunks of 64 * adj_r ring pairs

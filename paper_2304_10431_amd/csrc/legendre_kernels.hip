@@ -12,8 +12,10 @@
 //
 // Start values at l0 = max(m, s) can lie far below the double range: each channel
 // carries an exponent offset e (a non-positive multiple of 512), the true value
-// being p 2^e, and contributes only while e = 0; anything smaller than about
-// 2^-256 relative is dropped.
+// being p 2^e, and contributes only while e = 0.  A channel reaches e = 0 once its
+// true value passes 2^-900 (synthesis) or 2^-256 (adjoint), checked at block ends,
+// so terms smaller than that, relative to the O(1) values of the oscillating
+// region, are dropped.
 //
 // Work decomposition: one wave per (m, chunk); a chunk is R slices of 64
 // consecutive ring pairs, lane L of slice r owning pair 64 (R chunk + r) + L.
@@ -85,14 +87,21 @@ __device__ inline XD start_value(double mant, int ex0, int a, int b, double sh, 
 
 constexpr double TWO_P256 = 0x1p256;
 constexpr double TWO_M512 = 0x1p-512;
+// In-range thresholds 2^INX: values from there up are held unscaled (normal
+// doubles; in the decaying region the recurrence only grows them).  The synthesis
+// takes 2^-900, which ends its masked phase early; the adjoint takes 2^-256, which
+// spares it the lane reductions of blocks that hold only negligible terms.
+constexpr int SYN_IN_EXP = -900;
+constexpr int ADJ_IN_EXP = -256;
 
 // true value = p 2^ex, ex a non-positive multiple of 512, ex == 0 <=> in range.
+template <int INX>
 __device__ inline void to_scaled(const XD &v, double &p, int &ex)
 {
     if (v.m == 0.0) {
         p = 0.0;
         ex = 0;
-    } else if (v.e >= -256) {
+    } else if (v.e >= INX + 1) {
         p = ldexp(v.m, v.e);
         ex = 0;
     } else {
@@ -225,15 +234,16 @@ struct Ring {
     int ea, eb;             // exponent offsets
 };
 
+template <int INX>
 __device__ inline Ring ring_init(const StartInfo &si, int q, int ntheta, bool active, bool spin)
 {
     Ring r;
     double sh, ch;
     ring_geom(active ? q : 0, ntheta, r.x, sh, ch);
     r.a0 = r.b0 = 0.0;
-    to_scaled(start_value(si.mant_p, si.ex_p, si.a_p, si.b_p, sh, ch), r.a1, r.ea);
+    to_scaled<INX>(start_value(si.mant_p, si.ex_p, si.a_p, si.b_p, sh, ch), r.a1, r.ea);
     if (spin)
-        to_scaled(start_value(si.mant_m, si.ex_m, si.a_m, si.b_m, sh, ch), r.b1, r.eb);
+        to_scaled<INX>(start_value(si.mant_m, si.ex_m, si.a_m, si.b_m, sh, ch), r.b1, r.eb);
     else {
         r.b1 = 0.0;
         r.eb = 0;
@@ -260,19 +270,30 @@ __device__ inline void ring_advance(Ring &r, double a, double b)
     }
 }
 
-template <bool SPIN>
+// A scaled channel whose true value p 2^e has reached 2^INX is folded to e = 0;
+// otherwise it is rescaled by 2^-512 once |p| reaches 2^256.
+template <int INX>
+__device__ inline void rescale_channel(double &p0, double &p1, int &e)
+{
+    if (e >= 0)
+        return;
+    if (fabs(p1) >= ldexp(1.0, INX - e)) {
+        p0 = ldexp(p0, e);
+        p1 = ldexp(p1, e);
+        e = 0;
+    } else if (fabs(p1) >= TWO_P256) {
+        p0 *= TWO_M512;
+        p1 *= TWO_M512;
+        e += 512;
+    }
+}
+
+template <bool SPIN, int INX>
 __device__ inline void ring_rescale(Ring &r)
 {
-    if (r.ea < 0 && fabs(r.a1) >= TWO_P256) {
-        r.a0 *= TWO_M512;
-        r.a1 *= TWO_M512;
-        r.ea += 512;
-    }
-    if (SPIN && r.eb < 0 && fabs(r.b1) >= TWO_P256) {
-        r.b0 *= TWO_M512;
-        r.b1 *= TWO_M512;
-        r.eb += 512;
-    }
+    rescale_channel<INX>(r.a0, r.a1, r.ea);
+    if (SPIN)
+        rescale_channel<INX>(r.b0, r.b1, r.eb);
 }
 
 // Wave-uniform slice state: 0 = no lane in range, 1 = some, 2 = all.
@@ -369,7 +390,7 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int q = chunk * 64 * R + 64 * r + lane;
-        rg[r] = ring_init(si, q, ntheta, live && q < npairs, SPIN);
+        rg[r] = ring_init<SYN_IN_EXP>(si, q, ntheta, live && q < npairs, SPIN);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             c[r][k] = 0.0;
@@ -418,7 +439,7 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
         all_in = true;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            ring_rescale<SPIN>(rg[r]);
+            ring_rescale<SPIN, SYN_IN_EXP>(rg[r]);
             all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
         }
     };
@@ -429,19 +450,35 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
         int lb = l0;
         for (; lb + LB - 1 <= lmax && !all_in; lb += LB)
             masked_block(lb, flag<false>());
-        for (; lb + LB - 1 <= lmax; lb += LB) {
-            const double2 *abl = ab + base + lb;
-            const double *ul = u + US * (base + lb);
+        // Full plain blocks, run as degree pairs whose coefficients are loaded one
+        // pair ahead, so that the scalar loads overlap the previous pair's arithmetic.
+        if (lb + LB - 1 <= lmax) {
+            const int lend = lb + ((lmax - lb + 1) / LB) * LB;
+            struct Pair {
+                double2 c0, c1;
+                double u[2 * US];
+            };
+            auto load_pair = [&](int l) {
+                Pair q;
+                q.c0 = ab[base + l];
+                q.c1 = ab[base + l + 1];
 #pragma unroll
-            for (int b = 0; b < LB; b += 2) {
-                const double2 c0 = abl[b], c1 = abl[b + 1];
+                for (int k = 0; k < 2 * US; ++k)
+                    q.u[k] = u[US * (base + l) + k];
+                return q;
+            };
+            Pair cur = load_pair(lb);
+#pragma unroll 4
+            for (; lb < lend; lb += 2) {
+                const Pair nxt = load_pair(lb + 2 < lend ? lb + 2 : lb);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, ul + US * b);
-                    ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                    synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
-                    ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                    synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, cur.u);
+                    ring_advance<SPIN>(rg[r], cur.c0.x, cur.c0.y);
+                    synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, cur.u + US);
+                    ring_advance<SPIN>(rg[r], cur.c1.x, cur.c1.y);
                 }
+                cur = nxt;
             }
         }
         if (lb <= lmax)
@@ -613,7 +650,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     for (int r = 0; r < R; ++r) {
         const int q = chunk * 64 * R + 64 * r + lane;
         const bool active = q < npairs;
-        rg[r] = ring_init(si, q, ntheta, active, SPIN);
+        rg[r] = ring_init<ADJ_IN_EXP>(si, q, ntheta, active, SPIN);
         ph[r] = slice_phase<SPIN>(rg[r]);
         double2 fpn = make_double2(0, 0), fps = fpn, fmn = fpn, fms = fpn;
         if (active) {
@@ -729,7 +766,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
         some_in = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            ring_rescale<SPIN>(rg[r]);
+            ring_rescale<SPIN, ADJ_IN_EXP>(rg[r]);
             const int p = slice_phase<SPIN>(rg[r]);
             all_in = all_in && p == 2;
             some_in = some_in || p != 0;
@@ -797,6 +834,8 @@ hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s
     case 208: adj_launch<2, 8>(p, Din, s); break;
     case 204: adj_launch<2, 4>(p, Din, s); break;
     case 404: adj_launch<4, 4>(p, Din, s); break;
+    case 308: adj_launch<3, 8>(p, Din, s); break;
+    case 408: adj_launch<4, 8>(p, Din, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

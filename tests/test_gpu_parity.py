@@ -117,6 +117,40 @@ def test_legendre_adjoint_stage_matches_oracle(G, lmax, mmax, spin, ntheta):
     assert np.all(got[:, :lmax + 1].imag == 0)
 
 
+@pytest.mark.parametrize("syn_r,adj_r,adj_b", [(1, 1, 8), (2, 2, 8), (4, 2, 4), (1, 4, 4),
+                                               (2, 3, 8), (4, 4, 8)])
+@pytest.mark.parametrize("lmax,mmax,spin,ntheta", [(300, 300, 2, 302), (200, 200, 0, 203),
+                                                   (130, 100, 2, 520)])
+def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta):
+    """Every supported launch shape (ring pairs per lane, degrees per adjoint block)
+    of both Legendre kernels against the oracle; ntheta = 520 spans several chunks
+    and a ragged last one for every shape."""
+    say("legendre shapes", syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta)
+    monkeypatch.setenv("GSHT_SYN_R", str(syn_r))
+    monkeypatch.setenv("GSHT_ADJ_R", str(adj_r))
+    monkeypatch.setenv("GSHT_ADJ_B", str(adj_b))
+    rng = np.random.default_rng(lmax + 13 * spin)
+    a = wl.gaussian_alm(lmax, mmax, spin, rng, cl=np.ones(lmax + 1))
+    ref = doubled_reference(a, lmax, mmax, spin, ntheta)
+    F = G.legendre_rings(dev(a), lmax, mmax, spin, ntheta, "f64").cpu().numpy()
+    assert rel_l2(F, ref) < 1e-12, rel_l2(F, ref)
+    # adjoint stage on the same doubled field, against the oracle after undoubling
+    ahf = G.legendre_rings_adjoint(dev(F), lmax, mmax, spin, ntheta, "f64").cpu().numpy()
+    nd = 2 * ntheta - 2
+    ms = np.arange(0, mmax + 1) if spin == 0 else np.arange(-mmax, mmax + 1)
+    sign = (-1.0) ** ((spin + ms) % 2)
+    H = F[:, :ntheta].copy()
+    for j in range(1, ntheta - 1):
+        H[:, j] += sign * F[:, nd - j]
+    Hfull = np.zeros((2 * mmax + 1, ntheta), complex)
+    if spin == 0:
+        Hfull[mmax:] = H
+    else:
+        Hfull[:] = H
+    ref_a = oracle.ring_adjoint(Hfull, lmax, mmax, spin, ring_thetas(ntheta))
+    assert rel_l2(ahf, ref_a) < 1e-12, rel_l2(ahf, ref_a)
+
+
 def make_case(kind, n, seed):
     rng = np.random.default_rng(seed)
     if kind == "uniform":
