@@ -144,6 +144,9 @@ typedef struct {
                            FFT in one kernel per column (column in LDS), 1 = doubled FFT and
                            deconvolution fused with a separate theta FFT, 0 = separate
                            library FFTs; chosen from the LDS size per workgroup */
+    int spread_colors;  /* > 0: spreading runs tile by tile in this many launches of
+                           mutually disjoint patches, flushed without atomics; 0: one
+                           workgroup per chunk with an atomic flush */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */

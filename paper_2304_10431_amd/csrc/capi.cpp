@@ -475,6 +475,11 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
             return fail(GSHT_EINVAL, "%lld point(s) have theta outside [0, pi] or non-finite phi",
                         (long long)ninv);
         }
+        e = build_tile_colors(*p, s);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return fail(GSHT_EHIP, "tile colouring failed: %s", hipGetErrorString(e));
+        }
     }
     // per-column stage, then the rocFFT plans it leaves to rocFFT
     if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
@@ -719,6 +724,7 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->nchunks = p->nchunks;
     info->workspace_bytes = p->workspace_bytes;
     info->column_mode = p->colmode;
+    info->spread_colors = p->ncolors;
     return ok();
 }
 

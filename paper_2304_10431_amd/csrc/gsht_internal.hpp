@@ -111,6 +111,10 @@ struct gsht_plan {
     int32_t *perm = nullptr;                // sorted position -> input index
     int32_t *tile_start = nullptr;          // [ntiles + 1]
     int4 *chunks = nullptr;                 // [nchunks] (tile, begin, end, 0)
+    // spreading by tile colour (0 colours = one workgroup per chunk, atomic flush)
+    int ncolors = 0;
+    int color_start[7] = {};                // items of colour c: [color_start[c], color_start[c+1])
+    int2 *tile_items = nullptr;             // (first chunk, number of chunks) per tile
     // work buffers
     void *D = nullptr;     // [ncol][nd] complex
     void *E = nullptr;     // [ncol][n1] complex
@@ -163,6 +167,7 @@ hipError_t launch_column_adj(const gsht_plan &p, hipStream_t s);  // E -> D
 // after synchronising the stream.
 hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hipStream_t s,
                        int64_t *n_invalid);
+hipError_t build_tile_colors(gsht_plan &p, hipStream_t s);  // after run_binsort
 hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s);
 hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s);
 

@@ -13,6 +13,9 @@
 // CHUNK consecutive sorted points of one tile, and stages that tile's grid patch
 // (tile plus a w - 1 halo) in LDS.  Spreading accumulates into the LDS patch with
 // fixed-point integer LDS atomics and then flushes it to the grid with global atomics.
+#include <cstdlib>
+#include <vector>
+
 #include "gsht_internal.hpp"
 
 #include <algorithm>
@@ -389,6 +392,57 @@ out:
     return e;
 }
 
+// Spreading work by tile colour: tile (tr, tc) gets colour (tr & 1) + 2 cc with
+// cc = tc & 1, except that with an odd number of tile columns the last column (a
+// neighbour of column 0 across phi = 0) gets cc = 2.  Tiles of one colour are then
+// at least two tiles apart, and with tiles at least W - 1 cells wide their patches
+// are disjoint.  Needs at least two tile columns; otherwise ncolors stays 0 and the
+// spreading flushes with atomics.  GSHT_SPREAD_COLORS=0 forces the atomic flush.
+hipError_t build_tile_colors(gsht_plan &p, hipStream_t s)
+{
+    p.ncolors = 0;
+    const char *env = getenv("GSHT_SPREAD_COLORS");
+    if ((env && atoi(env) == 0) || p.nchunks == 0 || p.nt2 < 2 || p.t1 < p.w - 1 ||
+        p.t2 < p.w - 1)
+        return hipSuccess;
+    std::vector<int4> ck((size_t)p.nchunks);
+    hipError_t e = hipMemcpyAsync(ck.data(), p.chunks, sizeof(int4) * ck.size(),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return e;
+    const int ncc = (p.nt2 % 2 == 0) ? 2 : 3;
+    const int ncol = 2 * ncc;
+    std::vector<std::vector<int2>> lists((size_t)ncol);
+    for (size_t i = 0; i < ck.size();) {
+        size_t j = i + 1;
+        while (j < ck.size() && ck[j].x == ck[i].x)
+            ++j;
+        const int t = ck[i].x, tr = t / p.nt2, tc = t - tr * p.nt2;
+        const int cc = (ncc == 3 && tc == p.nt2 - 1) ? 2 : (tc & 1);
+        lists[(size_t)((tr & 1) + 2 * cc)].push_back(make_int2((int)i, (int)(j - i)));
+        i = j;
+    }
+    std::vector<int2> items;
+    items.reserve(ck.size());
+    p.color_start[0] = 0;
+    for (int c = 0; c < ncol; ++c) {
+        items.insert(items.end(), lists[(size_t)c].begin(), lists[(size_t)c].end());
+        p.color_start[c + 1] = (int)items.size();
+    }
+    if ((e = hipMalloc(&p.tile_items, sizeof(int2) * items.size())) != hipSuccess)
+        return e;
+    p.allocations.push_back(p.tile_items);
+    if ((e = hipMemcpyAsync(p.tile_items, items.data(), sizeof(int2) * items.size(),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return e;
+    p.ncolors = ncol;
+    return hipSuccess;
+}
+
 // ---- interpolation and spreading ------------------------------------------------
 
 template <typename T> struct cpl;
@@ -508,21 +562,19 @@ template <> struct SpreadAcc<double> {
 // every contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with
 // S = sum over the chunk's points of |Re y| + |Im y|, which bounds every cell sum,
 // so the two's-complement integer adds never wrap; the quantisation step is
-// S / RANGE (2^-31 S for FP32, 2^-63 S for FP64).  Non-zero cells are flushed to the
-// grid with global atomics.
-template <typename T, int W, bool CPLX>
-__global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
-    const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
-    const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
-    T *__restrict__ grid)
+// S / RANGE (2^-31 S for FP32, 2^-63 S for FP64).  Non-zero cells are then added to
+// the grid: with global atomics (ATOMIC), or with plain read-add-write when no other
+// workgroup can touch the patch at the same time (tiles launched by colour).
+template <typename T, int W, bool CPLX, bool ATOMIC>
+__device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
+                                    const double *__restrict__ sph,
+                                    const int32_t *__restrict__ perm, const T *__restrict__ in,
+                                    const GridGeom &g, T beta, T *__restrict__ grid,
+                                    typename SpreadAcc<T>::U *patch, double *wsum)
 {
     using A = SpreadAcc<T>;
     using U = typename A::U;
-    extern __shared__ unsigned char smem_raw[];
-    U *patch = reinterpret_cast<U *>(smem_raw);  // interleaved (re, im) when CPLX
-    __shared__ double wsum[NUFFT_THREADS / 64];
     constexpr int NC = CPLX ? 2 : 1;
-    const int4 ck = chunks[blockIdx.x];
     const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
     const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
@@ -547,6 +599,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
 #pragma unroll
     for (int w = 0; w < NUFFT_THREADS / 64; ++w)
         S += wsum[w];
+    __syncthreads();  // wsum is reused by the next chunk of the same workgroup
     if (!(S > 0.0) || !isfinite(S))
         return;  // nothing (finite) to spread; uniform over the block
     const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
@@ -592,14 +645,58 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
         const typename A::S qr = (typename A::S)patch[idx * NC];
-        if (qr != 0)
-            unsafeAtomicAdd(dst, (T)((double)qr * inv));
-        if constexpr (CPLX) {
-            const typename A::S qi = (typename A::S)patch[idx * NC + 1];
-            if (qi != 0)
+        const typename A::S qi = CPLX ? (typename A::S)patch[idx * NC + 1] : 0;
+        if (ATOMIC) {
+            if (qr != 0)
+                unsafeAtomicAdd(dst, (T)((double)qr * inv));
+            if (CPLX && qi != 0)
                 unsafeAtomicAdd(dst + 1, (T)((double)qi * inv));
+        } else if (qr != 0 || qi != 0) {
+            if constexpr (CPLX) {
+                using C2 = typename cpl<T>::type;
+                C2 v = *reinterpret_cast<C2 *>(dst);
+                v.x += (T)((double)qr * inv);
+                v.y += (T)((double)qi * inv);
+                *reinterpret_cast<C2 *>(dst) = v;
+            } else {
+                *dst += (T)((double)qr * inv);
+            }
         }
     }
+    __syncthreads();  // the patch is reused by the next chunk of the same workgroup
+}
+
+// One workgroup per chunk, atomic flush (any grid).
+template <typename T, int W, bool CPLX>
+__global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
+    const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
+    const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
+    T *__restrict__ grid)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double wsum[NUFFT_THREADS / 64];
+    spread_chunk<T, W, CPLX, true>(chunks[blockIdx.x], sth, sph, perm, in, g, beta, grid,
+                                   reinterpret_cast<typename SpreadAcc<T>::U *>(smem_raw), wsum);
+}
+
+// One workgroup per tile of one colour (all of the tile's chunks in turn), plain
+// read-add-write flush: tiles of one colour are at least two tiles apart in both
+// directions and a patch reaches only W - 1 cells beyond its tile, so their
+// patches are disjoint.  items[i] = (first chunk, number of chunks).
+template <typename T, int W, bool CPLX>
+__global__ __launch_bounds__(NUFFT_THREADS) void spread_tile_kernel(
+    const int2 *__restrict__ items, const int4 *__restrict__ chunks,
+    const double *__restrict__ sth, const double *__restrict__ sph,
+    const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
+    T *__restrict__ grid)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double wsum[NUFFT_THREADS / 64];
+    const int2 it = items[blockIdx.x];
+    for (int c = 0; c < it.y; ++c)
+        spread_chunk<T, W, CPLX, false>(chunks[it.x + c], sth, sph, perm, in, g, beta, grid,
+                                        reinterpret_cast<typename SpreadAcc<T>::U *>(smem_raw),
+                                        wsum);
 }
 
 static GridGeom make_geom(const gsht_plan &p)
@@ -643,6 +740,24 @@ static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
     const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    if (p.ncolors > 0) {
+        const size_t sm = (size_t)PR * PC * (p.spin ? 2 : 1) * sizeof(typename SpreadAcc<T>::U);
+        for (int c = 0; c < p.ncolors; ++c) {
+            const int n = p.color_start[c + 1] - p.color_start[c];
+            if (n == 0)
+                continue;
+            const int2 *items = p.tile_items + p.color_start[c];
+            if (p.spin)
+                hipLaunchKernelGGL((spread_tile_kernel<T, W, true>), dim3((unsigned)n),
+                                   dim3(NUFFT_THREADS), sm, s, items, p.chunks, p.sth, p.sph,
+                                   p.perm, (const T *)map, g, (T)p.beta, (T *)p.G);
+            else
+                hipLaunchKernelGGL((spread_tile_kernel<T, W, false>), dim3((unsigned)n),
+                                   dim3(NUFFT_THREADS), sm, s, items, p.chunks, p.sth, p.sph,
+                                   p.perm, (const T *)map, g, (T)p.beta, (T *)p.g);
+        }
+        return hipGetLastError();
+    }
     if (p.spin) {
         const size_t sm = (size_t)PR * PC * 2 * sizeof(typename SpreadAcc<T>::U);
         hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),

@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("nrows", ctypes.c_int), ("a_min", ctypes.c_int),
                 ("tile1", ctypes.c_int), ("tile2", ctypes.c_int), ("ntile1", ctypes.c_int),
                 ("ntile2", ctypes.c_int), ("nchunks", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("column_mode", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_int64), ("column_mode", ctypes.c_int),
+                ("spread_colors", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

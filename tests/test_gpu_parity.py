@@ -319,3 +319,34 @@ def test_column_stage_modes_agree(G, monkeypatch, lmax, spin, prec, eps):
     for mode in (1, 2):
         assert rel_l2(outs[mode][0], outs[0][0]) <= tol
         assert rel_l2(outs[mode][1] * w, outs[0][1] * w) <= tol
+
+
+@pytest.mark.parametrize("lmax,mmax,spin,npts,prec,eps,colors", [
+    (127, 127, 2, 30000, "f64", 1e-10, 4),   # even number of tile columns
+    (40, 23, 2, 20000, "f64", 1e-10, 6),     # n2 = 96: three tile columns (odd)
+    (30, 30, 0, 60000, "f64", 1e-9, 4),      # thousands of points per tile: many chunks
+    (60, 60, 2, 40000, "f32", 1e-5, 4),
+])
+def test_spreading_by_tile_colour(G, monkeypatch, lmax, mmax, spin, npts, prec, eps, colors):
+    """Adjoint with the colour-ordered, atomic-free spreading flush against the
+    per-chunk atomic flush and against the oracle."""
+    say("spread colours", lmax, mmax, spin, npts, prec)
+    rng = np.random.default_rng(900 + lmax)
+    th, ph = wl.uniform_sphere(npts, rng)
+    y = rng.standard_normal((oracle.ncomp(spin), npts))
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    outs = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("GSHT_SPREAD_COLORS", raising=False)
+        else:
+            monkeypatch.setenv("GSHT_SPREAD_COLORS", env)
+        plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec)
+        assert plan.info()["spread_colors"] == (colors if env is None else 0)
+        outs.append(plan.adjoint(dev(y).to(rdt)).cpu().numpy().astype(np.complex128))
+        plan.close()
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert rel_l2(outs[0] * w, outs[1] * w) <= tol
+    ref = oracle.adjoint(y, lmax, mmax, spin, th, ph)
+    assert oracle.eps_eff(outs[0] * w, ref * w) <= eps
