@@ -279,14 +279,15 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         return rc;
     // Launch shapes of the Legendre kernels; GSHT_SYN_R, GSHT_ADJ_R and GSHT_ADJ_B
     // override the defaults for tuning (synthesis R in {1, 2, 4}; adjoint (R, B) in
-    // {(1,8), (2,8), (2,4), (4,4), (3,8), (4,8)}).
+    // {(1,8), (2,8), (2,4), (4,4), (3,8), (3,4), (4,8)}).
     {
         const char *sr = getenv("GSHT_SYN_R"), *ar = getenv("GSHT_ADJ_R"), *ab = getenv("GSHT_ADJ_B");
         const int r1 = sr ? atoi(sr) : p->syn_r;
         const int r2 = ar ? atoi(ar) : p->adj_r, b = ab ? atoi(ab) : p->adj_b;
         const int key = 100 * r2 + b;
         if ((r1 != 1 && r1 != 2 && r1 != 4) ||
-            (key != 108 && key != 208 && key != 204 && key != 404 && key != 308 && key != 408))
+            (key != 108 && key != 208 && key != 204 && key != 404 && key != 308 && key != 408 &&
+             key != 304))
             return fail(GSHT_EINVAL, "unsupported Legendre launch shape syn_r=%d adj_r=%d adj_b=%d",
                         r1, r2, b);
         p->syn_r = r1;
@@ -349,9 +350,10 @@ bool col_radices(int n, std::vector<int> &rad)
     return true;
 }
 
-// Twiddle table w_n^k = exp(-2 pi i k / n) and the position of every frequency after
-// the decimation-in-frequency passes (frequency k = q0 + r0 (q1 + r1 (q2 + ...)) sits
-// at sum_i q_i s_i, s_i = n / (r0 ... ri)).
+// Per-pass twiddle tables w_L^(q j) (computed in long double, stored in the plan's
+// precision) and the position of every frequency after the decimation-in-frequency
+// passes (frequency k = q0 + r0 (q1 + r1 (q2 + ...)) sits at sum_i q_i s_i,
+// s_i = n / (r0 ... ri)).
 int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
 {
     std::vector<int> rad;
@@ -359,15 +361,22 @@ int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
         return fail(GSHT_EINVAL, "length %d cannot run as an in-LDS transform", n);
     f.n = n;
     f.npass = (int)rad.size();
-    for (int i = 0; i < f.npass; ++i)
-        f.radix[i] = rad[i];
-    std::vector<double2> tw((size_t)n);
-    std::vector<int32_t> perm((size_t)n);
     const long double twopi = 6.283185307179586476925286766559005768L;
-    for (int k = 0; k < n; ++k) {
-        const long double ang = twopi * (long double)k / (long double)n;
-        tw[(size_t)k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+    std::vector<long double> re, im;
+    int L = n;
+    for (int i = 0; i < f.npass; ++i) {
+        const int r = rad[i], st = L / r;
+        f.radix[i] = r;
+        f.twoff[i] = (int)re.size();
+        for (int j = 0; j < st; ++j)
+            for (int q = 1; q < r; ++q) {
+                const long double ang = twopi * (long double)(q * j) / (long double)L;
+                re.push_back(cosl(ang));
+                im.push_back(-sinl(ang));
+            }
+        L = st;
     }
+    std::vector<int32_t> perm((size_t)n);
     for (int k = 0; k < n; ++k) {
         long rest = k, stride = n, pos = 0;
         for (int i = 0; i < f.npass; ++i) {
@@ -377,12 +386,26 @@ int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
         }
         perm[(size_t)k] = (int32_t)pos;
     }
+    const size_t nt = std::max<size_t>(re.size(), 1);
     int rc;
-    double2 *dtw = nullptr;
+    void *dtw = nullptr;
     int32_t *dperm = nullptr;
-    if ((rc = dev_alloc(p, &dtw, sizeof(double2) * (size_t)n)) != GSHT_OK) return rc;
+    if (p->prec == GSHT_F64) {
+        std::vector<double2> t(nt);
+        for (size_t i = 0; i < re.size(); ++i)
+            t[i] = make_double2((double)re[i], (double)im[i]);
+        if ((rc = dev_alloc(p, &dtw, sizeof(double2) * nt)) != GSHT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(dtw, t.data(), sizeof(double2) * nt, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        std::vector<float2> t(nt);
+        for (size_t i = 0; i < re.size(); ++i)
+            t[i] = make_float2((float)re[i], (float)im[i]);
+        if ((rc = dev_alloc(p, &dtw, sizeof(float2) * nt)) != GSHT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(dtw, t.data(), sizeof(float2) * nt, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if ((rc = dev_alloc(p, &dperm, sizeof(int32_t) * (size_t)n)) != GSHT_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(dtw, tw.data(), sizeof(double2) * (size_t)n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     f.tw = dtw;
@@ -399,14 +422,17 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t lim = std::min((size_t)maxsh, COL_MAX_BYTES), cs = csize(p->prec);
     std::vector<int> rad;
+    const int nh = p->n1 / 2;
     const bool fit_d = (size_t)p->nd * cs <= lim && col_radices(p->nd, rad);
-    const bool fit_1 = fit_d && (size_t)p->n1 * cs <= lim && p->n1 <= COL_MAX_N &&
-                       col_radices(p->n1, rad);
-    int mode = fit_1 ? 2 : fit_d ? 1 : 0;
+    const int novl = std::max(0, 2 * p->lmax - nh + 1);  // fold overlap kept in LDS
+    const bool fit_2 = fit_d && p->n1 % 2 == 0 && nh > p->lmax &&
+                       (size_t)(std::max(p->nd, nh) + novl) * cs <= lim &&
+                       std::max(p->nd, nh) <= column_half_maxn(p->prec) && col_radices(nh, rad);
+    int mode = fit_2 ? 2 : fit_d ? 1 : 0;
     const char *e = getenv("GSHT_COLUMN_MODE");
     if (e) {
         const int want = atoi(e);
-        if (want < 0 || want > 2 || (want == 2 && !fit_1) || (want == 1 && !fit_d))
+        if (want < 0 || want > 2 || (want == 2 && !fit_2) || (want == 1 && !fit_d))
             return fail(GSHT_EINVAL, "GSHT_COLUMN_MODE=%s is not possible for this plan", e);
         mode = want;
     }
@@ -423,7 +449,31 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     p->colmode = mode;
     int rc;
     if (mode >= 1 && (rc = setup_colfft(p, p->cf_d, p->nd, s)) != GSHT_OK) return rc;
-    if (mode == 2 && (rc = setup_colfft(p, p->cf_1, p->n1, s)) != GSHT_OK) return rc;
+    if (mode == 2) {
+        if ((rc = setup_colfft(p, p->cf_h, nh, s)) != GSHT_OK) return rc;
+        // twist factors exp(-2 pi i k / n1) between the even and odd output rows
+        const long double twopi = 6.283185307179586476925286766559005768L;
+        const size_t n1 = (size_t)p->n1;
+        if (p->prec == GSHT_F64) {
+            std::vector<double2> t(n1);
+            for (size_t k = 0; k < n1; ++k) {
+                const long double ang = twopi * (long double)k / (long double)n1;
+                t[k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+            }
+            if ((rc = dev_alloc(p, &p->twist, sizeof(double2) * n1)) != GSHT_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(p->twist, t.data(), sizeof(double2) * n1, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        } else {
+            std::vector<float2> t(n1);
+            for (size_t k = 0; k < n1; ++k) {
+                const long double ang = twopi * (long double)k / (long double)n1;
+                t[k] = make_float2((float)cosl(ang), (float)-sinl(ang));
+            }
+            if ((rc = dev_alloc(p, &p->twist, sizeof(float2) * n1)) != GSHT_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(p->twist, t.data(), sizeof(float2) * n1, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
     return GSHT_OK;
 }
 

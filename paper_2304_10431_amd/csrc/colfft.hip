@@ -17,8 +17,8 @@
 // 16, 8, 4, 2, 3, 5, 7): pass i splits sub-transforms of length L into radix r_i
 // butterflies of stride s = L / r_i, each followed by the twiddles w_L^(q j).  The
 // result sits in digit-reversed order; a host-built table gives the LDS position of
-// every frequency.  Twiddles come from an FP64 table of w_n^k (one read per
-// butterfly) and FP64 powers of it.
+// every frequency.  Twiddles come from per-pass tables in the working precision,
+// read contiguously per butterfly.
 #include <algorithm>
 
 #include "gsht_internal.hpp"
@@ -33,12 +33,24 @@ template <typename T> struct cx;
 template <> struct cx<float> { using type = float2; };
 template <> struct cx<double> { using type = double2; };
 
-// Values per thread when a whole column (at most COL_MAX_BYTES) is staged in
-// registers between reading and overwriting the LDS buffer.
+// Mode 2 (split theta transform): threads per workgroup and the largest nd or
+// n1 / 2 it takes; each thread stages up to col_half_maxn / 512 values in
+// registers.  FP32: two workgroups (2 x 66 KB of LDS at lmax 4096) share a CU within
+// 128 VGPRs.  FP64: one workgroup per CU (132 KB), up to 256 VGPRs.
 template <typename T>
-constexpr int col_maxv()
+constexpr int col_half_threads()
 {
-    return (int)(COL_MAX_BYTES / sizeof(typename cx<T>::type)) / COL_THREADS;
+    return 512;
+}
+template <typename T>
+constexpr int col_half_waves()  // waves per SIMD to fit: two workgroups per CU for FP32
+{
+    return sizeof(T) == 4 ? 4 : 2;
+}
+template <typename T>
+constexpr int col_half_maxn()
+{
+    return sizeof(T) == 4 ? 17 * 512 : 20 * 512;
 }
 
 template <typename C>
@@ -183,15 +195,17 @@ __device__ inline void dft(C (&v)[R])
         dft_odd<C, R, DIR>(v);
 }
 
-// One decimation-in-frequency pass: butterflies b < n / R over sub-transforms of
-// length L = R s; butterfly (sub, j) reads positions sub L + j + t s, t < R.
-template <typename C, int R, int DIR>
-__device__ inline void dif_pass(C *X, const double2 *__restrict__ tw, int n, int s)
+// One decimation-in-frequency pass over NT threads: butterflies b < n / R over
+// sub-transforms of length L = R s; butterfly (sub, j) reads positions
+// sub L + j + t s, t < R, and its twiddles w_L^(q j) from tw[j (R - 1) + q - 1]
+// (conjugated for DIR > 0).
+template <typename C, int R, int DIR, int NT>
+__device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s)
 {
-    using T = decltype(X[0].x);
-    const int L = R * s, tstep = n / L, nb = n / R;
-    for (int b = threadIdx.x; b < nb; b += COL_THREADS) {
-        const int sub = b / s, j = b - sub * s;
+    const int L = R * s, nb = n / R;
+    const double rs = 1.0 / (double)s;  // b / s by an FP64 product: exact for b < 2^26
+    for (int b = threadIdx.x; b < nb; b += NT) {
+        const int sub = (int)(((double)b + 0.5) * rs), j = b - sub * s;
         const int base = sub * L + j;
         C v[R];
 #pragma unroll
@@ -199,20 +213,15 @@ __device__ inline void dif_pass(C *X, const double2 *__restrict__ tw, int n, int
             v[t] = X[base + t * s];
         dft<C, R, DIR>(v);
         if (j != 0) {
-            // w_L^(DIR q j) = (w_n^(tstep j))^q, powers formed in FP64
-            double2 w1 = tw[tstep * j];
-            if (DIR > 0)
-                w1.y = -w1.y;
-            double2 w = w1;
+            const C *wt = tw + j * (R - 1);
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                const T wr = (T)w.x, wi = (T)w.y;
+                C w = wt[q - 1];
+                if (DIR > 0)
+                    w.y = -w.y;
                 const C a = v[q];
-                v[q].x = a.x * wr - a.y * wi;
-                v[q].y = a.x * wi + a.y * wr;
-                const double xr = w.x * w1.x - w.y * w1.y;
-                w.y = w.x * w1.y + w.y * w1.x;
-                w.x = xr;
+                v[q].x = a.x * w.x - a.y * w.y;
+                v[q].y = a.x * w.y + a.y * w.x;
             }
         }
 #pragma unroll
@@ -223,21 +232,22 @@ __device__ inline void dif_pass(C *X, const double2 *__restrict__ tw, int n, int
 
 // Whole transform in LDS (the block must hold the column before the call; the
 // result is in digit-reversed order when it returns, after a barrier).
-template <typename C, int DIR>
+template <typename C, int DIR, int NT>
 __device__ void lds_fft(C *X, const ColFFT &f)
 {
     int L = f.n;
     for (int p = 0; p < f.npass; ++p) {
         const int r = f.radix[p];
         const int s = L / r;
+        const C *tw = reinterpret_cast<const C *>(f.tw) + f.twoff[p];
         switch (r) {
-        case 16: dif_pass<C, 16, DIR>(X, f.tw, f.n, s); break;
-        case 8: dif_pass<C, 8, DIR>(X, f.tw, f.n, s); break;
-        case 4: dif_pass<C, 4, DIR>(X, f.tw, f.n, s); break;
-        case 2: dif_pass<C, 2, DIR>(X, f.tw, f.n, s); break;
-        case 3: dif_pass<C, 3, DIR>(X, f.tw, f.n, s); break;
-        case 5: dif_pass<C, 5, DIR>(X, f.tw, f.n, s); break;
-        case 7: dif_pass<C, 7, DIR>(X, f.tw, f.n, s); break;
+        case 16: dif_pass<C, 16, DIR, NT>(X, tw, f.n, s); break;
+        case 8: dif_pass<C, 8, DIR, NT>(X, tw, f.n, s); break;
+        case 4: dif_pass<C, 4, DIR, NT>(X, tw, f.n, s); break;
+        case 2: dif_pass<C, 2, DIR, NT>(X, tw, f.n, s); break;
+        case 3: dif_pass<C, 3, DIR, NT>(X, tw, f.n, s); break;
+        case 5: dif_pass<C, 5, DIR, NT>(X, tw, f.n, s); break;
+        case 7: dif_pass<C, 7, DIR, NT>(X, tw, f.n, s); break;
         default: break;
         }
         L = s;
@@ -262,6 +272,33 @@ __device__ inline C scale_c(C v, double f)
     return v;
 }
 
+template <typename C>
+__device__ inline C cmul(C a, C b)
+{
+    C o;
+    o.x = a.x * b.x - a.y * b.y;
+    o.y = a.x * b.y + a.y * b.x;
+    return o;
+}
+
+template <typename C>
+__device__ inline C cmulc(C a, C b)  // a * conj(b)
+{
+    C o;
+    o.x = a.x * b.x + a.y * b.y;
+    o.y = a.y * b.x - a.x * b.y;
+    return o;
+}
+
+// LDS of mode 2: the column buffer, then the overlap differences (residues
+// nh - lmax .. lmax of the fold, present when nh <= 2 lmax).
+__host__ __device__ inline int col_half_lds_n(int nd, int nh) { return nd > nh ? nd : nh; }
+__host__ __device__ inline int col_half_ovl(int lmax, int nh)
+{
+    const int n = 2 * lmax - nh + 1;
+    return n > 0 ? n : 0;
+}
+
 struct ColArgs {
     const double *kf1, *kf2;
     int lmax, mmax, spin, nd, n1, nrows, a_min;
@@ -269,12 +306,175 @@ struct ColArgs {
 
 __device__ inline int col_m(const ColArgs &a, int col) { return a.spin ? col - a.mmax : col; }
 
-// FULL: D column -> E column (kept rows).  Otherwise D column -> zero-padded,
-// deconvolved spectrum E^ over all n1 entries (the theta transform follows).
-template <typename T, bool FULL>
+// Mode 2, D column -> E column (kept rows).  The oversampled theta transform is
+// split by output parity: with nh = n1 / 2 and the spectrum c_k, |k| <= lmax,
+//   E[2a'] = sum_k c_k e^{2 pi i k a' / nh},  E[2a' + 1] = sum_k (c_k t^k) e^{2 pi i k a' / nh},
+// t = e^{2 pi i / n1}: two length-nh transforms of the spectra folded modulo nh (at
+// most two k per residue, since nh > lmax), so the LDS buffer holds max(nd, nh)
+// values.  twist[k] = e^{-2 pi i k / n1}, k < n1.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kernel(
+    const typename cx<T>::type *__restrict__ D, typename cx<T>::type *__restrict__ E, ColArgs a,
+    ColFFT fd, ColFFT fh, const typename cx<T>::type *__restrict__ twist)
+{
+    using C = typename cx<T>::type;
+    constexpr int MAXV = col_half_maxn<T>() / NT;
+    extern __shared__ unsigned char smem_raw[];
+    C *X = reinterpret_cast<C *>(smem_raw);
+    const int col = blockIdx.x, tid = threadIdx.x, nh = fh.n;
+    const int m = col_m(a, col);
+    const double fm = a.kf2[m < 0 ? -m : m];
+    const C *dc = D + (size_t)col * a.nd;
+    C *ec = E + (size_t)col * a.n1;
+    for (int i = tid; i < a.nd; i += NT)
+        X[i] = dc[i];
+    __syncthreads();
+    lds_fft<C, -1, NT>(X, fd);
+    auto chat = [&](int k) {
+        const int ak = k < 0 ? -k : k;
+        return scale_c(X[fd.perm[k < 0 ? k + a.nd : k]], a.kf1[ak] * fm);
+    };
+    // Fold: residue i < nh receives c_i (i <= lmax) and c_{i - nh} (i >= nh - lmax).
+    // Only the even-row input ye = c_i + c_{i-nh} stays in registers: the odd-row
+    // input is t^i (c_i - c_{i-nh}) (t^{-nh} = -1), i.e. t^i (+-ye) where only one
+    // term exists; the few residues with both keep c_i - c_{i-nh} in LDS (ovl).
+    const int ov0 = nh - a.lmax;
+    C *ovl = X + col_half_lds_n(a.nd, nh);
+    C ye[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        ye[v].x = ye[v].y = 0;
+        if (i < nh) {
+            C c1, c2;
+            c1.x = c1.y = 0;
+            c2 = c1;
+            if (i <= a.lmax)
+                c1 = chat(i);
+            if (i >= ov0)
+                c2 = chat(i - nh);
+            ye[v] = cadd(c1, c2);
+            if (i >= ov0 && i <= a.lmax)
+                ovl[i - ov0] = csub(c1, c2);
+        }
+    }
+    __syncthreads();
+    // odd rows
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh) {
+            C d = ye[v];
+            if (i >= ov0 && i <= a.lmax) {
+                d = ovl[i - ov0];
+            } else if (i > a.lmax) {
+                d.x = -d.x;
+                d.y = -d.y;
+            }
+            X[i] = cmulc(d, twist[i]);
+        }
+    }
+    __syncthreads();
+    lds_fft<C, 1, NT>(X, fh);
+    for (int i = tid; i < nh; i += NT)
+        if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
+            ec[2 * i + 1] = X[fh.perm[i]];
+    __syncthreads();
+    // even rows
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh)
+            X[i] = ye[v];
+    }
+    __syncthreads();
+    lds_fft<C, 1, NT>(X, fh);
+    for (int i = tid; i < nh; i += NT)
+        if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
+            ec[2 * i] = X[fh.perm[i]];
+}
+
+// Mode 2, E column (kept rows; the rest counts as zero) -> D column: the transpose
+// of column_fwd_half_kernel (odd rows first, then even rows, each read straight
+// from E into LDS).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kernel(
+    const typename cx<T>::type *__restrict__ E, typename cx<T>::type *__restrict__ D, ColArgs a,
+    ColFFT fd, ColFFT fh, const typename cx<T>::type *__restrict__ twist)
+{
+    using C = typename cx<T>::type;
+    constexpr int MAXV = col_half_maxn<T>() / NT;
+    extern __shared__ unsigned char smem_raw[];
+    C *X = reinterpret_cast<C *>(smem_raw);
+    const int col = blockIdx.x, tid = threadIdx.x, nh = fh.n;
+    const int m = col_m(a, col);
+    const double fm = a.kf2[m < 0 ? -m : m];
+    const C *ec = E + (size_t)col * a.n1;
+    C *dc = D + (size_t)col * a.nd;
+    // theta frequency k of output i (|k| <= lmax contributes) and its residue mod nh
+    auto freq = [&](int i, int &k, int &kh) {
+        k = (i <= a.nd / 2) ? i : i - a.nd;
+        kh = k % nh;
+        if (kh < 0)
+            kh += nh;
+        return (k < 0 ? -k : k) <= a.lmax;
+    };
+    // odd rows
+    for (int i = tid; i < nh; i += NT) {
+        C v;
+        v.x = v.y = 0;
+        if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
+            v = ec[2 * i + 1];
+        X[i] = v;
+    }
+    __syncthreads();
+    lds_fft<C, -1, NT>(X, fh);
+    C acc[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        acc[v].x = acc[v].y = 0;
+        int k, kh;
+        if (i < a.nd && freq(i, k, kh))
+            acc[v] = cmul(X[fh.perm[kh]], twist[k < 0 ? k + a.n1 : k]);
+    }
+    __syncthreads();
+    // even rows
+    for (int i = tid; i < nh; i += NT) {
+        C v;
+        v.x = v.y = 0;
+        if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
+            v = ec[2 * i];
+        X[i] = v;
+    }
+    __syncthreads();
+    lds_fft<C, -1, NT>(X, fh);
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        int k, kh;
+        if (i < a.nd && freq(i, k, kh))
+            acc[v] = scale_c(cadd(acc[v], X[fh.perm[kh]]), a.kf1[k < 0 ? -k : k] * fm);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < a.nd)
+            X[i] = acc[v];
+    }
+    __syncthreads();
+    lds_fft<C, 1, NT>(X, fd);
+    for (int i = tid; i < a.nd; i += NT)
+        dc[i] = X[fd.perm[i]];
+}
+
+// Mode 1, D column -> zero-padded, deconvolved spectrum over all n1 entries (the
+// theta transform follows in the library FFT).
+template <typename T>
 __global__ __launch_bounds__(COL_THREADS) void column_fwd_kernel(
     const typename cx<T>::type *__restrict__ D, typename cx<T>::type *__restrict__ E, ColArgs a,
-    ColFFT fd, ColFFT f1)
+    ColFFT fd)
 {
     using C = typename cx<T>::type;
     extern __shared__ unsigned char smem_raw[];
@@ -287,9 +487,8 @@ __global__ __launch_bounds__(COL_THREADS) void column_fwd_kernel(
     for (int i = tid; i < a.nd; i += COL_THREADS)
         X[i] = dc[i];
     __syncthreads();
-    lds_fft<C, -1>(X, fd);
-    // deconvolution and zero padding: output i in [0, n1) <- frequency k
-    auto deconv = [&](int i) {
+    lds_fft<C, -1, COL_THREADS>(X, fd);
+    for (int i = tid; i < a.n1; i += COL_THREADS) {
         C o;
         o.x = 0;
         o.y = 0;
@@ -297,41 +496,15 @@ __global__ __launch_bounds__(COL_THREADS) void column_fwd_kernel(
         const int ak = k < 0 ? -k : k;
         if (ak <= a.lmax)
             o = scale_c(X[fd.perm[k < 0 ? k + a.nd : k]], a.kf1[ak] * fm);
-        return o;
-    };
-    if (!FULL) {
-        for (int i = tid; i < a.n1; i += COL_THREADS)
-            ec[i] = deconv(i);
-        return;
+        ec[i] = o;
     }
-    constexpr int MAXV = col_maxv<T>();
-    C y[MAXV];
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int i = tid + v * COL_THREADS;
-        if (i < a.n1)
-            y[v] = deconv(i);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int i = tid + v * COL_THREADS;
-        if (i < a.n1)
-            X[i] = y[v];
-    }
-    __syncthreads();
-    lds_fft<C, 1>(X, f1);
-    for (int i = tid; i < a.n1; i += COL_THREADS)
-        if (row_kept(i, a.n1, a.nrows, a.a_min))
-            ec[i] = X[f1.perm[i]];
 }
 
-// FULL: E column (kept rows; the rest is zero) -> D column.  Otherwise E holds
-// the theta spectrum already and only the deconvolution and nd transform run here.
-template <typename T, bool FULL>
+// Mode 1, theta spectrum E^ -> deconvolution and nd transform -> D column.
+template <typename T>
 __global__ __launch_bounds__(COL_THREADS) void column_adj_kernel(
     const typename cx<T>::type *__restrict__ E, typename cx<T>::type *__restrict__ D, ColArgs a,
-    ColFFT fd, ColFFT f1)
+    ColFFT fd)
 {
     using C = typename cx<T>::type;
     extern __shared__ unsigned char smem_raw[];
@@ -341,53 +514,18 @@ __global__ __launch_bounds__(COL_THREADS) void column_adj_kernel(
     const double fm = a.kf2[m < 0 ? -m : m];
     const C *ec = E + (size_t)col * a.n1;
     C *dc = D + (size_t)col * a.nd;
-    if (FULL) {
-        for (int i = tid; i < a.n1; i += COL_THREADS) {
-            C v;
-            v.x = 0;
-            v.y = 0;
-            if (row_kept(i, a.n1, a.nrows, a.a_min))
-                v = ec[i];
-            X[i] = v;
-        }
-        __syncthreads();
-        lds_fft<C, -1>(X, f1);
-    }
-    // deconvolution: output i in [0, nd) <- theta frequency k
-    auto deconv = [&](int i) {
+    for (int i = tid; i < a.nd; i += COL_THREADS) {
         C o;
         o.x = 0;
         o.y = 0;
         const int k = (i <= a.nd / 2) ? i : i - a.nd;
         const int ak = k < 0 ? -k : k;
-        if (ak <= a.lmax) {
-            const int ka = k < 0 ? k + a.n1 : k;
-            o = scale_c(FULL ? X[f1.perm[ka]] : ec[ka], a.kf1[ak] * fm);
-        }
-        return o;
-    };
-    if (FULL) {
-        constexpr int MAXV = col_maxv<T>();
-        C y[MAXV];
-#pragma unroll
-        for (int v = 0; v < MAXV; ++v) {
-            const int i = tid + v * COL_THREADS;
-            if (i < a.nd)
-                y[v] = deconv(i);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < MAXV; ++v) {
-            const int i = tid + v * COL_THREADS;
-            if (i < a.nd)
-                X[i] = y[v];
-        }
-    } else {
-        for (int i = tid; i < a.nd; i += COL_THREADS)
-            X[i] = deconv(i);
+        if (ak <= a.lmax)
+            o = scale_c(ec[k < 0 ? k + a.n1 : k], a.kf1[ak] * fm);
+        X[i] = o;
     }
     __syncthreads();
-    lds_fft<C, 1>(X, fd);
+    lds_fft<C, 1, COL_THREADS>(X, fd);
     for (int i = tid; i < a.nd; i += COL_THREADS)
         dc[i] = X[fd.perm[i]];
 }
@@ -410,94 +548,93 @@ ColArgs col_args(const gsht_plan &p)
 template <typename T>
 size_t col_lds(const gsht_plan &p)
 {
-    const int n = p.colmode == 2 ? std::max(p.nd, p.n1) : p.nd;
+    const int n = p.colmode == 2 ? col_half_lds_n(p.nd, p.n1 / 2) + col_half_ovl(p.lmax, p.n1 / 2)
+                                 : p.nd;
     return sizeof(typename cx<T>::type) * (size_t)n;
+}
+
+template <typename T>
+hipError_t set_lds(const gsht_plan &p)
+{
+    const int b = (int)col_lds<T>(p);
+    hipError_t e;
+    if (p.colmode == 2) {
+        e = hipFuncSetAttribute((const void *)column_fwd_half_kernel<T, col_half_threads<T>()>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)column_adj_half_kernel<T, col_half_threads<T>()>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    } else {
+        e = hipFuncSetAttribute((const void *)column_fwd_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)column_adj_kernel<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    }
+    return e;
+}
+
+template <typename T>
+void launch_fwd(const gsht_plan &p, hipStream_t s)
+{
+    using C = typename cx<T>::type;
+    const ColArgs a = col_args(p);
+    const size_t b = col_lds<T>(p);
+    if (p.colmode == 2) {
+        constexpr int NT = col_half_threads<T>();
+        hipLaunchKernelGGL((column_fwd_half_kernel<T, NT>), dim3(p.ncol), dim3(NT), b, s,
+                           (const C *)p.D, (C *)p.E, a, p.cf_d, p.cf_h, (const C *)p.twist);
+    } else {
+        hipLaunchKernelGGL((column_fwd_kernel<T>), dim3(p.ncol), dim3(COL_THREADS), b, s,
+                           (const C *)p.D, (C *)p.E, a, p.cf_d);
+    }
+}
+
+template <typename T>
+void launch_adj(const gsht_plan &p, hipStream_t s)
+{
+    using C = typename cx<T>::type;
+    const ColArgs a = col_args(p);
+    const size_t b = col_lds<T>(p);
+    if (p.colmode == 2) {
+        constexpr int NT = col_half_threads<T>();
+        hipLaunchKernelGGL((column_adj_half_kernel<T, NT>), dim3(p.ncol), dim3(NT), b, s,
+                           (const C *)p.E, (C *)p.D, a, p.cf_d, p.cf_h, (const C *)p.twist);
+    } else {
+        hipLaunchKernelGGL((column_adj_kernel<T>), dim3(p.ncol), dim3(COL_THREADS), b, s,
+                           (const C *)p.E, (C *)p.D, a, p.cf_d);
+    }
 }
 
 }  // namespace
 
 hipError_t column_set_lds(const gsht_plan &p)
 {
-    hipError_t e = hipSuccess;
-    if (p.prec == GSHT_F64) {
-        const int b = (int)col_lds<double>(p);
-        if (p.colmode == 2) {
-            e = hipFuncSetAttribute((const void *)column_fwd_kernel<double, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)column_adj_kernel<double, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
-        } else {
-            e = hipFuncSetAttribute((const void *)column_fwd_kernel<double, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)column_adj_kernel<double, false>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
-        }
-    } else {
-        const int b = (int)col_lds<float>(p);
-        if (p.colmode == 2) {
-            e = hipFuncSetAttribute((const void *)column_fwd_kernel<float, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)column_adj_kernel<float, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
-        } else {
-            e = hipFuncSetAttribute((const void *)column_fwd_kernel<float, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)column_adj_kernel<float, false>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, b);
-        }
-    }
-    return e;
+    return p.prec == GSHT_F64 ? set_lds<double>(p) : set_lds<float>(p);
+}
+
+int column_half_maxn(int prec) { return prec == GSHT_F64 ? col_half_maxn<double>() : col_half_maxn<float>(); }
+
+size_t column_lds_bytes(const gsht_plan &p)
+{
+    return p.prec == GSHT_F64 ? col_lds<double>(p) : col_lds<float>(p);
 }
 
 hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s)
 {
-    const ColArgs a = col_args(p);
-    const dim3 grd(p.ncol), blk(COL_THREADS);
-    if (p.prec == GSHT_F64) {
-        const size_t b = col_lds<double>(p);
-        if (p.colmode == 2)
-            hipLaunchKernelGGL((column_fwd_kernel<double, true>), grd, blk, b, s,
-                               (const double2 *)p.D, (double2 *)p.E, a, p.cf_d, p.cf_1);
-        else
-            hipLaunchKernelGGL((column_fwd_kernel<double, false>), grd, blk, b, s,
-                               (const double2 *)p.D, (double2 *)p.E, a, p.cf_d, p.cf_1);
-    } else {
-        const size_t b = col_lds<float>(p);
-        if (p.colmode == 2)
-            hipLaunchKernelGGL((column_fwd_kernel<float, true>), grd, blk, b, s,
-                               (const float2 *)p.D, (float2 *)p.E, a, p.cf_d, p.cf_1);
-        else
-            hipLaunchKernelGGL((column_fwd_kernel<float, false>), grd, blk, b, s,
-                               (const float2 *)p.D, (float2 *)p.E, a, p.cf_d, p.cf_1);
-    }
+    if (p.prec == GSHT_F64)
+        launch_fwd<double>(p, s);
+    else
+        launch_fwd<float>(p, s);
     return hipGetLastError();
 }
 
 hipError_t launch_column_adj(const gsht_plan &p, hipStream_t s)
 {
-    const ColArgs a = col_args(p);
-    const dim3 grd(p.ncol), blk(COL_THREADS);
-    if (p.prec == GSHT_F64) {
-        const size_t b = col_lds<double>(p);
-        if (p.colmode == 2)
-            hipLaunchKernelGGL((column_adj_kernel<double, true>), grd, blk, b, s,
-                               (const double2 *)p.E, (double2 *)p.D, a, p.cf_d, p.cf_1);
-        else
-            hipLaunchKernelGGL((column_adj_kernel<double, false>), grd, blk, b, s,
-                               (const double2 *)p.E, (double2 *)p.D, a, p.cf_d, p.cf_1);
-    } else {
-        const size_t b = col_lds<float>(p);
-        if (p.colmode == 2)
-            hipLaunchKernelGGL((column_adj_kernel<float, true>), grd, blk, b, s,
-                               (const float2 *)p.E, (float2 *)p.D, a, p.cf_d, p.cf_1);
-        else
-            hipLaunchKernelGGL((column_adj_kernel<float, false>), grd, blk, b, s,
-                               (const float2 *)p.E, (float2 *)p.D, a, p.cf_d, p.cf_1);
-    }
+    if (p.prec == GSHT_F64)
+        launch_adj<double>(p, s);
+    else
+        launch_adj<float>(p, s);
     return hipGetLastError();
 }
 

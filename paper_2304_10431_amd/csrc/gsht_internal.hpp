@@ -36,19 +36,20 @@ struct LegendreTables {
 };
 
 // One in-LDS FFT of length n (per-column stage): decimation-in-frequency passes of
-// the given radices, twiddle table tw[k] = exp(-2 pi i k / n) (FP64), and perm[k] =
-// LDS position of frequency k after the last pass (digit reversal).
+// the given radices; per pass p (sub-transform length L, stride s = L / r) the
+// twiddles w_L^(q j) = exp(-2 pi i q j / L), q = 1..r-1, j < s, stored in the
+// plan's precision at tw + twoff[p] + j (r - 1) + q - 1; perm[k] = LDS position of
+// frequency k after the last pass (digit reversal).
 constexpr int COL_MAXP = 16;
 struct ColFFT {
     int n = 0, npass = 0;
     int radix[COL_MAXP] = {};
-    const double2 *tw = nullptr;
+    int twoff[COL_MAXP] = {};
+    const void *tw = nullptr;
     const int32_t *perm = nullptr;
 };
-// Largest LDS buffer a column workgroup may use, and the resulting length limit
-// (the kernels keep up to COL_MAX_N / 1024 deconvolved values per thread).
+// Largest LDS buffer a column workgroup may use.
 constexpr size_t COL_MAX_BYTES = 163840;
-constexpr int COL_MAX_N = 20480;
 
 enum Stage {
     ST_PREP = 0,
@@ -123,9 +124,11 @@ struct gsht_plan {
     double *acc = nullptr; // adjoint accumulators [nalm][2 * ncomp]
     // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
     // transform and deconvolution in one kernel (theta transform by rocFFT),
-    // 2 = doubled transform, deconvolution and theta transform in one kernel
+    // 2 = doubled transform, deconvolution and theta transform (split into its
+    // even and odd output rows, two transforms of length n1 / 2) in one kernel
     int colmode = 0;
-    gsht::ColFFT cf_d, cf_1;  // lengths nd and n1
+    gsht::ColFFT cf_d, cf_h;  // lengths nd and n1 / 2
+    void *twist = nullptr;    // [n1] exp(-2 pi i k / n1), plan precision (mode 2)
     // FFT plans
     gsht::FFTPlan fD_fwd, fD_inv, fT_inv, fT_fwd, fP_inv, fP_fwd;
     void *fftwork = nullptr;
@@ -159,6 +162,8 @@ hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
 
 // ---- per-column FFT stage (colfft.hip) ------------------------------------
 hipError_t column_set_lds(const gsht_plan &p);                    // once per plan
+int column_half_maxn(int prec);  // largest nd or n1 / 2 of mode 2
+size_t column_lds_bytes(const gsht_plan &p);  // LDS per workgroup of the plan's mode
 hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s);  // D -> E
 hipError_t launch_column_adj(const gsht_plan &p, hipStream_t s);  // E -> D
 

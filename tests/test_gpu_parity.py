@@ -118,7 +118,7 @@ def test_legendre_adjoint_stage_matches_oracle(G, lmax, mmax, spin, ntheta):
 
 
 @pytest.mark.parametrize("syn_r,adj_r,adj_b", [(1, 1, 8), (2, 2, 8), (4, 2, 4), (1, 4, 4),
-                                               (2, 3, 8), (4, 4, 8)])
+                                               (2, 3, 8), (4, 4, 8), (2, 3, 4)])
 @pytest.mark.parametrize("lmax,mmax,spin,ntheta", [(300, 300, 2, 302), (200, 200, 0, 203),
                                                    (130, 100, 2, 520)])
 def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta):
@@ -289,10 +289,13 @@ def test_plan_reuse_and_repeatability(G):
 
 
 @pytest.mark.parametrize("lmax,spin,prec,eps", [(130, 2, "f64", 1e-11), (130, 0, "f32", 1e-5),
-                                                (269, 1, "f64", 1e-9), (47, 3, "f32", 1e-4)])
+                                                (269, 1, "f64", 1e-9), (47, 3, "f32", 1e-4),
+                                                (512, 2, "f32", 1e-5), (512, 0, "f64", 1e-10)])
 def test_column_stage_modes_agree(G, monkeypatch, lmax, spin, prec, eps):
     """The fused per-column FFT stage (modes 2 and 1) against the separate library
-    FFTs (mode 0) and against the oracle, synthesis and adjoint."""
+    FFTs (mode 0) and against the oracle, synthesis and adjoint.  lmax = 512 gives
+    n1 = 4 lmax, where the split theta transform of mode 2 folds two frequencies
+    onto one residue."""
     say("column modes", lmax, spin, prec, eps)
     rng = np.random.default_rng(400 + lmax)
     th, ph = wl.uniform_sphere(6000, rng)
