@@ -780,24 +780,32 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     int lb = l0;
     for (; lb + B - 1 <= lmax && !all_in; lb += B)
         masked_block(lb, flag<false>());
-    for (; lb + B - 1 <= lmax; lb += B) {
-        double cb[V];
+    // Plain blocks; the coefficients of each degree pair are loaded one pair ahead
+    // (across block ends too), so the scalar loads overlap the current pair's work.
+    if (lb + B - 1 <= lmax) {
+        double2 q0 = ab[base + lb], q1 = ab[base + lb + 1];
+        for (; lb + B - 1 <= lmax; lb += B) {
+            double cb[V];
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            cb[k] = 0.0;
-        const double2 *abl = ab + base + lb;
+            for (int k = 0; k < V; ++k)
+                cb[k] = 0.0;
 #pragma unroll
-        for (int b = 0; b < B; b += 2) {
-            const double2 c0 = abl[b], c1 = abl[b + 1];
+            for (int b = 0; b < B; b += 2) {
+                const int ln = lb + b + 2;                    // next pair
+                const int lc = ln + 1 <= lmax ? ln : lb + b;  // stays inside this m's table
+                const double2 n0 = ab[base + lc], n1 = ab[base + lc + 1];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
-                ring_advance<SPIN>(rg[r], c0.x, c0.y);
-                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
-                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+                for (int r = 0; r < R; ++r) {
+                    adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
+                    ring_advance<SPIN>(rg[r], q0.x, q0.y);
+                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
+                    ring_advance<SPIN>(rg[r], q1.x, q1.y);
+                }
+                q0 = n0;
+                q1 = n1;
             }
+            reduce_add(cb, lb);
         }
-        reduce_add(cb, lb);
     }
     if (lb <= lmax)
         masked_block(lb, flag<true>());
@@ -835,6 +843,7 @@ hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s
     case 204: adj_launch<2, 4>(p, Din, s); break;
     case 404: adj_launch<4, 4>(p, Din, s); break;
     case 308: adj_launch<3, 8>(p, Din, s); break;
+    case 304: adj_launch<3, 4>(p, Din, s); break;
     case 408: adj_launch<4, 8>(p, Din, s); break;
     default: return hipErrorInvalidValue;
     }
