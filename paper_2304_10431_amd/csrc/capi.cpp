@@ -344,6 +344,13 @@ bool col_radices(int n, std::vector<int> &rad)
             rad.push_back(f);
             m /= f;
         }
+    // a lone radix-2 pass does little work per LDS round trip: 16 x 2 -> 8 x 4
+    auto two = std::find(rad.begin(), rad.end(), 2);
+    auto sixteen = std::find(rad.begin(), rad.end(), 16);
+    if (two != rad.end() && sixteen != rad.end()) {
+        *sixteen = 8;
+        *two = 4;
+    }
     if (m != 1 || rad.empty() || (int)rad.size() > COL_MAXP)
         return false;
     std::sort(rad.begin(), rad.end(), [](int a, int b) { return a > b; });
