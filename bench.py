@@ -13,10 +13,12 @@ longitude-thinned Gauss-Legendre grid displaced by a 2.5 arcmin rms deflection
 field (about 4.8e7 points; the "~5e7 pixel" intermediate grid of the paper's
 Sect. 4 benchmark).  Synthetic data, generated with fixed seeds.
 
-Also reported: the dominant kernel's achieved fraction of the MI355X FP64 vector
-peak (Legendre recurrence), per-stage times from HIP events inside the library,
-and the FP64 CPU oracle timed on a bounded sample of points on the host cores
-(with the GPU result's effective accuracy on that sample).
+Also reported: synthesis and adjoint times of each form (HIP events), the dominant
+kernel's achieved fraction of the MI355X FP64 vector peak (Legendre recurrence),
+the spreading kernel's HBM fraction and LDS atomic rate, per-stage times from HIP
+events inside the library, and the FP64 CPU oracle timed on a bounded sample of
+points on the host cores, with each form's effective accuracy against it
+(synthesis on the sampled points, adjoint of an input supported on them).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -42,16 +44,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_legendre_synth_pollens_th
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_10431_amd", "csrc", "legendre_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per launch of the Legendre synthesis from the committed counter
-    runs, or None if they were taken on a different version of the kernel source."""
+    runs, or None if they were taken on another workload or on a different version
+    of the kernel source."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    if rec.get("kernel_source_sha256") != sha or rec.get("workload", "").split()[0] != workload:
         return None
     return rec.get("bytes_per_launch")
 
@@ -89,41 +92,113 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup):
         plan.adjoint(m, out=b)
     torch.cuda.synchronize()
     plan.set_profiling(True)
+    # the library launches on torch's current stream, so events recorded there
+    # bracket exactly one synthesis and one adjoint
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
+        ev[k][0].record()
         plan.synth(a, out=m)
+        ev[k][1].record()
         plan.adjoint(m, out=b)
+        ev[k][2].record()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    syn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     stages = plan.stage_times()
     plan.set_profiling(False)
     info = plan.info()
-    return plan, m, dict(s_per_step=dt, plan_s=t_plan, stages=stages, info=info)
+    return plan, m, dict(s_per_step=dt, synth_ms=syn_ms, adjoint_ms=adj_ms, plan_s=t_plan,
+                         stages=stages, info=info)
 
 
-def cpu_baseline(spec, th_h, ph_h, alm_h, m_gpu_h, nsample, eps):
+def spreading_figures(info, stages, npts, ncomp, prec):
+    """Spreading (type-1 NUFFT) throughput.  Algorithmic HBM bytes per launch:
+    per point its sorted FP64 (theta, phi) (16 B), its 4 B permutation entry and its
+    ncomp map values; per grid cell one read and one write of the grid value (complex
+    for spin > 0, real for spin 0), times the halo factor ((T + w - 1) / T)^2 of a
+    tile's patch.  LDS integer atomics: w^2 taps x ncomp per point."""
+    rs = 8 if prec == "f64" else 4
+    w, t1, t2 = info["w"], info["tile1"], info["tile2"]
+    halo = (t1 + w - 1) * (t2 + w - 1) / float(t1 * t2)
+    grid = info["nrows"] * info["n2"] * ncomp * rs
+    nbytes = npts * (16 + 4 + ncomp * rs) + 2 * grid * halo
+    ms, cnt = stages["spread"]
+    avg_s = ms / max(cnt, 1) / 1e3
+    atomics = npts * w * w * ncomp
+    return {"kernel": "spread", "bound": "hbm", "achieved": nbytes / avg_s / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / avg_s / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3,
+            "lds_atomics_per_launch": atomics, "lds_atomic_gops": atomics / avg_s / 1e9}
+
+
+def sample_points(npts, nsample, ncomp):
+    """The bounded sample the oracle is timed on: sorted random point indices and an
+    adjoint input supported on them."""
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(npts, nsample, replace=False))
+    y = np.random.default_rng(7).standard_normal((ncomp, nsample))
+    return idx, y
+
+
+def cpu_baseline(spec, th_h, ph_h, alm_h, idx, y, m_gpu_h, adj_gpu_h):
     """Oracle (FP64 direct sum, all host cores) on a bounded random sample of the
-    workload's points, scaled linearly to the full point count."""
+    workload's points, scaled linearly to the full point count.  Also returns the
+    GPU forms' effective accuracy against it: synthesis on the sampled points, and the
+    adjoint of an input supported on them (w_m-weighted over a_lm)."""
     import oracle
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
-    rng = np.random.default_rng(12345)
-    idx = np.sort(rng.choice(th_h.size, nsample, replace=False))
+    nsample = idx.size
     cores = len(os.sched_getaffinity(0))
     t0 = time.time()
     ref = oracle.synth(alm_h, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
     t_syn = time.time() - t0
-    y = np.random.default_rng(7).standard_normal((ref.shape[0], nsample))
     t0 = time.time()
-    oracle.adjoint(y, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
+    ref_adj = oracle.adjoint(y, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
     t_adj = time.time() - t0
     npts = th_h.size
     per_step = (t_syn + t_adj) * npts / nsample
-    err = {k: oracle.eps_eff(v[:, idx], ref) for k, v in m_gpu_h.items()}
+    wts = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    err = {k: {"synthesis": oracle.eps_eff(v[:, idx], ref),
+               "adjoint": oracle.eps_eff(wts * adj_gpu_h[k], wts * ref_adj)}
+           for k, v in m_gpu_h.items()}
     return dict(value=per_step, unit="s", cores=cores, kind="oracle",
                 sample="%d random points of the %d-point workload: synthesis %.1f s + adjoint "
                        "%.1f s on %d threads, scaled linearly to all points" %
                        (nsample, npts, t_syn, t_adj, cores)), err
+
+
+def cpu_nufft_baseline(spec, th_h, ph_h, alm_h, eps):
+    """The plain CPU NUFFT-based SHT (FP64, all host cores), one synthesis and one
+    adjoint at the full workload, with its own parameter choice for eps."""
+    from oracle import nufft_sht
+    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    p = nufft_sht.default_params(lmax, mmax, eps)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.time()
+    m = nufft_sht.synth(alm_h, lmax, mmax, spin, th_h, ph_h, nthreads=cores, **p)
+    t_syn = time.time() - t0
+    log("cpu nufft synthesis %.1f s" % t_syn)
+    t0 = time.time()
+    nufft_sht.adjoint(m, lmax, mmax, spin, th_h, ph_h, nthreads=cores, **p)
+    t_adj = time.time() - t0
+    log("cpu nufft adjoint %.1f s" % t_adj)
+    return dict(value=t_syn + t_adj, unit="s", cores=cores, kind="oracle (plain CPU NUFFT SHT)",
+                eps=eps, params=p,
+                sample="whole workload, one synthesis (%.1f s) + one adjoint (%.1f s), FP64"
+                       % (t_syn, t_adj))
+
+
+def point_desc(spec):
+    if spec["points"] == "thin":
+        return ("%d-ring longitude-thinned Gauss-Legendre grid, 2.5 arcmin rms deflection"
+                % spec["nring"])
+    if spec["points"] == "gl":
+        return ("%d x %d Gauss-Legendre grid, 2.5 arcmin rms deflection"
+                % (spec["nring"], spec["nphi"]))
+    return "uniform random points"
 
 
 def main():
@@ -134,6 +209,9 @@ def main():
     ap.add_argument("--workload", default="pollens_thin6144")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-nufft", action="store_true",
+                    help="also time the plain CPU NUFFT-based SHT on the whole workload "
+                         "(FP64, eps 1e-10; minutes at lmax 2048)")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (counter calibration)")
@@ -175,6 +253,12 @@ def main():
     npts = th.numel()
     log("inputs ready: %d points, %.1f s" % (npts, time.time() - t0))
 
+    ncomp = 2 if spin else 1
+    if not args.no_cpu:
+        idx, ysam = sample_points(npts, args.cpu_sample, ncomp)
+        yfull = torch.zeros((ncomp, npts), dtype=torch.float64, device="cuda")
+        yfull[:, torch.from_numpy(idx).cuda()] = torch.from_numpy(ysam).cuda()
+    adj_maps = {}
     forms = [("f32", 1e-5)]
     if not args.no_f64:
         forms += [("f64", 1e-5), ("f64", 1e-10)]
@@ -186,7 +270,11 @@ def main():
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
         maps[key] = m.detach().to(torch.float64).cpu().numpy()
-        log("%s: %.2f ms/step (plan %.2f s)" % (key, 1e3 * r["s_per_step"], r["plan_s"]))
+        if not args.no_cpu:
+            rdt = torch.float64 if prec == "f64" else torch.float32
+            adj_maps[key] = plan.adjoint(yfull.to(rdt)).to(torch.complex128).cpu().numpy()
+        log("%s: %.2f ms/step (synthesis %.2f, adjoint %.2f; plan %.2f s)" %
+            (key, 1e3 * r["s_per_step"], r["synth_ms"], r["adjoint_ms"], r["plan_s"]))
         plan.close()
         del plan, m
         torch.cuda.empty_cache()
@@ -214,21 +302,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (FFT/NUFFT), f64 Legendre",
         "data": "synthetic",
-        "config": {"workload": "%s: spin %d, lmax=mmax=%d, %d points (6144-ring thinned "
-                               "Gauss-Legendre grid, 2.5 arcmin rms deflection), FP32 eps 1e-5"
-                               % (args.workload, spin, lmax, npts),
+        "config": {"workload": "%s: spin %d, lmax=mmax=%d, %d points (%s), FP32 eps 1e-5"
+                               % (args.workload, spin, lmax, npts, point_desc(spec)),
                    "npts": npts, "lmax": lmax, "mmax": mmax, "spin": spin},
-        "forms": {k: {"s_per_step": v["s_per_step"], "plan_s": v["plan_s"],
+        "forms": {k: {"s_per_step": v["s_per_step"], "synth_ms": v["synth_ms"],
+                      "adjoint_ms": v["adjoint_ms"], "plan_s": v["plan_s"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
                       "column_mode": v["info"]["column_mode"],
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
                      "flops_per_launch": flops, "avg_launch_ms": leg_avg_s * 1e3,
                      "legendre_adj_frac": flops / adj_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
     }
+    out["spreading"] = {k: spreading_figures(v["info"], v["stages"], npts, ncomp, k[:3])
+                        for k, v in results.items()}
     if "f64_eps1e-05" in results:
         out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / head["s_per_step"]
     if "f64_eps1e-10" in results:
@@ -236,9 +326,12 @@ def main():
     if not args.no_cpu:
         th_h = th.cpu().numpy()
         ph_h = ph.cpu().numpy()
-        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, maps, args.cpu_sample, 1e-5)
+        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, idx, ysam, maps, adj_maps)
         out["cpu_baseline"] = cb
         out["eps_eff_on_sample"] = err
+    if args.cpu_nufft:
+        out["cpu_nufft_baseline"] = cpu_nufft_baseline(spec, th.cpu().numpy(), ph.cpu().numpy(),
+                                                       alm_h, 1e-10)
     print(json.dumps(out), flush=True)
 
 

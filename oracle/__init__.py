@@ -15,7 +15,11 @@ What it computes (Reinecke, Belkner & Carron 2023, Sect. 2):
   Sect. 3 and its adjoint), used as stage references.
 * ``bin_keys`` / ``binsort`` -- definition of the point-to-tile bin sort (no
   paper counterpart; an integer, bit-exact definition).
+* ``synth_deriv`` -- derivatives of the synthesis along theta and phi (for the
+  gradients with respect to positions that the lensing application of Sect. 2 needs).
 * ``eps_eff`` -- the effective relative accuracy of Sect. 4.
+* ``nufft_sht`` (submodule) -- a plain FP64 CPU implementation of the FFT/NUFFT
+  steps of Sect. 3.
 
 The C part lives in ``gsht_oracle.c`` (plain C + OpenMP) and is compiled with gcc
 on first use (or by ``build()``).
@@ -58,8 +62,13 @@ def _load():
         lib.gsht_oracle_adjoint.argtypes = [dp, i, i, i, i64, dp, dp, dp, i]
         lib.gsht_oracle_ring_synth.argtypes = [dp, i, i, i, i, dp, dp, i]
         lib.gsht_oracle_ring_adjoint.argtypes = [dp, i, i, i, i, dp, dp, i]
+        lib.gsht_oracle_synth_deriv.argtypes = [dp, i, i, i, i64, dp, dp, dp, dp, i]
+        lib.gsht_oracle_synth_deriv.restype = ctypes.c_int
+        lib.gsht_oracle_nufft_interp.argtypes = [dp, i, i, i, ctypes.c_double, i64, dp, dp, dp, i]
+        lib.gsht_oracle_nufft_spread.argtypes = [dp, i, i, i, ctypes.c_double, i64, dp, dp, dp]
         for f in (lib.gsht_oracle_slambda, lib.gsht_oracle_synth, lib.gsht_oracle_adjoint,
-                  lib.gsht_oracle_ring_synth, lib.gsht_oracle_ring_adjoint):
+                  lib.gsht_oracle_ring_synth, lib.gsht_oracle_ring_adjoint,
+                  lib.gsht_oracle_nufft_interp, lib.gsht_oracle_nufft_spread):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -120,6 +129,21 @@ def adjoint(maps, lmax: int, mmax: int, spin: int, theta, phi, nthreads: int = 0
     _check(_load().gsht_oracle_adjoint(_p(y), lmax, mmax, spin, th.size, _p(th), _p(ph),
                                        _p(out.view(np.float64)), nthreads), "adjoint")
     return out
+
+
+def synth_deriv(alm, lmax: int, mmax: int, spin: int, theta, phi, nthreads: int = 0):
+    """Derivatives of the direct-sum synthesis along theta and phi at the points:
+    (dtheta, dphi), each [ncomp][npts] float64.  d/dphi multiplies each term by i m;
+    d/dtheta uses the spin-weighted ladder relation between spins s - 1, s and s + 1."""
+    a = _as_alm(alm, lmax, mmax, spin)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    dth = np.zeros((ncomp(spin), th.size))
+    dph = np.zeros((ncomp(spin), th.size))
+    _check(_load().gsht_oracle_synth_deriv(_p(a.view(np.float64)), lmax, mmax, spin, th.size,
+                                           _p(th), _p(ph), _p(dth), _p(dph), nthreads),
+           "synth_deriv")
+    return dth, dph
 
 
 def ring_synth(alm, lmax: int, mmax: int, spin: int, theta, nthreads: int = 0) -> np.ndarray:

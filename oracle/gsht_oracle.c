@@ -572,3 +572,207 @@ int gsht_oracle_ring_adjoint(const double *H, int lmax, int mmax, int spin, int 
     }
     return status;
 }
+
+/*
+ * ---- Plain NUFFT steps of the FFT-based general SHT (Sect. 3) ----------------
+ *
+ * The grid is the whole periodic N1 x N2 torus (theta in [0, 2 pi) after the
+ * doubling, phi in [0, 2 pi)), complex, row-major g[a][b], cell sizes
+ * h1 = 2 pi / N1, h2 = 2 pi / N2.  The kernel in cell units is
+ *     psi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1))   for |t| <= w/2, else 0,
+ * the "exponential of semicircle" kernel with support w cells.  A point at
+ * (u, v) = (theta N1 / 2 pi, phi N2 / 2 pi) touches the w x w cells
+ * a = a0 .. a0 + w - 1, b = b0 .. b0 + w - 1, a0 = ceil(u - w/2),
+ * b0 = ceil(v - w/2), taken modulo N1 and N2.
+ */
+static double es_psi(double t, int w, double beta)
+{
+    double z = 2.0 * t / w;
+    if (z * z > 1.0)
+        return 0.0;
+    return exp(beta * (sqrt(1.0 - z * z) - 1.0));
+}
+
+static int64_t wrap_index(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+static int nufft_args_ok(int n1, int n2, int w, int64_t npts)
+{
+    return n1 >= w && n2 >= w && w >= 1 && w <= 32 && npts >= 0;
+}
+
+/* Type-2 step (uniform grid -> points): out_i = sum_{a,b} g[a][b] psi(u_i - a) psi(v_i - b). */
+int gsht_oracle_nufft_interp(const double *g, int n1, int n2, int w, double beta, int64_t npts,
+                             const double *theta, const double *phi, double *out, int nthreads)
+{
+    int nt = nthreads_or_default(nthreads);
+    const double c1 = (double)n1 / (2.0 * M_PI), c2 = (double)n2 / (2.0 * M_PI);
+    if (!nufft_args_ok(n1, n2, w, npts))
+        return ORACLE_EINVAL;
+#pragma omp parallel for num_threads(nt) schedule(static)
+    for (int64_t i = 0; i < npts; ++i) {
+        double u = theta[i] * c1, v = phi[i] * c2, pb[32];
+        int64_t a0 = (int64_t)ceil(u - 0.5 * w), b0 = (int64_t)ceil(v - 0.5 * w);
+        double sr = 0.0, si = 0.0;
+        for (int db = 0; db < w; ++db)
+            pb[db] = es_psi(v - (double)(b0 + db), w, beta);
+        for (int da = 0; da < w; ++da) {
+            double pa = es_psi(u - (double)(a0 + da), w, beta);
+            const double *row = g + 2 * (size_t)wrap_index(a0 + da, n1) * (size_t)n2;
+            for (int db = 0; db < w; ++db) {
+                double k = pa * pb[db];
+                const double *c = row + 2 * wrap_index(b0 + db, n2);
+                sr += c[0] * k;
+                si += c[1] * k;
+            }
+        }
+        out[2 * i] = sr;
+        out[2 * i + 1] = si;
+    }
+    return ORACLE_OK;
+}
+
+/* Type-1 step (points -> uniform grid), the exact transpose of the type-2 step:
+ * g[a][b] += y_i psi(u_i - a) psi(v_i - b).  g is accumulated, not cleared.  One
+ * thread: points are added in input order. */
+int gsht_oracle_nufft_spread(const double *y, int n1, int n2, int w, double beta, int64_t npts,
+                             const double *theta, const double *phi, double *g)
+{
+    const double c1 = (double)n1 / (2.0 * M_PI), c2 = (double)n2 / (2.0 * M_PI);
+    if (!nufft_args_ok(n1, n2, w, npts))
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < npts; ++i) {
+        double u = theta[i] * c1, v = phi[i] * c2, pb[32];
+        int64_t a0 = (int64_t)ceil(u - 0.5 * w), b0 = (int64_t)ceil(v - 0.5 * w);
+        for (int db = 0; db < w; ++db)
+            pb[db] = es_psi(v - (double)(b0 + db), w, beta);
+        for (int da = 0; da < w; ++da) {
+            double pa = es_psi(u - (double)(a0 + da), w, beta);
+            double *row = g + 2 * (size_t)wrap_index(a0 + da, n1) * (size_t)n2;
+            for (int db = 0; db < w; ++db) {
+                double k = pa * pb[db];
+                double *c = row + 2 * wrap_index(b0 + db, n2);
+                c[0] += y[2 * i] * k;
+                c[1] += y[2 * i + 1] * k;
+            }
+        }
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * Derivatives of the direct-sum synthesis with respect to the point coordinates:
+ *   d/dphi:   each term c_lm sY_lm(theta) e^{i m phi} gains the factor i m;
+ *   d/dtheta: the spin-weighted ladder relation
+ *     d/dtheta sY_lm = -(1/2) [ sqrt((l-s)(l+s+1)) (s+1)Y_lm - sqrt((l+s)(l-s+1)) (s-1)Y_lm ],
+ *   evaluated with the recurrences of spins s + 1 and s - 1.
+ * dth, dph: [ncomp][npts] real (derivatives of T, or of Q and U).  Serial over
+ * points is not needed: parallel over m with private accumulators, as the synthesis.
+ */
+int gsht_oracle_synth_deriv(const double *alm, int lmax, int mmax, int spin, int64_t npts,
+                            const double *theta, const double *phi, double *dth, double *dph,
+                            int nthreads)
+{
+    int nt = nthreads_or_default(nthreads);
+    int64_t nalm;
+    double *priv;
+    int status = ORACLE_OK;
+    if (lmax < 0 || mmax < 0 || mmax > lmax || spin < 0 || spin > lmax || npts < 0)
+        return ORACLE_EINVAL;
+    nalm = alm_count(lmax, mmax);
+    priv = (double *)calloc((size_t)nt * 4 * (size_t)(npts > 0 ? npts : 1), sizeof(double));
+    if (!priv)
+        return ORACLE_ENOMEM;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *acc = priv + (size_t)tid * 4 * (size_t)npts; /* (dtheta, dphi) complex */
+#pragma omp for schedule(dynamic, 1)
+        for (int mm = -mmax; mm <= mmax; ++mm) {
+            rec_table t0 = {0}, tp = {0}, tm = {0};
+            double *cr = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+            double *ci = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+            int ok = cr && ci && rec_table_init(&t0, lmax, mm, spin) == ORACLE_OK &&
+                     rec_table_init(&tp, lmax, mm, spin + 1) == ORACLE_OK &&
+                     rec_table_init(&tm, lmax, mm, spin - 1) == ORACLE_OK;
+            if (!ok) {
+#pragma omp atomic write
+                status = ORACLE_ENOMEM;
+            } else if (t0.l0 <= lmax) {
+                for (int l = t0.l0; l <= lmax; ++l) {
+                    if (spin == 0) {
+                        full_coef(alm, lmax, l, mm, &cr[l], &ci[l]);
+                    } else {
+                        double gr, gi, xr, xi;
+                        full_coef(alm, lmax, l, mm, &gr, &gi);
+                        full_coef(alm + 2 * nalm, lmax, l, mm, &xr, &xi);
+                        cr[l] = -(gr - xi);
+                        ci[l] = -(gi + xr);
+                    }
+                }
+                for (int64_t i = 0; i < npts; ++i) {
+                    double sr = 0.0, si = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+                    WALK_BEGIN(&t0, lmax, theta[i])
+                    if (l >= t0.l0) {
+                        sr += cr[l] * lam;
+                        si += ci[l] * lam;
+                    }
+                    WALK_END(lmax)
+                    if (tp.l0 <= lmax) {
+                        WALK_BEGIN(&tp, lmax, theta[i])
+                        if (l >= t0.l0) {
+                            double f = sqrt((double)(l - spin) * (double)(l + spin + 1)) * lam;
+                            ar += cr[l] * f;
+                            ai += ci[l] * f;
+                        }
+                        WALK_END(lmax)
+                    }
+                    if (tm.l0 <= lmax) {
+                        WALK_BEGIN(&tm, lmax, theta[i])
+                        if (l >= t0.l0) {
+                            double f = sqrt((double)(l + spin) * (double)(l - spin + 1)) * lam;
+                            br += cr[l] * f;
+                            bi += ci[l] * f;
+                        }
+                        WALK_END(lmax)
+                    }
+                    {
+                        double c = cos(mm * phi[i]), s = sin(mm * phi[i]);
+                        double tr = -0.5 * (ar - br), ti = -0.5 * (ai - bi);
+                        /* d/dphi: i m (sr + i si) */
+                        double pr = -mm * si, pi = mm * sr;
+                        acc[4 * i] += tr * c - ti * s;
+                        acc[4 * i + 1] += tr * s + ti * c;
+                        acc[4 * i + 2] += pr * c - pi * s;
+                        acc[4 * i + 3] += pr * s + pi * c;
+                    }
+                }
+            }
+            rec_table_free(&t0);
+            rec_table_free(&tp);
+            rec_table_free(&tm);
+            free(cr);
+            free(ci);
+        }
+    }
+    for (int64_t i = 0; i < npts; ++i) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < 4; ++k)
+                v[k] += priv[(size_t)t * 4 * npts + 4 * i + k];
+        dth[i] = v[0];
+        dph[i] = v[2];
+        if (spin > 0) {
+            dth[npts + i] = v[1];
+            dph[npts + i] = v[3];
+        }
+    }
+    free(priv);
+    return status;
+}

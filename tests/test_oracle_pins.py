@@ -250,3 +250,47 @@ def test_bin_sort_definition_small():
         buckets[k].append(i)
     assert perm.tolist() == [i for b in buckets for i in b]
     assert start.tolist() == list(np.cumsum([0] + [len(b) for b in buckets]))
+
+
+@pytest.mark.parametrize("spin", [0, 1, 2, 3])
+def test_synth_deriv_vs_finite_differences(spin):
+    """Oracle derivatives against Richardson-extrapolated central differences of the
+    oracle's own synthesis (lmax 12, so that the fifth derivative stays small)."""
+    lmax, mmax = 12, 9
+    rng = np.random.default_rng(60 + spin)
+    nc = oracle.ncomp(spin)
+    a = rng.standard_normal((nc, oracle.nalm(lmax, mmax))) + 1j * rng.standard_normal((nc, oracle.nalm(lmax, mmax)))
+    th = rng.uniform(0.2, math.pi - 0.2, 40)
+    ph = rng.uniform(0, 2 * math.pi, 40)
+    dth, dph = oracle.synth_deriv(a, lmax, mmax, spin, th, ph)
+
+    def fd(f, h):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    h = 1e-3
+    gt = fd(lambda e: oracle.synth(a, lmax, mmax, spin, th + e, ph), h)
+    gp = fd(lambda e: oracle.synth(a, lmax, mmax, spin, th, ph + e), h)
+    assert np.max(np.abs(dth - gt)) <= 1e-7 * np.max(np.abs(gt))
+    assert np.max(np.abs(dph - gp)) <= 1e-7 * np.max(np.abs(gp))
+
+
+def test_synth_deriv_spin0_is_spin1_synthesis():
+    """For spin 0, (d/dtheta + i / sin(theta) d/dphi) f is the spin-1 synthesis with
+    G_lm = sqrt(l (l + 1)) a_lm, C = 0, in the sign convention of eq. forwardpol."""
+    lmax = mmax = 60
+    rng = np.random.default_rng(61)
+    a = rng.standard_normal((1, oracle.nalm(lmax, mmax))) + 1j * rng.standard_normal((1, oracle.nalm(lmax, mmax)))
+    th = np.arccos(rng.uniform(-0.99, 0.99, 300))
+    ph = rng.uniform(0, 2 * math.pi, 300)
+    dth, dph = oracle.synth_deriv(a, lmax, mmax, 0, th, ph)
+    g = np.zeros((2, oracle.nalm(lmax, mmax)), complex)
+    for m in range(mmax + 1):
+        i0 = oracle.alm_index(m, m, lmax)
+        ls = np.arange(m, lmax + 1)
+        g[0, i0:i0 + ls.size] = np.sqrt(ls * (ls + 1.0)) * a[0, i0:i0 + ls.size]
+    qu = oracle.synth(g, lmax, mmax, 1, th, ph)
+    scale = np.max(np.abs(qu))
+    assert np.max(np.abs(qu[0] - dth[0])) <= 1e-12 * scale
+    assert np.max(np.abs(qu[1] - dph[0] / np.sin(th))) <= 1e-12 * scale
