@@ -120,6 +120,46 @@ int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
 /* Adjoint with a plan: map -> alm.  Does not allocate and does not synchronise. */
 int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream);
 
+/*
+ * Derivatives with respect to the point positions (Sect. 2: the lensed map is the
+ * unlensed field synthesised at deflected angles, so its dependence on the
+ * deflection goes through these derivatives).  With the plan's points:
+ *   map     [ncomp][npts] real (prec) or NULL: the synthesis itself;
+ *   dtheta  [ncomp][npts] real (prec) or NULL: d map / d theta at each point;
+ *   dphi    [ncomp][npts] real (prec) or NULL: d map / d phi at each point.
+ * At least one output must be given (else GSHT_EINVAL).  The derivatives come from
+ * the same oversampled grid as the synthesis, interpolated with the kernel's
+ * derivative; their error relative to the derivative field's norm is of the
+ * order of epsilon.  For spin s the components are Q and U in the local
+ * (theta, phi) basis, differentiated as functions of the coordinates.
+ * Does not allocate and does not synchronise.
+ */
+int gsht_plan_synth_deriv(gsht_plan *p, const void *alm, void *map, void *dtheta, void *dphi,
+                          void *hip_stream);
+
+/*
+ * Vector-Jacobian product of the synthesis map = A(alm; theta, phi), for the
+ * gradients of a real scalar loss L given gmap = dL/dmap ([ncomp][npts], prec):
+ *   galm    [ncomp][nalm] complex (prec) or NULL: dL/dRe(a) + i dL/dIm(a) for every
+ *           stored coefficient, which is w_m times the adjoint of gmap (w_0 = 1,
+ *           w_m = 2 for m > 0: a stored m > 0 coefficient also sets its -m partner);
+ *           entries that the synthesis ignores (Im a_l0, l < spin) are 0;
+ *   gtheta  [npts] FP64 or NULL: sum over components of gmap * d map / d theta;
+ *   gphi    [npts] FP64 or NULL: the same along phi.
+ * alm (the synthesis input) is needed only for gtheta/gphi; the grid is recomputed,
+ * not kept from an earlier synthesis.  Does not allocate and does not synchronise.
+ */
+int gsht_plan_synth_vjp(gsht_plan *p, const void *alm, const void *gmap, void *galm,
+                        double *gtheta, double *gphi, void *hip_stream);
+
+/*
+ * Vector-Jacobian product of the adjoint alm = A^H(map): given galm =
+ * dL/dRe(alm) + i dL/dIm(alm) ([ncomp][nalm] complex, prec), writes
+ * gmap = dL/dmap ([ncomp][npts] real, prec), which is the synthesis of galm / w_m.
+ * Does not allocate and does not synchronise.
+ */
+int gsht_plan_adjoint_vjp(gsht_plan *p, const void *galm, void *gmap, void *hip_stream);
+
 /* Release a plan and its workspace (NULL is ignored).  Synchronises the device. */
 void gsht_plan_destroy(gsht_plan *p);
 

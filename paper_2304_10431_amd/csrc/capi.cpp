@@ -630,9 +630,10 @@ int check_launch(hipError_t e, const char *what)
             return rc_;                                                                        \
     } while (0)
 
-int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s)
+// Synthesis up to the oversampled grid (G, or g for spin 0), before interpolation.
+int plan_synth_grid(gsht_plan *p, const void *alm, double mscale, hipStream_t s)
 {
-    RUN(ST_PREP, launch_prep_alm(*p, alm, s));
+    RUN(ST_PREP, launch_prep_alm(*p, alm, mscale, s));
     RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, s));
     if (p->colmode == 0) {
         RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
@@ -647,11 +648,32 @@ int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s)
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
     else
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, p->g, p->fftwork, p->fftwork_bytes, s));
+    return ok();
+}
+
+int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s, double mscale = 1.0)
+{
+    int rc = plan_synth_grid(p, alm, mscale, s);
+    if (rc != GSHT_OK)
+        return rc;
     RUN(ST_INTERP, launch_interp(*p, map, s));
     return ok();
 }
 
-int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s)
+// Synthesis with the map's derivatives along theta and phi (or, with gin, their
+// products with a map gradient summed over components).
+int plan_deriv_impl(gsht_plan *p, const void *alm, void *map, void *dth, void *dph,
+                    const void *gin, double *gth, double *gph, hipStream_t s)
+{
+    int rc = plan_synth_grid(p, alm, 1.0, s);
+    if (rc != GSHT_OK)
+        return rc;
+    RUN(ST_INTERP_DERIV, launch_interp_deriv(*p, map, dth, dph, gin, gth, gph, s));
+    return ok();
+}
+
+int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
+                      double mscale = 1.0)
 {
     const size_t cs = csize(p->prec);
     if (p->spin)
@@ -673,7 +695,7 @@ int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s)
         RUN(ST_COLUMN_ADJ, launch_column_adj(*p, s));
     }
     RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, s));
-    RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, s));
+    RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, mscale, s));
     return ok();
 }
 
@@ -681,7 +703,7 @@ const char *kStageNames[ST_COUNT] = {
     "prep_alm",     "legendre_synth", "fft_doubled_fwd", "deconv_fwd", "fft_theta_inv",
     "transpose_fwd", "fft_phi_inv",   "interp",          "zero_grid",  "spread",
     "fft_phi_fwd",  "transpose_adj",  "fft_theta_fwd",   "deconv_adj", "fft_doubled_inv",
-    "legendre_adj", "finalize",       "column_fwd",      "column_adj"};
+    "legendre_adj", "finalize",       "column_fwd",      "column_adj", "interp_deriv"};
 
 }  // namespace
 
@@ -721,6 +743,46 @@ int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream
     if (!alm || (!map && p->npts > 0))
         return fail(GSHT_EINVAL, "alm/map must not be NULL");
     return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+}
+
+int gsht_plan_synth_deriv(gsht_plan *p, const void *alm, void *map, void *dtheta, void *dphi,
+                          void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!alm)
+        return fail(GSHT_EINVAL, "alm must not be NULL");
+    if (!map && !dtheta && !dphi)
+        return fail(GSHT_EINVAL, "at least one of map/dtheta/dphi must be given");
+    return plan_deriv_impl(p, alm, map, dtheta, dphi, nullptr, nullptr, nullptr,
+                           (hipStream_t)hip_stream);
+}
+
+int gsht_plan_synth_vjp(gsht_plan *p, const void *alm, const void *gmap, void *galm,
+                        double *gtheta, double *gphi, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!gmap && p->npts > 0)
+        return fail(GSHT_EINVAL, "gmap must not be NULL");
+    if ((gtheta || gphi) && !alm)
+        return fail(GSHT_EINVAL, "alm is needed for position gradients");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = GSHT_OK;
+    if (galm && (rc = plan_adjoint_impl(p, gmap, galm, s, 2.0)) != GSHT_OK)
+        return rc;
+    if (gtheta || gphi)
+        rc = plan_deriv_impl(p, alm, nullptr, nullptr, nullptr, gmap, gtheta, gphi, s);
+    return rc;
+}
+
+int gsht_plan_adjoint_vjp(gsht_plan *p, const void *galm, void *gmap, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!galm || (!gmap && p->npts > 0))
+        return fail(GSHT_EINVAL, "galm/gmap must not be NULL");
+    return plan_synth_impl(p, galm, gmap, (hipStream_t)hip_stream, 0.5);
 }
 
 void gsht_plan_destroy(gsht_plan *p) { free_plan(p); }
@@ -869,7 +931,7 @@ int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int nthet
     p->ncol = spin ? 2 * mmax + 1 : mmax + 1;
     p->npairs = (ntheta + 1) / 2;
     if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
-    int rc2 = check_launch(launch_prep_alm(*p, alm, s), "prep_alm");
+    int rc2 = check_launch(launch_prep_alm(*p, alm, 1.0, s), "prep_alm");
     if (rc2 == GSHT_OK)
         rc2 = check_launch(launch_leg_synth(*p, F, s), "legendre_synth");
     if (rc2 == GSHT_OK)
@@ -903,7 +965,7 @@ int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int
     if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
     int rc2 = check_launch(launch_leg_adjoint(*p, F, s), "legendre_adjoint");
     if (rc2 == GSHT_OK)
-        rc2 = check_launch(launch_leg_finalize(*p, alm, s), "finalize");
+        rc2 = check_launch(launch_leg_finalize(*p, alm, 1.0, s), "finalize");
     if (rc2 == GSHT_OK)
         rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
     free_plan(p);

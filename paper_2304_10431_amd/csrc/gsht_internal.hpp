@@ -71,6 +71,7 @@ enum Stage {
     ST_FINALIZE,
     ST_COLUMN_FWD,
     ST_COLUMN_ADJ,
+    ST_INTERP_DERIV,
     ST_COUNT
 };
 
@@ -147,10 +148,12 @@ namespace gsht {
 // ---- Legendre step (legendre.hip) ------------------------------------------
 hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s);
 hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s);
-hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, hipStream_t s);
+// mscale multiplies the coefficients (prep) or results (finalize) of every m > 0:
+// 1 for the transforms, 1/2 or 2 for the weights w_m of their derivatives.
+hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, hipStream_t s);
 hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s);
-hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, hipStream_t s);
+hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, hipStream_t s);
 
 // ---- staging (staging.hip) -------------------------------------------------
 hipError_t launch_deconv_fwd(const gsht_plan &p, hipStream_t s);     // D -> E
@@ -174,6 +177,8 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
                        int64_t *n_invalid);
 hipError_t build_tile_colors(gsht_plan &p, hipStream_t s);  // after run_binsort
 hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s);
+hipError_t launch_interp_deriv(const gsht_plan &p, void *out_map, void *dth, void *dph,
+                              const void *gin, double *gth, double *gph, hipStream_t s);
 hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s);
 
 }  // namespace gsht

@@ -542,6 +542,119 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
     }
 }
 
+// Kernel weight and its derivative with respect to the point's cell coordinate at
+// z = 2 (u - a) / W:  d/du exp(beta (sqrt(1 - z^2) - 1)) = -beta z / sqrt(1 - z^2)
+// * (2 / W) times the weight (taken as 0 at |z| = 1, where the kernel's value is
+// e^-beta and its slope unbounded).
+template <typename T, int W>
+__device__ inline void es_weight_d(T z, T beta, T &wv, T &dv)
+{
+    const T q = sqrt(fmax((T)0, (T)1 - z * z));
+    wv = exp(beta * (q - (T)1));
+    dv = q > (T)0 ? -beta * z / q * (T)(2.0 / W) * wv : (T)0;
+}
+
+// Type-2 interpolation of the map's first derivatives: with the patch values G,
+//   f = sum G w_i w_j,  df/du = sum G w'_i w_j,  df/dv = sum G w_i w'_j,
+// d/dtheta = (N1 / 2 pi) d/du and d/dphi = (N2 / 2 pi) d/dv.  Without VJP the
+// derivative maps are written ([ncomp][npts], any of map / dth / dph may be null);
+// with VJP the products with the incoming map gradient gin are summed over the
+// components and written in FP64 to gth / gph ([npts], either may be null).
+template <typename T, int W, bool CPLX, bool VJP>
+__global__ __launch_bounds__(NUFFT_THREADS) void interp_deriv_kernel(
+    const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
+    const int32_t *__restrict__ perm, const void *__restrict__ gridv, GridGeom g, T beta,
+    T *__restrict__ map, T *__restrict__ dth, T *__restrict__ dph, const T *__restrict__ gin,
+    double *__restrict__ gth, double *__restrict__ gph)
+{
+    using C = typename cpl<T>::type;
+    using V = typename std::conditional<CPLX, C, T>::type;
+    constexpr int NC = CPLX ? 2 : 1;
+    extern __shared__ unsigned char smem_raw[];
+    V *patch = reinterpret_cast<V *>(smem_raw);
+    const V *grid = reinterpret_cast<const V *>(gridv);
+    const int4 ck = chunks[blockIdx.x];
+    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
+        const int pr = idx / PC, pc = idx - (idx / PC) * PC;
+        const int r = row0 + pr;
+        int c = col0 + pc;
+        if (c >= g.n2)
+            c -= g.n2;
+        V v{};
+        if (r < g.nrows)
+            v = grid[(size_t)r * g.stride + c];
+        patch[idx] = v;
+    }
+    __syncthreads();
+    const T cu = (T)g.c1, cv = (T)g.c2;
+    const T sc = (T)(2.0 / W);
+    for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
+        const Cell cell = point_cell(sth[p], sph[p], g.c1, g.c2, g.half, g.a_min, g.n2, g.nrows, W);
+        const int lr = cell.r0 - row0, lc = cell.bi - col0;
+        if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
+            continue;  // cannot happen for points sorted by the same arithmetic
+        const T fx = (T)(cell.u - cell.a0), fy = (T)(cell.v - cell.b0);  // in (w/2 - 1, w/2]
+        T wy[W], dwy[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            es_weight_d<T, W>((fy - (T)j) * sc, beta, wy[j], dwy[j]);
+        T f[NC] = {}, fu[NC] = {}, fv[NC] = {};
+#pragma unroll 1
+        for (int i = 0; i < W; ++i) {
+            T wxi, dwxi;
+            es_weight_d<T, W>((fx - (T)i) * sc, beta, wxi, dwxi);
+            const V *rowp = patch + (lr + i) * PC + lc;
+            T s0[NC] = {}, s1[NC] = {};
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if constexpr (CPLX) {
+                    const C v = rowp[j];
+                    s0[0] = fma(wy[j], v.x, s0[0]);
+                    s0[1] = fma(wy[j], v.y, s0[1]);
+                    s1[0] = fma(dwy[j], v.x, s1[0]);
+                    s1[1] = fma(dwy[j], v.y, s1[1]);
+                } else {
+                    s0[0] = fma(wy[j], rowp[j], s0[0]);
+                    s1[0] = fma(dwy[j], rowp[j], s1[0]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                f[c] = fma(wxi, s0[c], f[c]);
+                fu[c] = fma(dwxi, s0[c], fu[c]);
+                fv[c] = fma(wxi, s1[c], fv[c]);
+            }
+        }
+        const int32_t dst = perm[p];
+        if constexpr (VJP) {
+            double at = 0.0, ap = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double gc = (double)gin[c * g.npts + dst];
+                at += gc * (double)(cu * fu[c]);
+                ap += gc * (double)(cv * fv[c]);
+            }
+            if (gth)
+                gth[dst] = at;
+            if (gph)
+                gph[dst] = ap;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (map)
+                    map[c * g.npts + dst] = f[c];
+                if (dth)
+                    dth[c * g.npts + dst] = cu * fu[c];
+                if (dph)
+                    dph[c * g.npts + dst] = cv * fv[c];
+            }
+        }
+    }
+}
+
 // Fixed-point accumulator of the spreading patch: on gfx950 integer LDS atomic adds
 // run 3.6x (u32) / 2x (u64) faster than FP64 ones and 26x faster than FP32 ones.
 template <typename T> struct SpreadAcc;
@@ -735,6 +848,45 @@ static hipError_t interp_w(const gsht_plan &p, void *map, hipStream_t s)
     return hipGetLastError();
 }
 
+struct DerivOut {
+    void *map, *dth, *dph;
+    const void *gin;
+    double *gth, *gph;
+};
+
+template <typename T, int W>
+static hipError_t interp_deriv_w(const gsht_plan &p, const DerivOut &o, hipStream_t s)
+{
+    const GridGeom g = make_geom(p);
+    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    const bool vjp = o.gin != nullptr;
+    const dim3 grd((unsigned)p.nchunks), blk(NUFFT_THREADS);
+    T *map = (T *)o.map, *dth = (T *)o.dth, *dph = (T *)o.dph;
+    const T *gin = (const T *)o.gin;
+    if (p.spin) {
+        const size_t sm = (size_t)PR * PC * sizeof(typename cpl<T>::type);
+        if (vjp)
+            hipLaunchKernelGGL((interp_deriv_kernel<T, W, true, true>), grd, blk, sm, s, p.chunks,
+                               p.sth, p.sph, p.perm, p.G, g, (T)p.beta, map, dth, dph, gin, o.gth,
+                               o.gph);
+        else
+            hipLaunchKernelGGL((interp_deriv_kernel<T, W, true, false>), grd, blk, sm, s, p.chunks,
+                               p.sth, p.sph, p.perm, p.G, g, (T)p.beta, map, dth, dph, gin, o.gth,
+                               o.gph);
+    } else {
+        const size_t sm = (size_t)PR * PC * sizeof(T);
+        if (vjp)
+            hipLaunchKernelGGL((interp_deriv_kernel<T, W, false, true>), grd, blk, sm, s, p.chunks,
+                               p.sth, p.sph, p.perm, p.g, g, (T)p.beta, map, dth, dph, gin, o.gth,
+                               o.gph);
+        else
+            hipLaunchKernelGGL((interp_deriv_kernel<T, W, false, false>), grd, blk, sm, s,
+                               p.chunks, p.sth, p.sph, p.perm, p.g, g, (T)p.beta, map, dth, dph,
+                               gin, o.gth, o.gph);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int W>
 static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
 {
@@ -808,6 +960,19 @@ hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s)
         GSHT_W_CASES(interp_w, double)
     } else {
         GSHT_W_CASES_F32(interp_w)
+    }
+}
+
+hipError_t launch_interp_deriv(const gsht_plan &p, void *out_map, void *dth, void *dph,
+                              const void *gin, double *gth, double *gph, hipStream_t s)
+{
+    if (p.nchunks == 0)
+        return hipSuccess;
+    const DerivOut map{out_map, dth, dph, gin, gth, gph};  // the W switch passes "map" on
+    if (p.prec == GSHT_F64) {
+        GSHT_W_CASES(interp_deriv_w, double)
+    } else {
+        GSHT_W_CASES_F32(interp_deriv_w)
     }
 }
 

@@ -59,6 +59,9 @@ _SIGS = {
     "gsht_plan_create": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
     "gsht_plan_synth": [_vp, _vp, _vp, _vp],
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
+    "gsht_plan_synth_deriv": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "gsht_plan_synth_vjp": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "gsht_plan_adjoint_vjp": [_vp, _vp, _vp, _vp],
     "gsht_plan_get_info": [_vp, ctypes.POINTER(PlanInfo)],
     "gsht_plan_get_sort": [_vp, _vp, _vp, _vp],
     "gsht_plan_set_profiling": [_vp, _i],
@@ -193,6 +196,39 @@ class Plan:
                               device=self.device)
         _need(out, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "out")
         _check(_lib.gsht_plan_adjoint(self._h, _ptr(maps), _ptr(out), _stream()))
+        return out
+
+    def synth_deriv(self, alm, want_map=True):
+        """(map or None, d map/d theta, d map/d phi), each [ncomp][npts]."""
+        _need(alm, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "alm")
+        shape = (self.ncomp, self.npts)
+        mk = lambda: torch.empty(shape, dtype=_RDT[self.prec], device=self.device)
+        m = mk() if want_map else None
+        dth, dph = mk(), mk()
+        _check(_lib.gsht_plan_synth_deriv(self._h, _ptr(alm), _ptr(m), _ptr(dth), _ptr(dph),
+                                          _stream()))
+        return m, dth, dph
+
+    def synth_vjp(self, alm, gmap, want_alm=True, want_theta=True, want_phi=True):
+        """Gradients (galm, gtheta, gphi) of a real loss with dL/dmap = gmap; entries not
+        asked for are None."""
+        _need(gmap, _RDT[self.prec], (self.ncomp, self.npts), "gmap")
+        if want_theta or want_phi:
+            _need(alm, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "alm")
+        galm = (torch.empty((self.ncomp, nalm(self.lmax, self.mmax)), dtype=_CDT[self.prec],
+                            device=self.device) if want_alm else None)
+        gth = torch.empty(self.npts, dtype=torch.float64, device=self.device) if want_theta else None
+        gph = torch.empty(self.npts, dtype=torch.float64, device=self.device) if want_phi else None
+        if want_alm or want_theta or want_phi:
+            _check(_lib.gsht_plan_synth_vjp(self._h, _ptr(alm), _ptr(gmap), _ptr(galm), _ptr(gth),
+                                            _ptr(gph), _stream()))
+        return galm, gth, gph
+
+    def adjoint_vjp(self, galm):
+        """dL/dmap of a real loss of the adjoint's output, given galm = dL/dalm."""
+        _need(galm, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "galm")
+        out = torch.empty((self.ncomp, self.npts), dtype=_RDT[self.prec], device=self.device)
+        _check(_lib.gsht_plan_adjoint_vjp(self._h, _ptr(galm), _ptr(out), _stream()))
         return out
 
     def sort(self):
