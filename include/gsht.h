@@ -160,6 +160,56 @@ int gsht_plan_synth_vjp(gsht_plan *p, const void *alm, const void *gmap, void *g
  */
 int gsht_plan_adjoint_vjp(gsht_plan *p, const void *galm, void *gmap, void *hip_stream);
 
+/*
+ * Lensing geometry (Sect. 2; the deflected-angle formula at the end of Sect. 3).
+ *
+ * gsht_deflect: for each point n = (theta, phi) and deflection alpha =
+ * alpha_theta e_theta + alpha_phi e_phi (|alpha| = a), the point
+ *   n' = cos(a) n + (sin(a)/a) (alpha_theta e_theta + alpha_phi e_phi)
+ * at distance a along the great circle, and the spin phase chi: the angle by which
+ * the basis (e_theta, e_phi) parallel-transported from n to n' along that circle
+ * differs from the local basis at n' (chi = beta - beta', the angles the circle
+ * makes with e_theta at its ends), so that a spin-s field lenses as
+ * sT_len(n) = e^{i s chi} sT_unl(n').
+ *   theta, phi   [npts] FP64 device, the undeflected points;
+ *   alpha        [2][npts] real (prec): alpha_theta then alpha_phi, as written by a
+ *                spin-1 synthesis (Q, U) of sqrt(L(L+1)) (phi_LM + i Omega_LM);
+ *   theta_out, phi_out [npts] FP64 out: n' (phi' wrapped to [0, 2 pi));
+ *   chi_out      [npts] FP64 out or NULL.
+ * Elementwise, stream-ordered; all arithmetic in FP64.
+ */
+int gsht_deflect(const double *theta, const double *phi, const void *alpha, gsht_precision prec,
+                 int64_t npts, double *theta_out, double *phi_out, double *chi_out,
+                 void *hip_stream);
+
+/* Vector-Jacobian product of gsht_deflect: given the gradients of a real loss with
+ * respect to theta', phi' and chi (FP64 [npts] each, any may be NULL = zero),
+ * writes g_alpha [2][npts] (prec), the gradient with respect to (alpha_theta,
+ * alpha_phi), from the exact derivatives of the formula above. */
+int gsht_deflect_vjp(const double *theta, const void *alpha, gsht_precision prec, int64_t npts,
+                     const double *g_theta, const double *g_phi, const double *g_chi,
+                     void *g_alpha, void *hip_stream);
+
+/* In place: (Q + iU) <- e^{i sign spin chi} (Q + iU) for map [2][npts] (prec) and
+ * chi [npts] FP64; sign is +1 (lensing) or -1 (its adjoint). */
+int gsht_spin_phase(void *map, const double *chi, int spin, int sign, gsht_precision prec,
+                    int64_t npts, void *hip_stream);
+
+/* Vector-Jacobian product of M = e^{i spin chi} P: given gmap = dL/dM [2][npts]
+ * (prec) and the lensed map M (needed only for g_chi), writes
+ * g_unrot = dL/dP = e^{-i spin chi} gmap ([2][npts], prec, or NULL) and
+ * g_chi = spin (gU MQ - gQ MU) ([npts] FP64, or NULL). */
+int gsht_spin_phase_vjp(const void *gmap, const void *lensed, const double *chi, int spin,
+                        gsht_precision prec, int64_t npts, void *g_unrot, double *g_chi,
+                        void *hip_stream);
+
+/* alm_out = sqrt(l (l + 1)) alm_in for ncomp coefficient blocks ([ncomp][nalm]
+ * complex, prec; in place allowed): the lensing potential's coefficients become the
+ * gradient-mode coefficients of the spin-1 deflection field (eq. deflect). The
+ * factor is real, so the same call maps a coefficient gradient back. */
+int gsht_alm_lscale(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp,
+                    gsht_precision prec, void *hip_stream);
+
 /* Release a plan and its workspace (NULL is ignored).  Synchronises the device. */
 void gsht_plan_destroy(gsht_plan *p);
 

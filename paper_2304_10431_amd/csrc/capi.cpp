@@ -787,6 +787,80 @@ int gsht_plan_adjoint_vjp(gsht_plan *p, const void *galm, void *gmap, void *hip_
 
 void gsht_plan_destroy(gsht_plan *p) { free_plan(p); }
 
+int gsht_deflect(const double *theta, const double *phi, const void *alpha, gsht_precision prec,
+                 int64_t npts, double *theta_out, double *phi_out, double *chi_out,
+                 void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0)
+        return fail(GSHT_EINVAL, "npts must be >= 0");
+    if (npts > 0 && (!theta || !phi || !alpha || !theta_out || !phi_out))
+        return fail(GSHT_EINVAL, "theta/phi/alpha/theta_out/phi_out must not be NULL");
+    return check_launch(launch_deflect(theta, phi, alpha, prec, npts, theta_out, phi_out, chi_out,
+                                       (hipStream_t)hip_stream),
+                        "deflect");
+}
+
+int gsht_deflect_vjp(const double *theta, const void *alpha, gsht_precision prec, int64_t npts,
+                     const double *g_theta, const double *g_phi, const double *g_chi,
+                     void *g_alpha, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0)
+        return fail(GSHT_EINVAL, "npts must be >= 0");
+    if (npts > 0 && (!theta || !alpha || !g_alpha))
+        return fail(GSHT_EINVAL, "theta/alpha/g_alpha must not be NULL");
+    return check_launch(launch_deflect_vjp(theta, alpha, prec, npts, g_theta, g_phi, g_chi, g_alpha,
+                                           (hipStream_t)hip_stream),
+                        "deflect_vjp");
+}
+
+int gsht_spin_phase(void *map, const double *chi, int spin, int sign, gsht_precision prec,
+                    int64_t npts, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0 || (sign != 1 && sign != -1))
+        return fail(GSHT_EINVAL, "npts must be >= 0 and sign +1 or -1");
+    if (npts > 0 && (!map || !chi))
+        return fail(GSHT_EINVAL, "map/chi must not be NULL");
+    return check_launch(launch_spin_phase(map, chi, spin, sign, prec, npts,
+                                          (hipStream_t)hip_stream),
+                        "spin_phase");
+}
+
+int gsht_spin_phase_vjp(const void *gmap, const void *lensed, const double *chi, int spin,
+                        gsht_precision prec, int64_t npts, void *g_unrot, double *g_chi,
+                        void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0)
+        return fail(GSHT_EINVAL, "npts must be >= 0");
+    if (npts > 0 && (!gmap || !chi || (g_chi && !lensed) || (!g_unrot && !g_chi)))
+        return fail(GSHT_EINVAL, "gmap/chi (and lensed for g_chi) must not be NULL; "
+                                 "at least one output");
+    return check_launch(launch_spin_phase_vjp(gmap, lensed, chi, spin, prec, npts, g_unrot, g_chi,
+                                              (hipStream_t)hip_stream),
+                        "spin_phase_vjp");
+}
+
+int gsht_alm_lscale(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp,
+                    gsht_precision prec, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (lmax < 0 || mmax < 0 || mmax > lmax || lmax > 32766 || ncomp < 1 || ncomp > 2)
+        return fail(GSHT_EINVAL, "need 0 <= mmax <= lmax <= 32766 and ncomp in {1, 2}");
+    if (!alm_in || !alm_out)
+        return fail(GSHT_EINVAL, "alm_in/alm_out must not be NULL");
+    return check_launch(launch_alm_lscale(alm_in, lmax, mmax, ncomp, prec, alm_out,
+                                          (hipStream_t)hip_stream),
+                        "alm_lscale");
+}
+
 int gsht_synth_general(const void *alm, int lmax, int mmax, int spin, const double *theta,
                        const double *phi, int64_t npts, double epsilon, gsht_precision prec,
                        void *map, void *hip_stream)

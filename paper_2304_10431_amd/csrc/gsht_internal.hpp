@@ -177,6 +177,21 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
                        int64_t *n_invalid);
 hipError_t build_tile_colors(gsht_plan &p, hipStream_t s);  // after run_binsort
 hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s);
+
+// ---- lensing geometry (lensing.hip) ------------------------------------------
+hipError_t launch_deflect(const double *theta, const double *phi, const void *alpha, int prec,
+                          int64_t npts, double *theta_out, double *phi_out, double *chi_out,
+                          hipStream_t s);
+hipError_t launch_deflect_vjp(const double *theta, const void *alpha, int prec, int64_t npts,
+                              const double *g_theta, const double *g_phi, const double *g_chi,
+                              void *g_alpha, hipStream_t s);
+hipError_t launch_spin_phase(void *map, const double *chi, int spin, int sign, int prec,
+                             int64_t npts, hipStream_t s);
+hipError_t launch_spin_phase_vjp(const void *g, const void *lensed, const double *chi, int spin,
+                                 int prec, int64_t npts, void *g_unrot, double *g_chi,
+                                 hipStream_t s);
+hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int prec, void *out,
+                             hipStream_t s);
 hipError_t launch_interp_deriv(const gsht_plan &p, void *out_map, void *dth, void *dph,
                               const void *gin, double *gth, double *gph, hipStream_t s);
 hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s);

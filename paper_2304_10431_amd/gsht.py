@@ -68,6 +68,11 @@ _SIGS = {
     "gsht_plan_get_stage_times": [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i],
     "gsht_legendre_rings": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
     "gsht_legendre_rings_adjoint": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
+    "gsht_deflect": [_vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
+    "gsht_deflect_vjp": [_vp, _vp, _i, _i64, _vp, _vp, _vp, _vp, _vp],
+    "gsht_spin_phase": [_vp, _vp, _i, _i, _i, _i64, _vp],
+    "gsht_spin_phase_vjp": [_vp, _vp, _vp, _i, _i, _i64, _vp, _vp, _vp],
+    "gsht_alm_lscale": [_vp, _vp, _i, _i, _i, _i, _vp],
     "gsht_num_stages": [],
     "gsht_stage_name": [_i],
     "gsht_last_error": [],
@@ -274,6 +279,81 @@ def legendre_rings_adjoint(F, lmax: int, mmax: int, spin: int, ntheta: int, prec
     _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
     _check(_lib.gsht_legendre_rings_adjoint(_ptr(F), lmax, mmax, spin, ntheta, prec, _ptr(out),
                                             _stream()))
+    return out
+
+
+def _prec_of(t):
+    if t.dtype in (torch.float64, torch.complex128):
+        return F64
+    if t.dtype in (torch.float32, torch.complex64):
+        return F32
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def deflect(theta, phi, alpha, want_chi=True):
+    """gsht_deflect: deflected positions (theta', phi') and the spin phase chi (or None)
+    for a deflection field alpha [2][npts] (alpha_theta, alpha_phi)."""
+    npts = _coords(theta, phi)
+    prec = _prec_of(alpha)
+    _need(alpha, _RDT[prec], (2, npts), "alpha")
+    tho = torch.empty_like(theta)
+    pho = torch.empty_like(phi)
+    chi = torch.empty_like(theta) if want_chi else None
+    _check(_lib.gsht_deflect(_ptr(theta), _ptr(phi), _ptr(alpha), prec, npts, _ptr(tho), _ptr(pho),
+                             _ptr(chi), _stream()))
+    return tho, pho, chi
+
+
+def deflect_vjp(theta, alpha, g_theta=None, g_phi=None, g_chi=None):
+    """gsht_deflect_vjp: gradient with respect to alpha [2][npts] from the gradients with
+    respect to theta', phi' and chi (each [npts] FP64 or None)."""
+    _need(theta, torch.float64, None, "theta")
+    npts = theta.numel()
+    prec = _prec_of(alpha)
+    _need(alpha, _RDT[prec], (2, npts), "alpha")
+    for name, g in (("g_theta", g_theta), ("g_phi", g_phi), ("g_chi", g_chi)):
+        if g is not None:
+            _need(g, torch.float64, (npts,), name)
+    out = torch.empty_like(alpha)
+    _check(_lib.gsht_deflect_vjp(_ptr(theta), _ptr(alpha), prec, npts, _ptr(g_theta), _ptr(g_phi),
+                                 _ptr(g_chi), _ptr(out), _stream()))
+    return out
+
+
+def spin_phase(maps, chi, spin: int, sign: int):
+    """In place: (Q + iU) <- e^{i sign spin chi} (Q + iU); returns maps."""
+    prec = _prec_of(maps)
+    _need(chi, torch.float64, None, "chi")
+    npts = chi.numel()
+    _need(maps, _RDT[prec], (2, npts), "map")
+    _check(_lib.gsht_spin_phase(_ptr(maps), _ptr(chi), spin, sign, prec, npts, _stream()))
+    return maps
+
+
+def spin_phase_vjp(gmap, lensed, chi, spin: int, want_chi=True):
+    """(dL/dP, dL/dchi) for M = e^{i spin chi} P, given gmap = dL/dM and M."""
+    prec = _prec_of(gmap)
+    _need(chi, torch.float64, None, "chi")
+    npts = chi.numel()
+    _need(gmap, _RDT[prec], (2, npts), "gmap")
+    if want_chi:
+        _need(lensed, _RDT[prec], (2, npts), "lensed")
+    g_unrot = torch.empty_like(gmap)
+    g_chi = torch.empty_like(chi) if want_chi else None
+    _check(_lib.gsht_spin_phase_vjp(_ptr(gmap), _ptr(lensed if want_chi else None), _ptr(chi), spin,
+                                    prec, npts, _ptr(g_unrot), _ptr(g_chi), _stream()))
+    return g_unrot, g_chi
+
+
+def alm_lscale(alm, lmax: int, mmax: int, out=None):
+    """sqrt(l (l + 1)) times every coefficient of alm [ncomp][nalm]."""
+    prec = _prec_of(alm)
+    ncomp = alm.shape[0]
+    _need(alm, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    if out is None:
+        out = torch.empty_like(alm)
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "out")
+    _check(_lib.gsht_alm_lscale(_ptr(alm), _ptr(out), lmax, mmax, ncomp, prec, _stream()))
     return out
 
 

@@ -1,0 +1,75 @@
+"""Lensing operator built on the general SHT (Sect. 2 and the end of Sect. 3).
+
+The lensed field at the points n_i is the unlensed field synthesised at the
+deflected points n'_i, with the spin phase e^{i s chi} for spin s > 0 (eq. forwardpol);
+the deflection field is the spin-1 synthesis of sqrt(L (L+1)) (phi_LM + i Omega_LM)
+on the points n_i (eq. deflect).  ``Lensing`` builds both plans once (positions
+are fixed per instance, as when many maps share one set of angles) and offers the
+forward operator, its adjoint, and the gradients of a real loss of the lensed map
+with respect to the unlensed coefficients and to the lensing potentials.
+
+Every step runs in the library: spin-1 synthesis, ``gsht_alm_lscale``,
+``gsht_deflect``, the plan at the deflected points, ``gsht_spin_phase`` and, for
+gradients, ``gsht_spin_phase_vjp``, ``gsht_plan_synth_vjp`` and ``gsht_deflect_vjp``.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gsht
+
+
+class Lensing:
+    """D_alpha for one geometry: points (theta, phi), lensing potential plm (and curl
+    potential olm) with band limits (lmax_p, mmax_p), unlensed field band limits
+    (lmax, mmax), spin, accuracy epsilon and precision."""
+
+    def __init__(self, theta, phi, plm, lmax: int, mmax: int, spin: int, epsilon: float,
+                 precision="f64", olm=None, lmax_p: int | None = None, mmax_p: int | None = None):
+        self.spin = spin
+        self.lmax_p = lmax if lmax_p is None else lmax_p
+        self.mmax_p = self.lmax_p if mmax_p is None else mmax_p
+        prec = gsht._PREC[precision]
+        cdt = gsht._CDT[prec]
+        self.theta = theta
+        self.phi = phi
+        glm = torch.stack([plm.to(cdt), (torch.zeros_like(plm) if olm is None else olm).to(cdt)])
+        glm = gsht.alm_lscale(glm.contiguous(), self.lmax_p, self.mmax_p)
+        self.dplan = gsht.Plan(theta, phi, self.lmax_p, self.mmax_p, 1, epsilon, precision)
+        self.alpha = self.dplan.synth(glm)
+        self.theta_d, self.phi_d, chi = gsht.deflect(theta, phi, self.alpha, want_chi=spin > 0)
+        self.chi = chi
+        self.plan = gsht.Plan(self.theta_d, self.phi_d, lmax, mmax, spin, epsilon, precision)
+
+    def close(self):
+        self.plan.close()
+        self.dplan.close()
+
+    def forward(self, alm):
+        """Lensed map [ncomp][npts]."""
+        m = self.plan.synth(alm)
+        if self.spin:
+            gsht.spin_phase(m, self.chi, self.spin, 1)
+        return m
+
+    def adjoint(self, maps):
+        """Adjoint of ``forward`` (eq. adjoint and its spin-s form): a_lm [ncomp][nalm]."""
+        if self.spin:
+            maps = gsht.spin_phase(maps.clone(), self.chi, self.spin, -1)
+        return self.plan.adjoint(maps)
+
+    def vjp(self, alm, gmap, want_alm=True, want_potential=True):
+        """Gradients of a real loss L with dL/dmap = gmap (torch's convention for complex
+        tensors): (dL/dalm, dL/dplm, dL/dolm); entries not asked for are None."""
+        g_unrot, g_chi = gmap, None
+        if self.spin:
+            lensed = self.forward(alm) if want_potential else None
+            g_unrot, g_chi = gsht.spin_phase_vjp(gmap, lensed, self.chi, self.spin,
+                                                 want_chi=want_potential)
+        galm, gth, gph = self.plan.synth_vjp(alm, g_unrot, want_alm, want_potential, want_potential)
+        if not want_potential:
+            return galm, None, None
+        g_alpha = gsht.deflect_vjp(self.theta, self.alpha, gth, gph, g_chi)
+        gg, _, _ = self.dplan.synth_vjp(None, g_alpha, True, False, False)
+        gp = gsht.alm_lscale(gg, self.lmax_p, self.mmax_p)
+        return galm, gp[0], gp[1]

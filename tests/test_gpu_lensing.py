@@ -1,0 +1,190 @@
+"""GPU lensing geometry and operator against the CPU reference ``oracle.lensing``.
+
+* gsht_deflect: deflected positions and spin phase vs the reference (itself pinned
+  against spherical geometry and brute-force parallel transport);
+* gsht_deflect_vjp: exact Jacobian products vs central differences of the reference;
+* the lensing operator (spin-1 deflection synthesis, deflection, synthesis at the
+  deflected points, spin phase) and its adjoint vs the reference within epsilon;
+* gradients with respect to the lensing potential vs central differences of the GPU
+  FP64 operator, and with respect to the unlensed coefficients vs w_m times the
+  adjoint.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lensing as ol
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2304_10431_amd import gsht
+    return gsht
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _alm(spin, lmax, mmax, seed, decay=1.0):
+    rng = np.random.default_rng(seed)
+    nc = oracle.ncomp(spin)
+    a = rng.standard_normal((nc, oracle.nalm(lmax, mmax))) + 1j * rng.standard_normal((nc, oracle.nalm(lmax, mmax)))
+    for blk in a:
+        for m in range(mmax + 1):
+            i0 = oracle.alm_index(m, m, lmax)
+            ls = np.arange(m, lmax + 1)
+            blk[i0:i0 + ls.size] /= (ls + 1.0) ** decay
+            if m == 0:
+                blk[i0:i0 + ls.size] = blk[i0:i0 + ls.size].real
+            blk[i0:i0 + max(0, spin - m)] = 0
+    return a
+
+
+def _points(n, seed):
+    rng = np.random.default_rng(seed)
+    th = np.arccos(rng.uniform(-1, 1, n))
+    ph = rng.uniform(0, 2 * np.pi, n)
+    return th, ph
+
+
+def _potential(lmax_p, seed, rms):
+    """A potential whose deflection has roughly the given rms (radians)."""
+    plm = _alm(0, lmax_p, lmax_p, seed, decay=2.5)[0]
+    plm[:oracle.alm_index(0, 0, lmax_p) + 2] = 0.0       # no monopole / dipole
+    th, ph = _points(2000, seed + 1)
+    a = ol.deflection_field(plm, lmax_p, lmax_p, th, ph)
+    return plm * (rms / math.sqrt(np.mean(a[0] ** 2 + a[1] ** 2)))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_deflect_vs_reference(G, prec):
+    say("deflect", prec)
+    th, ph = _points(20000, 1)
+    th[:3] = [1e-3, math.pi - 1e-3, math.pi / 2]
+    rng = np.random.default_rng(2)
+    alpha = rng.normal(0, 0.01, (2, th.size))
+    alpha[:, 3] = 0.0                                       # no deflection
+    alpha[:, 4] = [1e-9, -2e-9]                            # series branch
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    al_d = dev(alpha).to(rdt)
+    al = al_d.double().cpu().numpy()                       # the values the GPU sees
+    t2, p2, chi = G.deflect(dev(th), dev(ph), al_d)
+    rt, rp, rc = ol.deflect(th, ph, al)
+    t2, p2, chi = t2.cpu().numpy(), p2.cpu().numpy(), chi.cpu().numpy()
+    assert np.max(np.abs(t2 - rt)) < 2e-14
+    dphi = np.angle(np.exp(1j * (p2 - rp)))
+    assert np.max(np.abs(dphi * np.sin(rt))) < 2e-14
+    assert np.all((p2 >= 0) & (p2 < 2 * math.pi))
+    away = (np.sin(rt) > 1e-2) & (np.sin(th) > 1e-2)
+    assert np.max(np.abs(np.angle(np.exp(1j * (chi - rc))))[away]) < 1e-11
+    assert chi[3] == 0.0 and t2[3] == th[3]
+
+
+def test_deflect_vjp_vs_central_differences(G):
+    say("deflect vjp")
+    th, ph = _points(3000, 3)
+    th = np.clip(th, 0.05, math.pi - 0.05)
+    rng = np.random.default_rng(4)
+    alpha = rng.normal(0, 0.01, (2, th.size))
+    alpha[:, 0] = 0.0
+    gt, gp, gc = rng.standard_normal((3, th.size))
+    ga = G.deflect_vjp(dev(th), dev(alpha), dev(gt), dev(gp), dev(gc)).cpu().numpy()
+    h = 1e-7
+    ref = np.zeros_like(alpha)
+    for c in range(2):
+        e = np.zeros_like(alpha)
+        e[c] = h
+        a1 = ol.deflect(th, ph, alpha + e)
+        a0 = ol.deflect(th, ph, alpha - e)
+        dt = (a1[0] - a0[0]) / (2 * h)
+        dp = np.angle(np.exp(1j * (a1[1] - a0[1]))) / (2 * h)
+        dc = np.angle(np.exp(1j * (a1[2] - a0[2]))) / (2 * h)
+        ref[c] = gt * dt + gp * dp + gc * dc
+    assert np.max(np.abs(ga - ref)) < 1e-6 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("spin", [0, 2])
+def test_lensing_operator_vs_reference(G, prec, eps, spin):
+    from paper_2304_10431_amd.lensing import Lensing
+    say("lensing operator", prec, eps, spin)
+    lmax = mmax = 96
+    lmax_p = 64
+    th, ph = _points(20000, 10 + spin)
+    plm = _potential(lmax_p, 20, 3e-3)
+    a = _alm(spin, lmax, mmax, 30 + spin)
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    L = Lensing(dev(th), dev(ph), dev(plm), lmax, mmax, spin, eps, prec, lmax_p=lmax_p)
+    m = L.forward(dev(a).to(cdt)).double().cpu().numpy()
+    alpha = ol.deflection_field(plm, lmax_p, lmax_p, th, ph)
+    ref = ol.lensed_synth(a, lmax, mmax, spin, th, ph, alpha)
+    e_f = oracle.eps_eff(m, ref)
+    y = np.random.default_rng(40).standard_normal(ref.shape)
+    b = L.adjoint(dev(y).to(rdt)).to(torch.complex128).cpu().numpy()
+    rb = ol.lensed_adjoint(y, lmax, mmax, spin, th, ph, alpha)
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    e_a = oracle.eps_eff(w * b, w * rb)
+    L.close()
+    say("  forward %.3e adjoint %.3e" % (e_f, e_a))
+    assert e_f <= eps
+    assert e_a <= eps
+
+
+@pytest.mark.parametrize("spin", [0, 2])
+def test_lensing_gradients(G, spin):
+    from paper_2304_10431_amd.lensing import Lensing
+    say("lensing gradients", spin)
+    lmax = mmax = 64
+    lmax_p = 32
+    th, ph = _points(4000, 50 + spin)
+    plm = _potential(lmax_p, 60, 5e-3)
+    a = _alm(spin, lmax, mmax, 70 + spin)
+    g = np.random.default_rng(80).standard_normal((oracle.ncomp(spin), th.size))
+    tht, pht, ad, gd = dev(th), dev(ph), dev(a), dev(g)
+
+    def loss(p):
+        L = Lensing(tht, pht, dev(p), lmax, mmax, spin, 1e-10, "f64", lmax_p=lmax_p)
+        v = float(torch.sum(L.forward(ad) * gd))
+        L.close()
+        return v
+
+    L = Lensing(tht, pht, dev(plm), lmax, mmax, spin, 1e-10, "f64", lmax_p=lmax_p)
+    galm, gp, go = L.vjp(ad, gd)
+    b = L.adjoint(gd)
+    L.close()
+    w = torch.from_numpy(oracle.alm_weights(lmax, mmax)).cuda()
+    bw = b * w[None, :]
+    assert float(torch.max(torch.abs(galm - bw))) <= 1e-13 * float(torch.max(torch.abs(bw)))
+    gp = gp.cpu().numpy()
+    rng = np.random.default_rng(90)
+    idx = rng.choice(np.arange(oracle.alm_index(2, 0, lmax_p), plm.size), 6, replace=False)
+    scale = np.max(np.abs(gp))
+    worst = 0.0
+    for i in idx:
+        for part in (1.0, 1j):
+            m_of_i = next(m for m in range(lmax_p + 1) if oracle.alm_index(m, m, lmax_p) <= i <
+                          oracle.alm_index(m, m, lmax_p) + lmax_p + 1 - m)
+            if m_of_i == 0 and part == 1j:
+                continue                                     # Im of m = 0 is ignored
+            h = 1e-6 * np.max(np.abs(plm))
+            e = np.zeros_like(plm)
+            e[i] = h * part
+            fd = (loss(plm + e) - loss(plm - e)) / (2 * h)
+            got = gp[i].real if part == 1.0 else gp[i].imag
+            worst = max(worst, abs(fd - got) / scale)
+    say("  worst |fd - grad| / max|grad| = %.3e" % worst)
+    assert worst <= 1e-5
