@@ -110,8 +110,27 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup):
     stages = plan.stage_times()
     plan.set_profiling(False)
     info = plan.info()
-    return plan, m, dict(s_per_step=dt, synth_ms=syn_ms, adjoint_ms=adj_ms, plan_s=t_plan,
-                         stages=stages, info=info)
+    r = dict(s_per_step=dt, synth_ms=syn_ms, adjoint_ms=adj_ms, plan_s=t_plan, stages=stages,
+             info=info)
+    if spec["spin"] > 0:
+        # the gradient-only setting (C = 0): same plan, same step count
+        g = a[:1].contiguous()
+        bg = plan.adjoint_grad(m)
+        plan.synth_grad(g, out=m)
+        torch.cuda.synchronize()
+        evg = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for k in range(steps):
+            evg[k][0].record()
+            plan.synth_grad(g, out=m)
+            evg[k][1].record()
+            plan.adjoint_grad(m, out=bg)
+            evg[k][2].record()
+        torch.cuda.synchronize()
+        r["gradient_only"] = {
+            "synth_ms": sum(e[0].elapsed_time(e[1]) for e in evg) / steps,
+            "adjoint_ms": sum(e[1].elapsed_time(e[2]) for e in evg) / steps}
+        m = plan.synth(a, out=m)
+    return plan, m, r
 
 
 def spreading_figures(info, stages, npts, ncomp, prec):
@@ -309,6 +328,7 @@ def main():
                       "adjoint_ms": v["adjoint_ms"], "plan_s": v["plan_s"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
                       "column_mode": v["info"]["column_mode"],
+                      "gradient_only_ms": v.get("gradient_only"),
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",

@@ -121,6 +121,19 @@ int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
 int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream);
 
 /*
+ * Gradient-only spin-s transforms (spin > 0 plans; Sect. 4 notes this setting for
+ * fields without a curl component): the synthesis of eq. forwardpol with C = 0,
+ * and the adjoint's gradient part G only.
+ *   glm [1][nalm] complex (prec): G; map [2][npts] real (prec): Q, U.
+ * Same results as gsht_plan_synth with C = 0 and as the G block of
+ * gsht_plan_adjoint, with about a third fewer Legendre operations (the two spin
+ * channels share the products with G).  GSHT_EINVAL for spin-0 plans.  Do not
+ * allocate and do not synchronise.
+ */
+int gsht_plan_synth_grad(gsht_plan *p, const void *glm, void *map, void *hip_stream);
+int gsht_plan_adjoint_grad(gsht_plan *p, const void *map, void *glm, void *hip_stream);
+
+/*
  * Derivatives with respect to the point positions (Sect. 2: the lensed map is the
  * unlensed field synthesised at deflected angles, so its dependence on the
  * deflection goes through these derivatives).  With the plan's points:
@@ -202,6 +215,13 @@ int gsht_spin_phase(void *map, const double *chi, int spin, int sign, gsht_preci
 int gsht_spin_phase_vjp(const void *gmap, const void *lensed, const double *chi, int spin,
                         gsht_precision prec, int64_t npts, void *g_unrot, double *g_chi,
                         void *hip_stream);
+
+/* map_out[c][i] = weights[i] map_in[c][i] for ncomp components ([ncomp][npts] real,
+ * prec; weights [npts] FP64; in place allowed): quadrature weights, which turn the
+ * adjoint synthesis on a grid into its analysis (Sect. 2: weights added to
+ * eq. adjoint approximate the integral over the sphere). */
+int gsht_map_weight(const void *map_in, const double *weights, int ncomp, int64_t npts,
+                    gsht_precision prec, void *map_out, void *hip_stream);
 
 /* alm_out = sqrt(l (l + 1)) alm_in for ncomp coefficient blocks ([ncomp][nalm]
  * complex, prec; in place allowed): the lensing potential's coefficients become the

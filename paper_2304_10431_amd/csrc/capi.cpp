@@ -631,10 +631,11 @@ int check_launch(hipError_t e, const char *what)
     } while (0)
 
 // Synthesis up to the oversampled grid (G, or g for spin 0), before interpolation.
-int plan_synth_grid(gsht_plan *p, const void *alm, double mscale, hipStream_t s)
+int plan_synth_grid(gsht_plan *p, const void *alm, double mscale, hipStream_t s,
+                    bool grad = false)
 {
-    RUN(ST_PREP, launch_prep_alm(*p, alm, mscale, s));
-    RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, s));
+    RUN(ST_PREP, launch_prep_alm(*p, alm, mscale, grad, s));
+    RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, grad, s));
     if (p->colmode == 0) {
         RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
         RUN(ST_DECONV_FWD, launch_deconv_fwd(*p, s));
@@ -651,9 +652,10 @@ int plan_synth_grid(gsht_plan *p, const void *alm, double mscale, hipStream_t s)
     return ok();
 }
 
-int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s, double mscale = 1.0)
+int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s, double mscale = 1.0,
+                    bool grad = false)
 {
-    int rc = plan_synth_grid(p, alm, mscale, s);
+    int rc = plan_synth_grid(p, alm, mscale, s, grad);
     if (rc != GSHT_OK)
         return rc;
     RUN(ST_INTERP, launch_interp(*p, map, s));
@@ -673,7 +675,7 @@ int plan_deriv_impl(gsht_plan *p, const void *alm, void *map, void *dth, void *d
 }
 
 int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
-                      double mscale = 1.0)
+                      double mscale = 1.0, bool grad = false)
 {
     const size_t cs = csize(p->prec);
     if (p->spin)
@@ -694,8 +696,8 @@ int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
     } else {
         RUN(ST_COLUMN_ADJ, launch_column_adj(*p, s));
     }
-    RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, s));
-    RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, mscale, s));
+    RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, grad, s));
+    RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, mscale, grad, s));
     return ok();
 }
 
@@ -743,6 +745,28 @@ int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream
     if (!alm || (!map && p->npts > 0))
         return fail(GSHT_EINVAL, "alm/map must not be NULL");
     return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+}
+
+int gsht_plan_synth_grad(gsht_plan *p, const void *glm, void *map, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (p->spin == 0)
+        return fail(GSHT_EINVAL, "gradient-only transforms need spin > 0");
+    if (!glm || (!map && p->npts > 0))
+        return fail(GSHT_EINVAL, "glm/map must not be NULL");
+    return plan_synth_impl(p, glm, map, (hipStream_t)hip_stream, 1.0, true);
+}
+
+int gsht_plan_adjoint_grad(gsht_plan *p, const void *map, void *glm, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (p->spin == 0)
+        return fail(GSHT_EINVAL, "gradient-only transforms need spin > 0");
+    if (!glm || (!map && p->npts > 0))
+        return fail(GSHT_EINVAL, "glm/map must not be NULL");
+    return plan_adjoint_impl(p, map, glm, (hipStream_t)hip_stream, 1.0, true);
 }
 
 int gsht_plan_synth_deriv(gsht_plan *p, const void *alm, void *map, void *dtheta, void *dphi,
@@ -845,6 +869,20 @@ int gsht_spin_phase_vjp(const void *gmap, const void *lensed, const double *chi,
     return check_launch(launch_spin_phase_vjp(gmap, lensed, chi, spin, prec, npts, g_unrot, g_chi,
                                               (hipStream_t)hip_stream),
                         "spin_phase_vjp");
+}
+
+int gsht_map_weight(const void *map_in, const double *weights, int ncomp, int64_t npts,
+                    gsht_precision prec, void *map_out, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0 || ncomp < 1 || ncomp > 2)
+        return fail(GSHT_EINVAL, "need npts >= 0 and ncomp in {1, 2}");
+    if (npts > 0 && (!map_in || !weights || !map_out))
+        return fail(GSHT_EINVAL, "map_in/weights/map_out must not be NULL");
+    return check_launch(launch_map_weight(map_in, weights, ncomp, npts, prec, map_out,
+                                          (hipStream_t)hip_stream),
+                        "map_weight");
 }
 
 int gsht_alm_lscale(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp,
@@ -1005,9 +1043,9 @@ int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int nthet
     p->ncol = spin ? 2 * mmax + 1 : mmax + 1;
     p->npairs = (ntheta + 1) / 2;
     if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
-    int rc2 = check_launch(launch_prep_alm(*p, alm, 1.0, s), "prep_alm");
+    int rc2 = check_launch(launch_prep_alm(*p, alm, 1.0, false, s), "prep_alm");
     if (rc2 == GSHT_OK)
-        rc2 = check_launch(launch_leg_synth(*p, F, s), "legendre_synth");
+        rc2 = check_launch(launch_leg_synth(*p, F, false, s), "legendre_synth");
     if (rc2 == GSHT_OK)
         rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
     free_plan(p);
@@ -1037,9 +1075,9 @@ int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int
     p->ncol = spin ? 2 * mmax + 1 : mmax + 1;
     p->npairs = (ntheta + 1) / 2;
     if ((rc = setup_legendre(p, s, false)) != GSHT_OK) { free_plan(p); return rc; }
-    int rc2 = check_launch(launch_leg_adjoint(*p, F, s), "legendre_adjoint");
+    int rc2 = check_launch(launch_leg_adjoint(*p, F, false, s), "legendre_adjoint");
     if (rc2 == GSHT_OK)
-        rc2 = check_launch(launch_leg_finalize(*p, alm, 1.0, s), "finalize");
+        rc2 = check_launch(launch_leg_finalize(*p, alm, 1.0, false, s), "finalize");
     if (rc2 == GSHT_OK)
         rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
     free_plan(p);

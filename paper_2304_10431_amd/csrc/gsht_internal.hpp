@@ -150,10 +150,13 @@ hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s);
 hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s);
 // mscale multiplies the coefficients (prep) or results (finalize) of every m > 0:
 // 1 for the transforms, 1/2 or 2 for the weights w_m of their derivatives.
-hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, hipStream_t s);
-hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s);
-hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s);
-hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, hipStream_t s);
+// grad: gradient-only spin s (C = 0 on input; only G on output).
+hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, bool grad,
+                           hipStream_t s);
+hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, bool grad, hipStream_t s);
+hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s);
+hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
+                               hipStream_t s);
 
 // ---- staging (staging.hip) -------------------------------------------------
 hipError_t launch_deconv_fwd(const gsht_plan &p, hipStream_t s);     // D -> E
@@ -190,6 +193,8 @@ hipError_t launch_spin_phase(void *map, const double *chi, int spin, int sign, i
 hipError_t launch_spin_phase_vjp(const void *g, const void *lensed, const double *chi, int spin,
                                  int prec, int64_t npts, void *g_unrot, double *g_chi,
                                  hipStream_t s);
+hipError_t launch_map_weight(const void *in, const double *w, int ncomp, int64_t npts, int prec,
+                             void *out, hipStream_t s);
 hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int prec, void *out,
                              hipStream_t s);
 hipError_t launch_interp_deriv(const gsht_plan &p, void *out_map, void *dth, void *dph,

@@ -144,7 +144,7 @@ hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s)
 //   spin 0: u = a_lm (Im a_l0 dropped);  spin s: u+ = -(G + iC), u- = -(-1)^s (G* + i C*).
 template <typename TC>
 __global__ void prep_alm_kernel(const TC *__restrict__ alm, const double *__restrict__ norm,
-                                int lmax, int mmax, int s, int64_t nalm, double mscale,
+                                int lmax, int mmax, int s, int64_t nalm, double mscale, int grad,
                                 double *__restrict__ u)
 {
     const int m = blockIdx.y;
@@ -153,7 +153,11 @@ __global__ void prep_alm_kernel(const TC *__restrict__ alm, const double *__rest
         return;
     const int64_t i = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
     const double n = (l < s) ? 0.0 : (m > 0 ? mscale : 1.0) * norm[i];
-    if (s == 0) {
+    if (grad) {  // gradient-only spin s: u+ = -G (C = 0); u- follows in the kernel
+        const TC gc = alm[i];
+        u[2 * i] = -n * (double)gc.x;
+        u[2 * i + 1] = (m == 0) ? 0.0 : -n * (double)gc.y;
+    } else if (s == 0) {
         const TC a = alm[i];
         u[2 * i] = n * (double)a.x;
         u[2 * i + 1] = (m == 0) ? 0.0 : n * (double)a.y;
@@ -169,15 +173,17 @@ __global__ void prep_alm_kernel(const TC *__restrict__ alm, const double *__rest
     }
 }
 
-hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, hipStream_t s)
+hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, bool grad,
+                           hipStream_t s)
 {
     dim3 blk(256), grd((p.lmax + 1 + 255) / 256, p.mmax + 1);
+    const int g = (grad && p.spin) ? 1 : 0;
     if (p.prec == GSHT_F64)
         hipLaunchKernelGGL(prep_alm_kernel<double2>, grd, blk, 0, s, (const double2 *)alm,
-                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, mscale, p.uprep);
+                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, mscale, g, p.uprep);
     else
         hipLaunchKernelGGL(prep_alm_kernel<float2>, grd, blk, 0, s, (const float2 *)alm,
-                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, mscale, p.uprep);
+                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, mscale, g, p.uprep);
     return hipGetLastError();
 }
 
@@ -185,7 +191,7 @@ hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, h
 template <typename TC>
 __global__ void leg_finalize_kernel(const double *__restrict__ acc, const double *__restrict__ norm,
                                     int lmax, int mmax, int s, int64_t nalm, double mscale,
-                                    TC *__restrict__ alm)
+                                    int grad, TC *__restrict__ alm)
 {
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,7 +200,11 @@ __global__ void leg_finalize_kernel(const double *__restrict__ acc, const double
     const int64_t i = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
     const double n = (l < s) ? 0.0 : (m > 0 ? mscale : 1.0) * norm[i];
     TC o;
-    if (s == 0) {
+    if (grad) {  // gradient-only: acc holds S+ + (-1)^s S-, G = -(that) / 2
+        o.x = -0.5 * n * acc[2 * i];
+        o.y = (m == 0) ? 0.0 : -0.5 * n * acc[2 * i + 1];
+        alm[i] = o;
+    } else if (s == 0) {
         o.x = n * acc[2 * i];
         o.y = (m == 0) ? 0.0 : n * acc[2 * i + 1];
         alm[i] = o;
@@ -212,15 +222,17 @@ __global__ void leg_finalize_kernel(const double *__restrict__ acc, const double
     }
 }
 
-hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, hipStream_t s)
+hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
+                               hipStream_t s)
 {
     dim3 blk(256), grd((p.lmax + 1 + 255) / 256, p.mmax + 1);
+    const int g = (grad && p.spin) ? 1 : 0;
     if (p.prec == GSHT_F64)
         hipLaunchKernelGGL(leg_finalize_kernel<double2>, grd, blk, 0, s, p.acc, p.leg.norm, p.lmax,
-                           p.mmax, p.spin, p.nalm, mscale, (double2 *)alm);
+                           p.mmax, p.spin, p.nalm, mscale, g, (double2 *)alm);
     else
         hipLaunchKernelGGL(leg_finalize_kernel<float2>, grd, blk, 0, s, p.acc, p.leg.norm, p.lmax,
-                           p.mmax, p.spin, p.nalm, mscale, (float2 *)alm);
+                           p.mmax, p.spin, p.nalm, mscale, g, (float2 *)alm);
     return hipGetLastError();
 }
 

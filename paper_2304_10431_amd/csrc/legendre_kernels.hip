@@ -351,29 +351,57 @@ __device__ inline void synth_acc(double (&c)[8], double va, double vb, const dou
     }
 }
 
+// Gradient-only spin s (C = 0): u- = (-1)^s conj(u+), so the four ring sums follow
+// from the products of u+ with both channels, kept per degree parity:
+// E_a (0,1), E_b (2,3) for SG = +1 and O_a (4,5), O_b (6,7) for SG = -1;
+//   N+ = E_a + O_a,  S+ = E_b - O_b,  N- = (-1)^s conj(E_b + O_b),
+//   S- = (-1)^s conj(E_a - O_a)
+// (4 FMA per ring pair and degree instead of 8).
+template <int SG>
+__device__ inline void synth_acc_grad(double (&c)[8], double va, double vb, const double *u)
+{
+    constexpr int o = SG > 0 ? 0 : 4;
+    c[o + 0] = fma(u[0], va, c[o + 0]);
+    c[o + 1] = fma(u[1], va, c[o + 1]);
+    c[o + 2] = fma(u[0], vb, c[o + 2]);
+    c[o + 3] = fma(u[1], vb, c[o + 3]);
+}
+
+template <bool SPIN, bool GRAD, int SG>
+__device__ inline void synth_acc_any(double (&c)[8], double va, double vb, const double *u)
+{
+    if constexpr (GRAD)
+        synth_acc_grad<SG>(c, va, vb, u);
+    else
+        synth_acc<SPIN, SG>(c, va, vb, u);
+}
+
 // Add a masked block's sums t to c for the channels in range (the offsets are
 // those the block ran with: rescaling happens after the fold).  Channel +s feeds
-// c[0,1,6,7], channel -s c[2..5]; spin 0 has channel +s only.
-template <bool SPIN>
+// c[0,1,6,7], channel -s c[2..5]; spin 0 has channel +s only.  Gradient-only:
+// channel +s feeds c[0,1,4,5], channel -s c[2,3,6,7].
+template <bool SPIN, bool GRAD = false>
 __device__ inline void synth_fold(double (&c)[8], const double (&t)[8], const Ring &r)
 {
     const bool ia = r.ea == 0, ib = SPIN && r.eb == 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const bool in = (!SPIN || k < 2 || k > 5) ? ia : ib;
+        const bool chan_a = GRAD ? ((k & 2) == 0) : (!SPIN || k < 2 || k > 5);
+        const bool in = chan_a ? ia : ib;
         c[k] += in ? t[k] : 0.0;
     }
 }
 
 constexpr int LB = 8;  // degrees per block
 
-template <typename T, bool SPIN, int R>
+template <typename T, bool SPIN, int R, bool GRAD = false>
 __global__ __launch_bounds__(64) void leg_synth_kernel(
     const double2 *__restrict__ ab, const double *__restrict__ u, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, int lmax, int mmax, int s, int ntheta, int nd, int npairs,
     int nchunk, typename cplxk<T>::type *__restrict__ D)
 {
-    constexpr int US = SPIN ? 4 : 2;
+    static_assert(SPIN || !GRAD, "gradient-only needs spin > 0");
+    constexpr int US = (SPIN && !GRAD) ? 4 : 2;
     int m, chunk;
     xcd_map(nchunk, m, chunk);
     if (m > mmax)
@@ -421,7 +449,7 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
             const double2 c0 = abl[b];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                synth_acc<SPIN, 1>(t[r], rg[r].a1, rg[r].b1, ul + US * b);
+                synth_acc_any<SPIN, GRAD, 1>(t[r], rg[r].a1, rg[r].b1, ul + US * b);
                 ring_advance<SPIN>(rg[r], c0.x, c0.y);
             }
             if (TAIL && l + 1 > lmax)
@@ -429,13 +457,13 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
             const double2 c1 = abl[b + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                synth_acc<SPIN, -1>(t[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
+                synth_acc_any<SPIN, GRAD, -1>(t[r], rg[r].a1, rg[r].b1, ul + US * (b + 1));
                 ring_advance<SPIN>(rg[r], c1.x, c1.y);
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            synth_fold<SPIN>(c[r], t[r], rg[r]);
+            synth_fold<SPIN, GRAD>(c[r], t[r], rg[r]);
         all_in = true;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -473,9 +501,9 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
                 const Pair nxt = load_pair(lb + 2 < lend ? lb + 2 : lb);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    synth_acc<SPIN, 1>(c[r], rg[r].a1, rg[r].b1, cur.u);
+                    synth_acc_any<SPIN, GRAD, 1>(c[r], rg[r].a1, rg[r].b1, cur.u);
                     ring_advance<SPIN>(rg[r], cur.c0.x, cur.c0.y);
-                    synth_acc<SPIN, -1>(c[r], rg[r].a1, rg[r].b1, cur.u + US);
+                    synth_acc_any<SPIN, GRAD, -1>(c[r], rg[r].a1, rg[r].b1, cur.u + US);
                     ring_advance<SPIN>(rg[r], cur.c1.x, cur.c1.y);
                 }
                 cur = nxt;
@@ -492,6 +520,20 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
         const int q = chunk * 64 * R + 64 * r + lane;
         if (q >= npairs)
             continue;
+        if constexpr (GRAD) {  // parity sums -> N+, S+, N-, S- (see synth_acc_grad)
+            const double sg = (s & 1) ? -1.0 : 1.0;
+            double (&v)[8] = c[r];
+            const double ea0 = v[0], ea1 = v[1], eb0 = v[2], eb1 = v[3];
+            const double oa0 = v[4], oa1 = v[5], ob0 = v[6], ob1 = v[7];
+            v[0] = ea0 + oa0;
+            v[1] = ea1 + oa1;
+            v[2] = eb0 - ob0;
+            v[3] = eb1 - ob1;
+            v[4] = sg * (eb0 + ob0);
+            v[5] = -sg * (eb1 + ob1);
+            v[6] = sg * (ea0 - oa0);
+            v[7] = -sg * (ea1 - oa1);
+        }
         const int jn = q, js = ntheta - 1 - q;
         typename cplxk<T>::type *colp = D + (size_t)(SPIN ? m + mmax : m) * nd;
         put_ring<T>(colp, jn, ntheta, nd, ms, c[r][0], c[r][1]);
@@ -507,29 +549,31 @@ __global__ __launch_bounds__(64) void leg_synth_kernel(
 }
 
 template <int R>
-static void synth_launch(const gsht_plan &p, void *Dout, hipStream_t s)
+static void synth_launch(const gsht_plan &p, void *Dout, bool grad, hipStream_t s)
 {
     dim3 blk(64), grd(xcd_grid(p.mmax, p.syn_nchunk));
-#define GSHT_LEG_SYNTH(T, SP, C)                                                                 \
-    hipLaunchKernelGGL((leg_synth_kernel<T, SP, R>), grd, blk, 0, s, p.leg.ab, p.uprep,          \
+#define GSHT_LEG_SYNTH(T, SP, G, C)                                                              \
+    hipLaunchKernelGGL((leg_synth_kernel<T, SP, R, G>), grd, blk, 0, s, p.leg.ab, p.uprep,       \
                        p.leg.start, p.leg.lfirst_syn, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,     \
                        p.npairs, p.syn_nchunk, (C *)Dout)
     if (p.prec == GSHT_F64) {
-        if (p.spin) GSHT_LEG_SYNTH(double, true, double2);
-        else GSHT_LEG_SYNTH(double, false, double2);
+        if (p.spin && grad) GSHT_LEG_SYNTH(double, true, true, double2);
+        else if (p.spin) GSHT_LEG_SYNTH(double, true, false, double2);
+        else GSHT_LEG_SYNTH(double, false, false, double2);
     } else {
-        if (p.spin) GSHT_LEG_SYNTH(float, true, float2);
-        else GSHT_LEG_SYNTH(float, false, float2);
+        if (p.spin && grad) GSHT_LEG_SYNTH(float, true, true, float2);
+        else if (p.spin) GSHT_LEG_SYNTH(float, true, false, float2);
+        else GSHT_LEG_SYNTH(float, false, false, float2);
     }
 #undef GSHT_LEG_SYNTH
 }
 
-hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, hipStream_t s)
+hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, bool grad, hipStream_t s)
 {
     switch (p.syn_r) {
-    case 1: synth_launch<1>(p, Dout, s); break;
-    case 2: synth_launch<2>(p, Dout, s); break;
-    case 4: synth_launch<4>(p, Dout, s); break;
+    case 1: synth_launch<1>(p, Dout, grad, s); break;
+    case 2: synth_launch<2>(p, Dout, grad, s); break;
+    case 4: synth_launch<4>(p, Dout, grad, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -585,6 +629,29 @@ __device__ inline void adj_acc(double *cb, const RingIn &in, double va, double v
     }
 }
 
+// Gradient-only spin s: only T = S+ + (-1)^s S- is needed (G = -T / 2).  With the
+// ring inputs precombined as X = F+(N) + SG sg cF-(S'), Y = SG F+(S') + sg cF-(N)
+// (sg = (-1)^s, one pair per degree parity SG), T += a X + b Y; a and b go to
+// separate sums (0,1) and (2,3), added before the lane reduction.
+template <int SG>
+__device__ inline void adj_acc_grad(double *cb, const RingIn &in, double va, double vb)
+{
+    constexpr int o = SG > 0 ? 0 : 2;
+    cb[0] = fma(va, in.v[o + 0], cb[0]);
+    cb[1] = fma(va, in.v[o + 1], cb[1]);
+    cb[2] = fma(vb, in.v[o + 4], cb[2]);
+    cb[3] = fma(vb, in.v[o + 5], cb[3]);
+}
+
+template <bool SPIN, bool GRAD, int SG>
+__device__ inline void adj_acc_any(double *cb, const RingIn &in, double va, double vb)
+{
+    if constexpr (GRAD)
+        adj_acc_grad<SG>(cb, in, va, vb);
+    else
+        adj_acc<SPIN, SG>(cb, in, va, vb);
+}
+
 // a' = [a(0..31), b(0..31)], b' = [a(32..63), b(32..63)] (v_permlane32_swap on both
 // halves of the doubles); returns a' + b': lanes 0..31 hold a summed over lanes L
 // and L + 32, lanes 32..63 hold b summed likewise.
@@ -620,14 +687,16 @@ __device__ inline double swap_add16(double a, double b)
 // (rotated slots, conflict free) and are summed by V groups of 64/V lanes.  The
 // results are added to acc[idx][0..NC-1] with one coalesced FP64 atomic per
 // (degree, component).
-template <typename T, bool SPIN, int R, int B>
+template <typename T, bool SPIN, int R, int B, bool GRAD = false>
 __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, const typename cplxk<T>::type *__restrict__ D, int lmax,
     int mmax, int s, int ntheta, int nd, int npairs, int nchunk, double *__restrict__ acc)
 {
-    constexpr int NC = SPIN ? 4 : 2;
-    constexpr int V = B * NC;
+    static_assert(SPIN || !GRAD, "gradient-only needs spin > 0");
+    constexpr int NC = SPIN ? 4 : 2;         // per-lane sums per degree
+    constexpr int NR = GRAD ? 2 : NC;        // reduced values per degree
+    constexpr int V = B * NR;
     static_assert(64 % V == 0 && V >= 8, "block values must divide the wave");
     __shared__ double red[V * 16];
     int m, chunk;
@@ -672,7 +741,13 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
                 }
             }
         }
-        if (SPIN) {
+        if (GRAD) {  // X_e, X_o, Y_e, Y_o (see adj_acc_grad)
+            const double sg = (s & 1) ? -1.0 : 1.0;
+            in[r].v[0] = fpn.x + sg * fms.x; in[r].v[1] = fpn.y - sg * fms.y;
+            in[r].v[2] = fpn.x - sg * fms.x; in[r].v[3] = fpn.y + sg * fms.y;
+            in[r].v[4] = fps.x + sg * fmn.x; in[r].v[5] = fps.y - sg * fmn.y;
+            in[r].v[6] = -fps.x + sg * fmn.x; in[r].v[7] = -fps.y - sg * fmn.y;
+        } else if (SPIN) {
             in[r].v[0] = fpn.x; in[r].v[1] = fpn.y;
             in[r].v[2] = fps.x; in[r].v[3] = fps.y;
             in[r].v[4] = fmn.x; in[r].v[5] = -fmn.y;
@@ -721,17 +796,31 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
 #pragma unroll
         for (int d = V; d < 64; d <<= 1)
             sum += __shfl_xor(sum, d, 64);
-        if (lane < V && lb + lane / NC <= lmax)
-            unsafeAtomicAdd(acc + (base + lb) * NC + lane, sum);
+        if (lane < V && lb + lane / NR <= lmax)
+            unsafeAtomicAdd(acc + (base + lb) * NR + lane, sum);
+    };
+    // per-lane sums of a block -> the values reduced over the wave
+    auto reduce_block = [&](double (&cf)[B * NC], int lb) {
+        if constexpr (GRAD) {
+            double cr[V];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                cr[2 * b] = cf[4 * b] + cf[4 * b + 2];
+                cr[2 * b + 1] = cf[4 * b + 1] + cf[4 * b + 3];
+            }
+            reduce_add(cr, lb);
+        } else {
+            reduce_add(cf, lb);
+        }
     };
     // Masked block: channels out of range (offset < 0, constant inside a block) get
     // the weight 0 for the block; rescaling and phase update at its end.  Only the
     // final partial block (TAIL) checks the degree bound.
     auto masked_block = [&](int lb, auto tail) {
         constexpr bool TAIL = decltype(tail)::value;
-        double cb[V];
+        double cb[B * NC];
 #pragma unroll
-        for (int k = 0; k < V; ++k)
+        for (int k = 0; k < B * NC; ++k)
             cb[k] = 0.0;
         const double2 *abl = ab + base + lb;
         const bool had_some = some_in;
@@ -749,7 +838,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             const double2 c0 = abl[b];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1 * wa[r], rg[r].b1 * wb[r]);
+                adj_acc_any<SPIN, GRAD, 1>(cb + b * NC, in[r], rg[r].a1 * wa[r], rg[r].b1 * wb[r]);
                 ring_advance<SPIN>(rg[r], c0.x, c0.y);
             }
             if (TAIL && l + 1 > lmax)
@@ -757,8 +846,8 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             const double2 c1 = abl[b + 1];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1 * wa[r],
-                                  rg[r].b1 * wb[r]);
+                adj_acc_any<SPIN, GRAD, -1>(cb + (b + 1) * NC, in[r], rg[r].a1 * wa[r],
+                                            rg[r].b1 * wb[r]);
                 ring_advance<SPIN>(rg[r], c1.x, c1.y);
             }
         }
@@ -772,7 +861,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             some_in = some_in || p != 0;
         }
         if (had_some)  // otherwise every lane was out of range for the whole block
-            reduce_add(cb, lb);
+            reduce_block(cb, lb);
     };
     // Three sequential loops (no loop-carried value crosses a branch merge):
     // masked full blocks until every lane is in range, full plain blocks, and a
@@ -785,9 +874,9 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     if (lb + B - 1 <= lmax) {
         double2 q0 = ab[base + lb], q1 = ab[base + lb + 1];
         for (; lb + B - 1 <= lmax; lb += B) {
-            double cb[V];
+            double cb[B * NC];
 #pragma unroll
-            for (int k = 0; k < V; ++k)
+            for (int k = 0; k < B * NC; ++k)
                 cb[k] = 0.0;
 #pragma unroll
             for (int b = 0; b < B; b += 2) {
@@ -796,15 +885,15 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
                 const double2 n0 = ab[base + lc], n1 = ab[base + lc + 1];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    adj_acc<SPIN, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
+                    adj_acc_any<SPIN, GRAD, 1>(cb + b * NC, in[r], rg[r].a1, rg[r].b1);
                     ring_advance<SPIN>(rg[r], q0.x, q0.y);
-                    adj_acc<SPIN, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
+                    adj_acc_any<SPIN, GRAD, -1>(cb + (b + 1) * NC, in[r], rg[r].a1, rg[r].b1);
                     ring_advance<SPIN>(rg[r], q1.x, q1.y);
                 }
                 q0 = n0;
                 q1 = n1;
             }
-            reduce_add(cb, lb);
+            reduce_block(cb, lb);
         }
     }
     if (lb <= lmax)
@@ -812,39 +901,41 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
 }
 
 template <int R, int B>
-static void adj_launch(const gsht_plan &p, const void *Din, hipStream_t s)
+static void adj_launch(const gsht_plan &p, const void *Din, bool grad, hipStream_t s)
 {
     dim3 blk(64), grd(xcd_grid(p.mmax, p.adj_nchunk));
-#define GSHT_LEG_ADJ(T, SP, C)                                                                   \
-    hipLaunchKernelGGL((leg_adjoint_kernel<T, SP, R, B>), grd, blk, 0, s, p.leg.ab, p.leg.start, \
-                       p.leg.lfirst_adj, (const C *)Din, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,  \
-                       p.npairs, p.adj_nchunk, p.acc)
+#define GSHT_LEG_ADJ(T, SP, G, C)                                                                \
+    hipLaunchKernelGGL((leg_adjoint_kernel<T, SP, R, B, G>), grd, blk, 0, s, p.leg.ab,           \
+                       p.leg.start, p.leg.lfirst_adj, (const C *)Din, p.lmax, p.mmax, p.spin,     \
+                       p.ntheta, p.nd, p.npairs, p.adj_nchunk, p.acc)
     if (p.prec == GSHT_F64) {
-        if (p.spin) GSHT_LEG_ADJ(double, true, double2);
-        else GSHT_LEG_ADJ(double, false, double2);
+        if (p.spin && grad) GSHT_LEG_ADJ(double, true, true, double2);
+        else if (p.spin) GSHT_LEG_ADJ(double, true, false, double2);
+        else GSHT_LEG_ADJ(double, false, false, double2);
     } else {
-        if (p.spin) GSHT_LEG_ADJ(float, true, float2);
-        else GSHT_LEG_ADJ(float, false, float2);
+        if (p.spin && grad) GSHT_LEG_ADJ(float, true, true, float2);
+        else if (p.spin) GSHT_LEG_ADJ(float, true, false, float2);
+        else GSHT_LEG_ADJ(float, false, false, float2);
     }
 #undef GSHT_LEG_ADJ
 }
 
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
 
-hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, hipStream_t s)
+hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s)
 {
     hipError_t e = launch_zero(p.acc, sizeof(double) * (size_t)p.nalm * 2 * p.ncomp, s);
     if (e != hipSuccess)
         return e;
     const int key = p.adj_r * 100 + p.adj_b;
     switch (key) {
-    case 108: adj_launch<1, 8>(p, Din, s); break;
-    case 208: adj_launch<2, 8>(p, Din, s); break;
-    case 204: adj_launch<2, 4>(p, Din, s); break;
-    case 404: adj_launch<4, 4>(p, Din, s); break;
-    case 308: adj_launch<3, 8>(p, Din, s); break;
-    case 304: adj_launch<3, 4>(p, Din, s); break;
-    case 408: adj_launch<4, 8>(p, Din, s); break;
+    case 108: adj_launch<1, 8>(p, Din, grad, s); break;
+    case 208: adj_launch<2, 8>(p, Din, grad, s); break;
+    case 204: adj_launch<2, 4>(p, Din, grad, s); break;
+    case 404: adj_launch<4, 4>(p, Din, grad, s); break;
+    case 308: adj_launch<3, 8>(p, Din, grad, s); break;
+    case 304: adj_launch<3, 4>(p, Din, grad, s); break;
+    case 408: adj_launch<4, 8>(p, Din, grad, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -220,6 +220,19 @@ __global__ void alm_lscale_kernel(const TC *__restrict__ in, int lmax, int mmax,
     }
 }
 
+// out[c][i] = w[i] in[c][i] (quadrature weights applied to a map).
+template <typename T>
+__global__ void map_weight_kernel(const T *__restrict__ in, const double *__restrict__ w,
+                                  int ncomp, int64_t npts, T *__restrict__ out)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += stride) {
+        const double wi = w[i];
+        for (int c = 0; c < ncomp; ++c)
+            out[c * npts + i] = (T)(wi * (double)in[c * npts + i]);
+    }
+}
+
 unsigned elem_blocks(int64_t n)
 {
     const int64_t b = (n + 255) / 256;
@@ -288,6 +301,20 @@ hipError_t launch_spin_phase_vjp(const void *g, const void *lensed, const double
         hipLaunchKernelGGL(spin_phase_vjp_kernel<float>, dim3(elem_blocks(npts)), dim3(256), 0, s,
                            (const float *)g, (const float *)lensed, chi, spin, npts,
                            (float *)g_unrot, g_chi);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_weight(const void *in, const double *w, int ncomp, int64_t npts, int prec,
+                             void *out, hipStream_t s)
+{
+    if (npts == 0)
+        return hipSuccess;
+    if (prec == GSHT_F64)
+        hipLaunchKernelGGL(map_weight_kernel<double>, dim3(elem_blocks(npts)), dim3(256), 0, s,
+                           (const double *)in, w, ncomp, npts, (double *)out);
+    else
+        hipLaunchKernelGGL(map_weight_kernel<float>, dim3(elem_blocks(npts)), dim3(256), 0, s,
+                           (const float *)in, w, ncomp, npts, (float *)out);
     return hipGetLastError();
 }
 

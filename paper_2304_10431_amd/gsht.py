@@ -59,6 +59,8 @@ _SIGS = {
     "gsht_plan_create": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
     "gsht_plan_synth": [_vp, _vp, _vp, _vp],
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
+    "gsht_plan_synth_grad": [_vp, _vp, _vp, _vp],
+    "gsht_plan_adjoint_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_deriv": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gsht_plan_synth_vjp": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "gsht_plan_adjoint_vjp": [_vp, _vp, _vp, _vp],
@@ -73,6 +75,7 @@ _SIGS = {
     "gsht_spin_phase": [_vp, _vp, _i, _i, _i, _i64, _vp],
     "gsht_spin_phase_vjp": [_vp, _vp, _vp, _i, _i, _i64, _vp, _vp, _vp],
     "gsht_alm_lscale": [_vp, _vp, _i, _i, _i, _i, _vp],
+    "gsht_map_weight": [_vp, _vp, _i, _i64, _i, _vp, _vp],
     "gsht_num_stages": [],
     "gsht_stage_name": [_i],
     "gsht_last_error": [],
@@ -201,6 +204,25 @@ class Plan:
                               device=self.device)
         _need(out, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "out")
         _check(_lib.gsht_plan_adjoint(self._h, _ptr(maps), _ptr(out), _stream()))
+        return out
+
+    def synth_grad(self, glm, out=None):
+        """Gradient-only synthesis (C = 0): glm [1][nalm] -> map [2][npts]."""
+        _need(glm, _CDT[self.prec], (1, nalm(self.lmax, self.mmax)), "glm")
+        if out is None:
+            out = torch.empty((self.ncomp, self.npts), dtype=_RDT[self.prec], device=self.device)
+        _need(out, _RDT[self.prec], (self.ncomp, self.npts), "out")
+        _check(_lib.gsht_plan_synth_grad(self._h, _ptr(glm), _ptr(out), _stream()))
+        return out
+
+    def adjoint_grad(self, maps, out=None):
+        """Gradient part of the adjoint: map [2][npts] -> G [1][nalm]."""
+        _need(maps, _RDT[self.prec], (self.ncomp, self.npts), "map")
+        if out is None:
+            out = torch.empty((1, nalm(self.lmax, self.mmax)), dtype=_CDT[self.prec],
+                              device=self.device)
+        _need(out, _CDT[self.prec], (1, nalm(self.lmax, self.mmax)), "out")
+        _check(_lib.gsht_plan_adjoint_grad(self._h, _ptr(maps), _ptr(out), _stream()))
         return out
 
     def synth_deriv(self, alm, want_map=True):
@@ -343,6 +365,19 @@ def spin_phase_vjp(gmap, lensed, chi, spin: int, want_chi=True):
     _check(_lib.gsht_spin_phase_vjp(_ptr(gmap), _ptr(lensed if want_chi else None), _ptr(chi), spin,
                                     prec, npts, _ptr(g_unrot), _ptr(g_chi), _stream()))
     return g_unrot, g_chi
+
+
+def map_weight(maps, weights, out=None):
+    """weights[i] * maps[c][i] (quadrature weights)."""
+    prec = _prec_of(maps)
+    ncomp, npts = maps.shape
+    _need(maps, _RDT[prec], (ncomp, npts), "map")
+    _need(weights, torch.float64, (npts,), "weights")
+    if out is None:
+        out = torch.empty_like(maps)
+    _need(out, _RDT[prec], (ncomp, npts), "out")
+    _check(_lib.gsht_map_weight(_ptr(maps), _ptr(weights), ncomp, npts, prec, _ptr(out), _stream()))
+    return out
 
 
 def alm_lscale(alm, lmax: int, mmax: int, out=None):

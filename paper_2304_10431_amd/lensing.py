@@ -33,10 +33,14 @@ class Lensing:
         cdt = gsht._CDT[prec]
         self.theta = theta
         self.phi = phi
-        glm = torch.stack([plm.to(cdt), (torch.zeros_like(plm) if olm is None else olm).to(cdt)])
-        glm = gsht.alm_lscale(glm.contiguous(), self.lmax_p, self.mmax_p)
         self.dplan = gsht.Plan(theta, phi, self.lmax_p, self.mmax_p, 1, epsilon, precision)
-        self.alpha = self.dplan.synth(glm)
+        if olm is None:   # no curl potential: gradient-only spin-1 synthesis
+            glm = gsht.alm_lscale(plm.to(cdt).reshape(1, -1).contiguous(), self.lmax_p, self.mmax_p)
+            self.alpha = self.dplan.synth_grad(glm)
+        else:
+            glm = torch.stack([plm.to(cdt), olm.to(cdt)]).contiguous()
+            glm = gsht.alm_lscale(glm, self.lmax_p, self.mmax_p)
+            self.alpha = self.dplan.synth(glm)
         self.theta_d, self.phi_d, chi = gsht.deflect(theta, phi, self.alpha, want_chi=spin > 0)
         self.chi = chi
         self.plan = gsht.Plan(self.theta_d, self.phi_d, lmax, mmax, spin, epsilon, precision)
@@ -73,3 +77,30 @@ class Lensing:
         gg, _, _ = self.dplan.synth_vjp(None, g_alpha, True, False, False)
         gp = gsht.alm_lscale(gg, self.lmax_p, self.mmax_p)
         return galm, gp[0], gp[1]
+
+
+class LensedAlm:
+    """Lensed coefficients from unlensed ones (Sect. 4): the lensed map on a grid with
+    quadrature weights (e.g. Gauss-Legendre), then the weighted adjoint synthesis
+    (a standard analysis) up to (lmax_len, mmax_len); ``adjoint`` is the exact
+    adjoint of the whole chain (synthesis on the grid, weights, lensing adjoint)."""
+
+    def __init__(self, theta, phi, weights, plm, lmax: int, mmax: int, lmax_len: int,
+                 mmax_len: int, spin: int, epsilon: float, precision="f64", olm=None,
+                 lmax_p: int | None = None, mmax_p: int | None = None):
+        self.lens = Lensing(theta, phi, plm, lmax, mmax, spin, epsilon, precision, olm=olm,
+                            lmax_p=lmax_p, mmax_p=mmax_p)
+        self.weights = weights
+        self.ana = gsht.Plan(theta, phi, lmax_len, mmax_len, spin, epsilon, precision)
+
+    def close(self):
+        self.lens.close()
+        self.ana.close()
+
+    def forward(self, alm):
+        m = self.lens.forward(alm)
+        return self.ana.adjoint(gsht.map_weight(m, self.weights, out=m))
+
+    def adjoint(self, alm_len):
+        m = self.ana.synth(alm_len)
+        return self.lens.adjoint(gsht.map_weight(m, self.weights, out=m))
