@@ -97,6 +97,23 @@ int gsht_adjoint_synth_general(const void *map, int lmax, int mmax, int spin,
                                double epsilon, gsht_precision prec, void *alm,
                                void *hip_stream);
 
+/*
+ * Map analysis on the minimal equiangular grid (Appendix A): the exact spherical
+ * harmonic coefficients of a band-limited map given on lmax + 2 rings
+ * theta_j = pi j / (lmax + 1) (both poles included) with nphi >= 2 mmax + 1
+ * equidistant points phi_k = 2 pi k / nphi per ring.  The doubled meridian of
+ * 2 lmax + 2 samples determines the field along it; the sin(theta)-weighted
+ * integral is taken exactly in Fourier space and folded back onto the rings
+ * before the adjoint Legendre step.
+ *   map  [ncomp][lmax + 2][nphi] real (prec), ring-major: T, or Q then U;
+ *   alm  [ncomp][nalm] complex (prec), overwritten: a_lm, or G then C.
+ * Exact up to rounding for maps with band limits (lmax, mmax).  Allocates its own
+ * workspace (about (2 mmax + 1) (6 lmax + 6) complex values) and synchronises
+ * hip_stream before returning.
+ */
+int gsht_analysis_minimal(const void *map, int lmax, int mmax, int spin, int nphi,
+                          gsht_precision prec, void *alm, void *hip_stream);
+
 /* Thread-local description of the last non-OK status ("" if none).  Host pointer,
  * valid until the next library call on the same thread. */
 const char *gsht_last_error(void);

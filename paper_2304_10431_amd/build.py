@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsht.so")
 SOURCES = ["capi.cpp", "legendre.hip", "legendre_kernels.hip", "staging.hip", "colfft.hip",
-           "nufft.hip", "lensing.hip"]
+           "nufft.hip", "lensing.hip", "analysis.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1052,6 +1052,112 @@ int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int nthet
     return rc2 == GSHT_OK ? ok() : rc2;
 }
 
+int gsht_analysis_minimal(const void *map, int lmax, int mmax, int spin, int nphi,
+                          gsht_precision prec, void *alm, void *hip_stream)
+{
+    int rc = check_common(lmax, mmax, spin, 0, prec == GSHT_F64 ? 1e-10 : 1e-5, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (nphi < 2 * mmax + 1 || nphi > 1 << 20)
+        return fail(GSHT_EINVAL, "nphi must be in [2 mmax + 1, 2^20], got %d", nphi);
+    if (!map || !alm)
+        return fail(GSHT_EINVAL, "map/alm must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int ntheta = lmax + 2, nd = 2 * lmax + 2, n2 = 2 * nd;
+    const int ncol = spin ? 2 * mmax + 1 : mmax + 1;
+    const size_t cs = prec == GSHT_F64 ? 16 : 8;
+    // weights of the |sin| integral on the fine doubled grid (see analysis.hip)
+    std::vector<double> u(n2);
+    for (int i = 0; i < n2; ++i) {
+        const long double t = 2.0L * (long double)M_PI * i / n2;
+        long double acc = 4.0L;
+        for (int n = 2; n <= 2 * lmax; n += 2)
+            acc += 8.0L * cosl((long double)n * t) / (1.0L - (long double)n * n);
+        u[i] = (double)(acc / n2);
+    }
+    void *P = nullptr, *D = nullptr, *Up = nullptr, *work = nullptr;
+    double *du = nullptr;
+    FFTPlan fphi, fnd, fn2;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (FFTPlan *f : {&fphi, &fnd, &fn2}) {
+            if (f->info) rocfft_execution_info_destroy(f->info);
+            if (f->plan) rocfft_plan_destroy(f->plan);
+        }
+        (void)hipFree(P);
+        (void)hipFree(D);
+        (void)hipFree(Up);
+        (void)hipFree(work);
+        (void)hipFree(du);
+    };
+#define AN_TRY(expr)                                                                              \
+    do {                                                                                         \
+        int rc_ = (expr);                                                                        \
+        if (rc_ != GSHT_OK) {                                                                    \
+            cleanup();                                                                           \
+            return rc_;                                                                          \
+        }                                                                                        \
+    } while (0)
+    auto halloc = [&](void **ptr, size_t bytes) {
+        return hipMalloc(ptr, bytes) == hipSuccess ? GSHT_OK
+                                                   : fail(GSHT_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    };
+    AN_TRY(halloc(&P, (size_t)ntheta * nphi * cs));
+    AN_TRY(halloc(&D, (size_t)ncol * nd * cs));
+    AN_TRY(halloc(&Up, (size_t)ncol * n2 * cs));
+    AN_TRY(halloc((void **)&du, sizeof(double) * n2));
+    AN_TRY(make_fft(fphi, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec,
+                    nphi, ntheta));
+    AN_TRY(make_fft(fnd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, nd,
+                    ncol));
+    AN_TRY(make_fft(fn2, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n2,
+                    ncol));
+    size_t wb = std::max(std::max(fphi.work_bytes, fnd.work_bytes), fn2.work_bytes);
+    if (wb)
+        AN_TRY(halloc(&work, wb));
+    AN_TRY(check_launch(hipMemcpyAsync(du, u.data(), sizeof(double) * n2, hipMemcpyHostToDevice, s),
+                        "weights"));
+    // rings -> phi transforms -> doubled columns (phi quadrature weight 2 pi / nphi)
+    AN_TRY(check_launch(launch_pack_rows(map, spin, (int64_t)ntheta * nphi, prec, P, s), "pack"));
+    AN_TRY(run_fft(fphi, P, nullptr, work, wb, s));
+    AN_TRY(check_launch(launch_gather_cols(P, ntheta, nphi, nd, mmax, spin, ncol,
+                                           2.0 * M_PI / nphi, prec, D, s), "gather"));
+    // theta weights in Fourier space, folded back onto the rings
+    AN_TRY(run_fft(fnd, D, nullptr, work, wb, s));
+    AN_TRY(check_launch(launch_pad_cols(D, nd, n2, lmax, ncol, 1.0 / nd, prec, Up, s), "pad"));
+    AN_TRY(run_fft(fn2, Up, nullptr, work, wb, s));
+    AN_TRY(check_launch(launch_weight_cols(Up, n2, ncol, du, prec, s), "weight"));
+    AN_TRY(run_fft(fn2, Up, nullptr, work, wb, s));
+    AN_TRY(check_launch(launch_trunc_cols(Up, nd, n2, lmax, ncol, 0.5 / nd, prec, D, s), "trunc"));
+    AN_TRY(run_fft(fnd, D, nullptr, work, wb, s));
+    // undoubling and adjoint Legendre step on the lmax + 2 rings
+    gsht_plan *p = new gsht_plan();
+    p->lmax = lmax;
+    p->mmax = mmax;
+    p->spin = spin;
+    p->prec = (int)prec;
+    p->ncomp = spin ? 2 : 1;
+    p->nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+    p->ntheta = ntheta;
+    p->nd = nd;
+    p->ncol = ncol;
+    p->npairs = (ntheta + 1) / 2;
+    if ((rc = setup_legendre(p, s, false)) != GSHT_OK) {
+        free_plan(p);
+        cleanup();
+        return rc;
+    }
+    int rc2 = check_launch(launch_leg_adjoint(*p, D, false, s), "legendre_adjoint");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(launch_leg_finalize(*p, alm, 1.0, false, s), "finalize");
+    if (rc2 == GSHT_OK)
+        rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
+    free_plan(p);
+    cleanup();
+#undef AN_TRY
+    return rc2 == GSHT_OK ? ok() : rc2;
+}
+
 int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int ntheta,
                                 gsht_precision prec, void *alm, void *hip_stream)
 {

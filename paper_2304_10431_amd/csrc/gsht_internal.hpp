@@ -181,6 +181,17 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
 hipError_t build_tile_colors(gsht_plan &p, hipStream_t s);  // after run_binsort
 hipError_t launch_interp(const gsht_plan &p, void *map, hipStream_t s);
 
+// ---- minimal-ring analysis (analysis.hip) ------------------------------------
+hipError_t launch_pack_rows(const void *map, int spin, int64_t n, int prec, void *P, hipStream_t s);
+hipError_t launch_gather_cols(const void *P, int ntheta, int nphi, int nd, int mmax, int spin,
+                              int ncol, double scale, int prec, void *D, hipStream_t s);
+hipError_t launch_pad_cols(const void *X, int n1, int n2, int kmax, int ncol, double scale,
+                           int prec, void *Up, hipStream_t s);
+hipError_t launch_trunc_cols(const void *Up, int n1, int n2, int kmax, int ncol, double scale,
+                             int prec, void *X, hipStream_t s);
+hipError_t launch_weight_cols(void *Up, int n2, int ncol, const double *u, int prec,
+                              hipStream_t s);
+
 // ---- lensing geometry (lensing.hip) ------------------------------------------
 hipError_t launch_deflect(const double *theta, const double *phi, const void *alpha, int prec,
                           int64_t npts, double *theta_out, double *phi_out, double *chi_out,

@@ -76,6 +76,7 @@ _SIGS = {
     "gsht_spin_phase_vjp": [_vp, _vp, _vp, _i, _i, _i64, _vp, _vp, _vp],
     "gsht_alm_lscale": [_vp, _vp, _i, _i, _i, _i, _vp],
     "gsht_map_weight": [_vp, _vp, _i, _i64, _i, _vp, _vp],
+    "gsht_analysis_minimal": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
     "gsht_num_stages": [],
     "gsht_stage_name": [_i],
     "gsht_last_error": [],
@@ -389,6 +390,22 @@ def alm_lscale(alm, lmax: int, mmax: int, out=None):
         out = torch.empty_like(alm)
     _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "out")
     _check(_lib.gsht_alm_lscale(_ptr(alm), _ptr(out), lmax, mmax, ncomp, prec, _stream()))
+    return out
+
+
+def analysis_minimal(maps, lmax: int, mmax: int, spin: int, out=None):
+    """gsht_analysis_minimal: maps [ncomp][lmax + 2][nphi] on the minimal equiangular grid
+    -> a_lm [ncomp][nalm]."""
+    prec = _prec_of(maps)
+    ncomp = 1 if spin == 0 else 2
+    if maps.dim() != 3 or maps.shape[0] != ncomp or maps.shape[1] != lmax + 2:
+        raise ValueError("map must have shape (%d, %d, nphi)" % (ncomp, lmax + 2))
+    _need(maps, _RDT[prec], None, "map")
+    if out is None:
+        out = torch.empty((ncomp, nalm(lmax, mmax)), dtype=_CDT[prec], device=maps.device)
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "out")
+    _check(_lib.gsht_analysis_minimal(_ptr(maps), lmax, mmax, spin, maps.shape[2], prec, _ptr(out),
+                                      _stream()))
     return out
 
 
