@@ -247,6 +247,26 @@ int gsht_map_weight(const void *map_in, const double *weights, int ncomp, int64_
 int gsht_alm_lscale(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp,
                     gsht_precision prec, void *hip_stream);
 
+/* alm_out = f_l alm_in (layout as above) with the real degree factors that map the
+ * lensing potential's coefficients onto the fields of Appendix B:
+ *   kind 0: sqrt(l (l+1))                   spin-1 deflection (= gsht_alm_lscale),
+ *   kind 1: l (l+1) / 2                     spin-0 convergence kappa (omega from the
+ *                                           curl potential),
+ *   kind 2: sqrt((l-1) l (l+1) (l+2)) / 2   spin-2 shear gamma_1 + i gamma_2,
+ * each to be synthesised with the spin given (spin-s sign convention of
+ * eq. forwardpol).  GSHT_EINVAL for other kinds. */
+int gsht_alm_lfactor(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp, int kind,
+                     gsht_precision prec, void *hip_stream);
+
+/* Magnification determinant |A| of the lensing remapping at each point
+ * (Appendix B):  (sin a / a) ((1 - kappa)^2 + omega^2 - gamma^2)
+ *   + (cos a - sin a / a) (1 - kappa - cos(2 beta) gamma_1 - sin(2 beta) gamma_2),
+ * with a = |alpha| and beta the direction of alpha from e_theta.
+ *   alpha [2][npts], kappa [npts], omega [npts] or NULL (= 0), gamma [2][npts]:
+ *   real (prec) device maps; det [npts] FP64 out.  Elementwise, stream-ordered. */
+int gsht_magnification(const void *alpha, const void *kappa, const void *omega, const void *gamma,
+                       gsht_precision prec, int64_t npts, double *det, void *hip_stream);
+
 /* Release a plan and its workspace (NULL is ignored).  Synchronises the device. */
 void gsht_plan_destroy(gsht_plan *p);
 

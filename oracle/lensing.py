@@ -113,3 +113,50 @@ def transport(v, n, ahat, a, steps: int = 2000):
         v = v + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
         s = s + h
     return v
+
+
+def lfactor(alm, lmax: int, mmax: int, kind: int):
+    """f_l alm: kind 1 -> l (l+1) / 2, kind 2 -> sqrt((l-1) l (l+1) (l+2)) / 2."""
+    out = np.array(alm, dtype=np.complex128, copy=True)
+    for m in range(mmax + 1):
+        i0 = alm_index(m, m, lmax)
+        ls = np.arange(m, lmax + 1).astype(float)
+        f = 0.5 * ls * (ls + 1) if kind == 1 else 0.5 * np.sqrt(np.maximum((ls - 1) * ls * (ls + 1) * (ls + 2), 0))
+        out[..., i0:i0 + ls.size] *= f
+    return out
+
+
+def magnification(plm, lmax: int, mmax: int, theta, phi, olm=None):
+    """Appendix B: |A| from the convergence kappa (+ i omega) = (1/2) eth-bar of the
+    spin-1 deflection and the shear gamma = (1/2) eth of it, i.e. the spin-0 synthesis
+    of l(l+1)/2 (phi, Omega) and the spin-2 synthesis of sqrt((l-1)l(l+1)(l+2))/2
+    (phi, Omega) in the sign convention of eq. forwardpol."""
+    alpha = deflection_field(plm, lmax, mmax, theta, phi, olm)
+    kappa = synth(lfactor(plm[None, :], lmax, mmax, 1), lmax, mmax, 0, theta, phi)[0]
+    omega = 0.0 if olm is None else synth(lfactor(olm[None, :], lmax, mmax, 1), lmax, mmax, 0, theta, phi)[0]
+    g = np.zeros((2, nalm(lmax, mmax)), complex)
+    g[0] = plm
+    if olm is not None:
+        g[1] = olm
+    gam = synth(lfactor(g, lmax, mmax, 2), lmax, mmax, 2, theta, phi)
+    a = np.hypot(alpha[0], alpha[1])
+    safe = np.where(a > 0, a, 1.0)
+    sc = np.where(a > 0, np.sin(a) / safe, 1.0)
+    beta = np.arctan2(alpha[1], alpha[0])
+    return (sc * ((1 - kappa) ** 2 + omega ** 2 - gam[0] ** 2 - gam[1] ** 2)
+            + (np.cos(a) - sc) * (1 - kappa - np.cos(2 * beta) * gam[0] - np.sin(2 * beta) * gam[1]))
+
+
+def magnification_fd(plm, lmax: int, mmax: int, theta, phi, olm=None, h: float = 1e-5):
+    """The Jacobian determinant d^2 n' / d^2 n (signed: negative where the remapping
+    folds) by central differences of the deflected point (unit vectors):
+    ((dn'/dtheta x dn'/dphi) . n') / sin(theta)."""
+    def npos(t, p):
+        al = deflection_field(plm, lmax, mmax, t, p, olm)
+        t2, p2, _ = deflect(t, p, al)
+        return basis(t2, p2)[0]
+    dt = (npos(theta + h, phi) - npos(theta - h, phi)) / (2 * h)
+    dp = (npos(theta, phi + h) - npos(theta, phi - h)) / (2 * h)
+    n2 = npos(theta, phi)
+    cr = np.cross(dt.T, dp.T).T
+    return np.sum(cr * n2, axis=0) / np.sin(theta)

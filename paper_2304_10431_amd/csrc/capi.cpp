@@ -894,9 +894,39 @@ int gsht_alm_lscale(const void *alm_in, void *alm_out, int lmax, int mmax, int n
         return fail(GSHT_EINVAL, "need 0 <= mmax <= lmax <= 32766 and ncomp in {1, 2}");
     if (!alm_in || !alm_out)
         return fail(GSHT_EINVAL, "alm_in/alm_out must not be NULL");
-    return check_launch(launch_alm_lscale(alm_in, lmax, mmax, ncomp, prec, alm_out,
+    return check_launch(launch_alm_lscale(alm_in, lmax, mmax, ncomp, 0, prec, alm_out,
                                           (hipStream_t)hip_stream),
                         "alm_lscale");
+}
+
+int gsht_alm_lfactor(const void *alm_in, void *alm_out, int lmax, int mmax, int ncomp, int kind,
+                     gsht_precision prec, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (lmax < 0 || mmax < 0 || mmax > lmax || lmax > 32766 || ncomp < 1 || ncomp > 2)
+        return fail(GSHT_EINVAL, "need 0 <= mmax <= lmax <= 32766 and ncomp in {1, 2}");
+    if (kind < 0 || kind > 2)
+        return fail(GSHT_EINVAL, "kind must be 0, 1 or 2, got %d", kind);
+    if (!alm_in || !alm_out)
+        return fail(GSHT_EINVAL, "alm_in/alm_out must not be NULL");
+    return check_launch(launch_alm_lscale(alm_in, lmax, mmax, ncomp, kind, prec, alm_out,
+                                          (hipStream_t)hip_stream),
+                        "alm_lfactor");
+}
+
+int gsht_magnification(const void *alpha, const void *kappa, const void *omega, const void *gamma,
+                       gsht_precision prec, int64_t npts, double *det, void *hip_stream)
+{
+    if (prec != GSHT_F64 && prec != GSHT_F32)
+        return fail(GSHT_EINVAL, "unknown precision %d", (int)prec);
+    if (npts < 0)
+        return fail(GSHT_EINVAL, "npts must be >= 0");
+    if (npts > 0 && (!alpha || !kappa || !gamma || !det))
+        return fail(GSHT_EINVAL, "alpha/kappa/gamma/det must not be NULL");
+    return check_launch(launch_magnification(alpha, kappa, omega, gamma, prec, npts, det,
+                                             (hipStream_t)hip_stream),
+                        "magnification");
 }
 
 int gsht_synth_general(const void *alm, int lmax, int mmax, int spin, const double *theta,

@@ -206,8 +206,11 @@ hipError_t launch_spin_phase_vjp(const void *g, const void *lensed, const double
                                  hipStream_t s);
 hipError_t launch_map_weight(const void *in, const double *w, int ncomp, int64_t npts, int prec,
                              void *out, hipStream_t s);
-hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int prec, void *out,
-                             hipStream_t s);
+hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int kind, int prec,
+                             void *out, hipStream_t s);
+hipError_t launch_magnification(const void *alpha, const void *kappa, const void *omega,
+                                const void *gamma, int prec, int64_t npts, double *det,
+                                hipStream_t s);
 hipError_t launch_interp_deriv(const gsht_plan &p, void *out_map, void *dth, void *dph,
                               const void *gin, double *gth, double *gph, hipStream_t s);
 hipError_t launch_spread(const gsht_plan &p, const void *map, hipStream_t s);

@@ -201,22 +201,67 @@ __global__ void spin_phase_vjp_kernel(const T *__restrict__ g, const T *__restri
     }
 }
 
-// out = sqrt(l (l + 1)) in, for every stored coefficient of ncomp blocks.
+// out = f_l in for every stored coefficient of ncomp blocks, with
+//   kind 0: f_l = sqrt(l (l + 1))                      (potential -> spin-1 deflection)
+//   kind 1: f_l = l (l + 1) / 2                        (potential -> convergence)
+//   kind 2: f_l = sqrt((l - 1) l (l + 1) (l + 2)) / 2  (potential -> spin-2 shear)
+__device__ inline double l_factor(int kind, int l)
+{
+    const double L = (double)l;
+    if (kind == 0)
+        return sqrt(L * (L + 1.0));
+    if (kind == 1)
+        return 0.5 * L * (L + 1.0);
+    return l >= 1 ? 0.5 * sqrt((L - 1.0) * L * (L + 1.0) * (L + 2.0)) : 0.0;
+}
+
 template <typename TC>
 __global__ void alm_lscale_kernel(const TC *__restrict__ in, int lmax, int mmax, int ncomp,
-                                  int64_t nalm, TC *__restrict__ out)
+                                  int64_t nalm, int kind, TC *__restrict__ out)
 {
     const int m = blockIdx.y;
     const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
     if (l > lmax)
         return;
     const int64_t i = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
-    const double f = sqrt((double)l * (double)(l + 1));
+    const double f = l_factor(kind, l);
     for (int c = 0; c < ncomp; ++c) {
         TC v = in[c * nalm + i];
         v.x = (decltype(v.x))(f * (double)v.x);
         v.y = (decltype(v.y))(f * (double)v.y);
         out[c * nalm + i] = v;
+    }
+}
+
+// Magnification determinant of the remapping n -> n' (Appendix B):
+//   |A| = (sin a / a) ((1 - kappa)^2 + omega^2 - gamma^2)
+//       + (cos a - sin a / a) (1 - kappa - cos(2 beta) gamma_1 - sin(2 beta) gamma_2),
+// beta the direction of alpha from e_theta (cos 2 beta = (a_t^2 - a_p^2) / a^2, ...).
+template <typename T>
+__global__ void magnification_kernel(const T *__restrict__ alpha, const T *__restrict__ kappa,
+                                     const T *__restrict__ omega, const T *__restrict__ gamma,
+                                     int64_t npts, double *__restrict__ det)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += stride) {
+        const double at = alpha[i], ap = alpha[npts + i];
+        const double k = kappa[i], w = omega ? (double)omega[i] : 0.0;
+        const double g1 = gamma[i], g2 = gamma[npts + i];
+        const double q = at * at + ap * ap;
+        double cs, sc;
+        if (q < 1e-4) {
+            cs = 1.0 + q * (-0.5 + q * ((1.0 / 24) + q * ((-1.0 / 720) + (1.0 / 40320) * q)));
+            sc = 1.0 + q * ((-1.0 / 6) + q * ((1.0 / 120) + q * ((-1.0 / 5040) + (1.0 / 362880) * q)));
+        } else {
+            const double a = sqrt(q);
+            double sa;
+            sincos(a, &sa, &cs);
+            sc = sa / a;
+        }
+        const double c2b = q > 0.0 ? (at * at - ap * ap) / q : 1.0;
+        const double s2b = q > 0.0 ? 2.0 * at * ap / q : 0.0;
+        det[i] = sc * ((1.0 - k) * (1.0 - k) + w * w - (g1 * g1 + g2 * g2)) +
+                 (cs - sc) * (1.0 - k - c2b * g1 - s2b * g2);
     }
 }
 
@@ -318,17 +363,34 @@ hipError_t launch_map_weight(const void *in, const double *w, int ncomp, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int prec, void *out,
-                             hipStream_t s)
+hipError_t launch_alm_lscale(const void *in, int lmax, int mmax, int ncomp, int kind, int prec,
+                             void *out, hipStream_t s)
 {
     const int64_t nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
     dim3 blk(256), grd((lmax + 1 + 255) / 256, mmax + 1);
     if (prec == GSHT_F64)
         hipLaunchKernelGGL(alm_lscale_kernel<double2>, grd, blk, 0, s, (const double2 *)in, lmax,
-                           mmax, ncomp, nalm, (double2 *)out);
+                           mmax, ncomp, nalm, kind, (double2 *)out);
     else
         hipLaunchKernelGGL(alm_lscale_kernel<float2>, grd, blk, 0, s, (const float2 *)in, lmax,
-                           mmax, ncomp, nalm, (float2 *)out);
+                           mmax, ncomp, nalm, kind, (float2 *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_magnification(const void *alpha, const void *kappa, const void *omega,
+                                const void *gamma, int prec, int64_t npts, double *det,
+                                hipStream_t s)
+{
+    if (npts == 0)
+        return hipSuccess;
+    if (prec == GSHT_F64)
+        hipLaunchKernelGGL(magnification_kernel<double>, dim3(elem_blocks(npts)), dim3(256), 0, s,
+                           (const double *)alpha, (const double *)kappa, (const double *)omega,
+                           (const double *)gamma, npts, det);
+    else
+        hipLaunchKernelGGL(magnification_kernel<float>, dim3(elem_blocks(npts)), dim3(256), 0, s,
+                           (const float *)alpha, (const float *)kappa, (const float *)omega,
+                           (const float *)gamma, npts, det);
     return hipGetLastError();
 }
 

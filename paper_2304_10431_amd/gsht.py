@@ -76,6 +76,8 @@ _SIGS = {
     "gsht_spin_phase_vjp": [_vp, _vp, _vp, _i, _i, _i64, _vp, _vp, _vp],
     "gsht_alm_lscale": [_vp, _vp, _i, _i, _i, _i, _vp],
     "gsht_map_weight": [_vp, _vp, _i, _i64, _i, _vp, _vp],
+    "gsht_alm_lfactor": [_vp, _vp, _i, _i, _i, _i, _i, _vp],
+    "gsht_magnification": [_vp, _vp, _vp, _vp, _i, _i64, _vp, _vp],
     "gsht_analysis_minimal": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
     "gsht_num_stages": [],
     "gsht_stage_name": [_i],
@@ -407,6 +409,36 @@ def analysis_minimal(maps, lmax: int, mmax: int, spin: int, out=None):
     _check(_lib.gsht_analysis_minimal(_ptr(maps), lmax, mmax, spin, maps.shape[2], prec, _ptr(out),
                                       _stream()))
     return out
+
+
+def alm_lfactor(alm, lmax: int, mmax: int, kind: int, out=None):
+    """f_l times every coefficient (kind 0: sqrt(l(l+1)), 1: l(l+1)/2,
+    2: sqrt((l-1)l(l+1)(l+2))/2)."""
+    prec = _prec_of(alm)
+    ncomp = alm.shape[0]
+    _need(alm, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    if out is None:
+        out = torch.empty_like(alm)
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "out")
+    _check(_lib.gsht_alm_lfactor(_ptr(alm), _ptr(out), lmax, mmax, ncomp, kind, prec, _stream()))
+    return out
+
+
+def magnification(alpha, kappa, gamma, omega=None):
+    """|A| [npts] FP64 from alpha [2][npts], kappa [npts], gamma [2][npts] (omega [npts])."""
+    prec = _prec_of(alpha)
+    npts = alpha.shape[1]
+    _need(alpha, _RDT[prec], (2, npts), "alpha")
+    _need(kappa, _RDT[prec], None, "kappa")
+    _need(gamma, _RDT[prec], (2, npts), "gamma")
+    if kappa.numel() != npts or (omega is not None and omega.numel() != npts):
+        raise ValueError("kappa/omega must have npts entries")
+    if omega is not None:
+        _need(omega, _RDT[prec], None, "omega")
+    det = torch.empty(npts, dtype=torch.float64, device=alpha.device)
+    _check(_lib.gsht_magnification(_ptr(alpha), _ptr(kappa), _ptr(omega), _ptr(gamma), prec, npts,
+                                   _ptr(det), _stream()))
+    return det
 
 
 def last_error() -> str:

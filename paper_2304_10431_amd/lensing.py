@@ -41,6 +41,7 @@ class Lensing:
             glm = torch.stack([plm.to(cdt), olm.to(cdt)]).contiguous()
             glm = gsht.alm_lscale(glm, self.lmax_p, self.mmax_p)
             self.alpha = self.dplan.synth(glm)
+        self._pot = (plm.to(cdt), None if olm is None else olm.to(cdt), epsilon, precision)
         self.theta_d, self.phi_d, chi = gsht.deflect(theta, phi, self.alpha, want_chi=spin > 0)
         self.chi = chi
         self.plan = gsht.Plan(self.theta_d, self.phi_d, lmax, mmax, spin, epsilon, precision)
@@ -61,6 +62,32 @@ class Lensing:
         if self.spin:
             maps = gsht.spin_phase(maps.clone(), self.chi, self.spin, -1)
         return self.plan.adjoint(maps)
+
+    def magnification(self):
+        """|A| at the points (Appendix B): convergence kappa (+ rotation omega) by a spin-0
+        synthesis of l(l+1)/2 (phi_LM, Omega_LM), shear by a spin-2 synthesis of
+        sqrt((l-1)l(l+1)(l+2))/2 (phi_LM, Omega_LM), then gsht_magnification."""
+        plm, olm, eps, prec = self._pot
+        lp, mp = self.lmax_p, self.mmax_p
+        p0 = gsht.Plan(self.theta, self.phi, lp, mp, 0, eps, prec)
+        p2 = gsht.Plan(self.theta, self.phi, lp, mp, 2, eps, prec)
+        kappa = p0.synth(gsht.alm_lfactor(plm.reshape(1, -1).contiguous(), lp, mp, 1))
+        omega = None
+        if olm is not None:
+            omega = p0.synth(gsht.alm_lfactor(olm.reshape(1, -1).contiguous(), lp, mp, 1))
+            gam = p2.synth(gsht.alm_lfactor(torch.stack([plm, olm]).contiguous(), lp, mp, 2))
+        else:
+            gam = p2.synth_grad(gsht.alm_lfactor(plm.reshape(1, -1).contiguous(), lp, mp, 2))
+        det = gsht.magnification(self.alpha, kappa, gam, omega)
+        p0.close()
+        p2.close()
+        return det
+
+    def inverse(self, maps, weights):
+        """Approximate inverse lensing (Appendix B): the adjoint applied to the lensed map
+        times the quadrature weights and the magnification determinant."""
+        w = gsht.map_weight(self.magnification().reshape(1, -1), weights).reshape(-1)
+        return self.adjoint(gsht.map_weight(maps, w))
 
     def vjp(self, alm, gmap, want_alm=True, want_potential=True):
         """Gradients of a real loss L with dL/dmap = gmap (torch's convention for complex

@@ -234,3 +234,50 @@ def test_lensed_alm_pipeline(G, spin):
     assert e0 <= 1e-10
     assert e1 <= 1e-10
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 2e-5)])
+@pytest.mark.parametrize("curl", [False, True])
+def test_magnification_vs_reference(G, prec, tol, curl):
+    from paper_2304_10431_amd.lensing import Lensing
+    say("magnification", prec, curl)
+    lmax_p = 48
+    th, ph = _points(5000, 130)
+    plm = _potential(lmax_p, 131, 2e-2)
+    olm = _potential(lmax_p, 132, 5e-3) if curl else None
+    eps = 1e-10 if prec == "f64" else 1e-5
+    L = Lensing(dev(th), dev(ph), dev(plm), 16, 16, 0, eps, prec,
+                olm=None if olm is None else dev(olm), lmax_p=lmax_p)
+    det = L.magnification().cpu().numpy()
+    L.close()
+    ref = ol.magnification(plm, lmax_p, lmax_p, th, ph, olm)
+    say("  max |A - 1| %.3e, max diff %.3e" % (np.max(np.abs(ref - 1)), np.max(np.abs(det - ref))))
+    assert np.max(np.abs(ref - 1)) > 1e-2
+    assert np.max(np.abs(det - ref)) <= tol
+
+
+def test_inverse_lensing(G):
+    """Appendix B: the adjoint applied to the lensed map times quadrature weights and
+    |A| recovers the unlensed coefficients (approximately: the lensed map is not band
+    limited); the GPU result equals the CPU chain (reference |A|, weights, direct
+    adjoint) within epsilon."""
+    from paper_2304_10431_amd.lensing import Lensing
+    say("inverse lensing")
+    lmax = mmax = 24
+    lmax_p = 16
+    th, ph, w = _gl_grid(3 * lmax, 6 * lmax)
+    a = _alm(0, lmax, mmax, 140, decay=1.5)
+    plm = _potential(lmax_p, 141, 1e-2)
+    L = Lensing(dev(th), dev(ph), dev(plm), lmax, mmax, 0, 1e-10, "f64", lmax_p=lmax_p)
+    t_len = L.forward(dev(a))
+    back = L.inverse(t_len, dev(w)).cpu().numpy()
+    L.close()
+    alpha = ol.deflection_field(plm, lmax_p, lmax_p, th, ph)
+    det = ol.magnification(plm, lmax_p, lmax_p, th, ph)
+    ref = ol.lensed_adjoint((w * det)[None, :] * t_len.cpu().numpy(), lmax, mmax, 0, th, ph, alpha)
+    wm = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    e_ref = oracle.eps_eff(wm * back, wm * ref)
+    e_unl = oracle.eps_eff(wm * back, wm * a)
+    say("  vs CPU chain %.3e, vs unlensed %.3e" % (e_ref, e_unl))
+    assert e_ref <= 1e-9
+    assert e_unl <= 1e-3

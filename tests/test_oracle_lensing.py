@@ -125,3 +125,17 @@ def test_lensed_pair_is_adjoint(spin):
     lhs = float(np.sum(y * f))
     rhs = oracle.alm_inner(a, b, lmax, mmax)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("curl", [False, True])
+def test_magnification_closed_form_vs_jacobian(curl):
+    """Appendix B's |A| (from kappa, omega and the shear) equals the Jacobian
+    determinant of n -> n' taken by central differences."""
+    lmax = mmax = 20
+    plm = _alm(0, lmax, mmax, 13, decay=2.0)[0] * 0.03
+    olm = _alm(0, lmax, mmax, 14, decay=2.0)[0] * 0.01 if curl else None
+    th, ph = _points(100, 15)
+    det = ol.magnification(plm, lmax, mmax, th, ph, olm)
+    fd = ol.magnification_fd(plm, lmax, mmax, th, ph, olm)
+    assert np.max(np.abs(det - 1)) > 0.05                 # non-trivial magnification
+    assert np.max(np.abs(det - fd)) < 1e-7
