@@ -77,7 +77,7 @@ def legendre_flops(lmax, mmax, spin, npairs):
     return per * units * npairs
 
 
-def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup):
+def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0):
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     cdt = torch.complex128 if prec == "f64" else torch.complex64
     t0 = time.time()
@@ -130,6 +130,19 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup):
             "synth_ms": sum(e[0].elapsed_time(e[1]) for e in evg) / steps,
             "adjoint_ms": sum(e[1].elapsed_time(e[2]) for e in evg) / steps}
         m = plan.synth(a, out=m)
+    if many > 1:
+        # several maps on the same plan (one group Legendre kernel per four maps)
+        am = a.unsqueeze(0).repeat(many, 1, 1).contiguous()
+        mm = plan.synth_many(am)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.synth_many(am, out=mm)
+        e1.record()
+        torch.cuda.synchronize()
+        r["synth_many"] = {"maps": many, "synth_ms_per_map": e0.elapsed_time(e1) / steps / many}
+        del am, mm
     return plan, m, r
 
 
@@ -228,6 +241,8 @@ def main():
     ap.add_argument("--workload", default="pollens_thin6144")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--many", type=int, default=4,
+                    help="maps per call for the several-map synthesis timing (FP32 form; 0: off)")
     ap.add_argument("--cpu-nufft", action="store_true",
                     help="also time the plain CPU NUFFT-based SHT on the whole workload "
                          "(FP64, eps 1e-10; minutes at lmax 2048)")
@@ -285,7 +300,8 @@ def main():
     maps = {}
     for prec, eps in forms:
         log("timing %s eps %.0e" % (prec, eps))
-        plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup)
+        plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
+                               many=args.many if prec == "f32" else 0)
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
         maps[key] = m.detach().to(torch.float64).cpu().numpy()
@@ -329,6 +345,7 @@ def main():
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
                       "column_mode": v["info"]["column_mode"],
                       "gradient_only_ms": v.get("gradient_only"),
+                      "synth_many": v.get("synth_many"),
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",

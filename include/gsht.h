@@ -134,6 +134,17 @@ int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin,
  * allocate and does not synchronise.  Calls on one plan must not overlap. */
 int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
 
+/*
+ * Synthesis of nmaps maps sharing the plan's geometry (Sect. 4: many maps deflected
+ * with one set of angles): alm [nmaps][ncomp][nalm] -> map [nmaps][ncomp][npts].
+ * Maps are taken in groups of up to four whose Legendre step runs in one kernel, the
+ * recurrence shared by the group (each map's values as from gsht_plan_synth, up to
+ * rounding); the later steps run per map.  The first call with nmaps >= 2 allocates
+ * the group buffers (about 4 (nalm 4 ncomp 8 + ncol nd csize) bytes), kept until
+ * gsht_plan_destroy; later calls do not allocate.  Does not synchronise.
+ */
+int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream);
+
 /* Adjoint with a plan: map -> alm.  Does not allocate and does not synchronise. */
 int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream);
 

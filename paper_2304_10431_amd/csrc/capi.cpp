@@ -630,12 +630,20 @@ int check_launch(hipError_t e, const char *what)
             return rc_;                                                                        \
     } while (0)
 
+int plan_synth_from_D(gsht_plan *p, hipStream_t s);
+
 // Synthesis up to the oversampled grid (G, or g for spin 0), before interpolation.
 int plan_synth_grid(gsht_plan *p, const void *alm, double mscale, hipStream_t s,
                     bool grad = false)
 {
     RUN(ST_PREP, launch_prep_alm(*p, alm, mscale, grad, s));
     RUN(ST_LEG_SYNTH, launch_leg_synth(*p, p->D, grad, s));
+    return plan_synth_from_D(p, s);
+}
+
+// Doubled columns D -> oversampled grid.
+int plan_synth_from_D(gsht_plan *p, hipStream_t s)
+{
     if (p->colmode == 0) {
         RUNFFT(ST_FFT_D_FWD, run_fft(p->fD_fwd, p->D, nullptr, p->fftwork, p->fftwork_bytes, s));
         RUN(ST_DECONV_FWD, launch_deconv_fwd(*p, s));
@@ -745,6 +753,54 @@ int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream
     if (!alm || (!map && p->npts > 0))
         return fail(GSHT_EINVAL, "alm/map must not be NULL");
     return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+}
+
+int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (nmaps < 0)
+        return fail(GSHT_EINVAL, "nmaps must be >= 0, got %d", nmaps);
+    if (nmaps > 0 && (!alm || (!map && p->npts > 0)))
+        return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t cs = csize(p->prec);
+    const size_t astride = (size_t)p->ncomp * p->nalm * cs;
+    const size_t mstride = (size_t)p->ncomp * p->npts * (cs / 2);
+    const size_t dstride = (size_t)p->ncol * p->nd;  // complex elements per map
+    int rc;
+    for (int k = 0; k < nmaps;) {
+        int nm = nmaps - k >= 4 ? 4 : (nmaps - k >= 2 ? 2 : 1);
+        if (p->syn_r > 2)
+            nm = 1;
+        const char *ak = (const char *)alm + k * astride;
+        char *mk = (char *)map + (map ? k * mstride : 0);
+        if (nm == 1) {
+            if ((rc = plan_synth_impl(p, ak, mk, s)) != GSHT_OK)
+                return rc;
+            k += 1;
+            continue;
+        }
+        if (!p->umulti &&
+            (rc = dev_alloc(p, &p->umulti, sizeof(double) * 4 * 2 * p->ncomp * (size_t)p->nalm)) !=
+                GSHT_OK)
+            return rc;
+        if (!p->Dmulti && (rc = dev_alloc(p, &p->Dmulti, 4 * dstride * cs)) != GSHT_OK)
+            return rc;
+        RUN(ST_PREP, launch_prep_multi(*p, ak, nm, p->umulti, s));
+        RUN(ST_LEG_SYNTH, launch_leg_synth_multi(*p, nm, p->umulti, p->Dmulti, dstride, s));
+        for (int j = 0; j < nm; ++j) {
+            void *dsave = p->D;
+            p->D = (char *)p->Dmulti + j * dstride * cs;
+            rc = plan_synth_from_D(p, s);
+            p->D = dsave;
+            if (rc != GSHT_OK)
+                return rc;
+            RUN(ST_INTERP, launch_interp(*p, mk + j * mstride, s));
+        }
+        k += nm;
+    }
+    return ok();
 }
 
 int gsht_plan_synth_grad(gsht_plan *p, const void *glm, void *map, void *hip_stream)

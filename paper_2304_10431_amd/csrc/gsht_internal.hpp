@@ -123,6 +123,8 @@ struct gsht_plan {
     void *G = nullptr;     // complex grid [nrows][n2] (spin > 0) or half spectrum [nrows][n2/2+1]
     void *g = nullptr;     // real grid [nrows][n2] (spin 0 only)
     double *acc = nullptr; // adjoint accumulators [nalm][2 * ncomp]
+    double *umulti = nullptr;  // several-map coefficients [nalm][4][2 or 4] (on first use)
+    void *Dmulti = nullptr;    // several-map doubled columns [4][ncol][nd] (on first use)
     // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
     // transform and deconvolution in one kernel (theta transform by rocFFT),
     // 2 = doubled transform, deconvolution and theta transform (split into its
@@ -154,6 +156,10 @@ hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s);
 hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, bool grad,
                            hipStream_t s);
 hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, bool grad, hipStream_t s);
+// several maps sharing the plan: nm in {2, 4}, synthesis slices per lane 1 or 2
+hipError_t launch_prep_multi(const gsht_plan &p, const void *alm, int nm, double *u, hipStream_t s);
+hipError_t launch_leg_synth_multi(const gsht_plan &p, int nm, const double *u, void *Dout,
+                                  size_t dstride, hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s);
 hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
                                hipStream_t s);

@@ -187,6 +187,52 @@ hipError_t launch_prep_alm(const gsht_plan &p, const void *alm, double mscale, b
     return hipGetLastError();
 }
 
+// Several maps: u[idx][k][US] for maps k < nm (interleaved per coefficient), each
+// as prep_alm_kernel.  alm holds the nm maps one after the other ([nm][ncomp][nalm]).
+template <typename TC>
+__global__ void prep_multi_kernel(const TC *__restrict__ alm, const double *__restrict__ norm,
+                                  int lmax, int mmax, int s, int64_t nalm, int nm,
+                                  double *__restrict__ u)
+{
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax)
+        return;
+    const int64_t i = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+    const double n = (l < s) ? 0.0 : norm[i];
+    const int ncomp = s ? 2 : 1, us = s ? 4 : 2;
+    for (int k = 0; k < nm; ++k) {
+        const TC *a = alm + (int64_t)k * ncomp * nalm;
+        double *o = u + ((int64_t)i * nm + k) * us;
+        if (s == 0) {
+            const TC c = a[i];
+            o[0] = n * (double)c.x;
+            o[1] = (m == 0) ? 0.0 : n * (double)c.y;
+        } else {
+            const TC gc = a[i], cc = a[nalm + i];
+            const double gr = gc.x, gi = (m == 0) ? 0.0 : (double)gc.y;
+            const double cr = cc.x, ci = (m == 0) ? 0.0 : (double)cc.y;
+            const double sg = (s & 1) ? -1.0 : 1.0;
+            o[0] = -n * (gr - ci);
+            o[1] = -n * (gi + cr);
+            o[2] = -sg * n * (gr + ci);
+            o[3] = -sg * n * (cr - gi);
+        }
+    }
+}
+
+hipError_t launch_prep_multi(const gsht_plan &p, const void *alm, int nm, double *u, hipStream_t s)
+{
+    dim3 blk(256), grd((p.lmax + 1 + 255) / 256, p.mmax + 1);
+    if (p.prec == GSHT_F64)
+        hipLaunchKernelGGL(prep_multi_kernel<double2>, grd, blk, 0, s, (const double2 *)alm,
+                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, nm, u);
+    else
+        hipLaunchKernelGGL(prep_multi_kernel<float2>, grd, blk, 0, s, (const float2 *)alm,
+                           p.leg.norm, p.lmax, p.mmax, p.spin, p.nalm, nm, u);
+    return hipGetLastError();
+}
+
 // S+-, N_l -> output coefficients (gradient/curl split for spin s).
 template <typename TC>
 __global__ void leg_finalize_kernel(const double *__restrict__ acc, const double *__restrict__ norm,

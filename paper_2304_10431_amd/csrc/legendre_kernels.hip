@@ -579,6 +579,172 @@ hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, bool grad, hipStream
     return hipGetLastError();
 }
 
+// ---- synthesis of several maps sharing one geometry --------------------------------
+
+// NM maps at once: the recurrence (both channels) runs once per ring pair and
+// degree and feeds the sums of every map; coefficients are interleaved per degree
+// as u[idx][map][US].  Masked blocks weight the Legendre values by 0/1 per channel
+// (offset 0 or not, constant inside a block) instead of keeping block sums.  The
+// chunking (R slices of 64 ring pairs) is the single-map kernel's, so the dead-chunk
+// table is shared.  Map k's doubled columns start at D + k dstride.
+template <typename T, bool SPIN, int R, int NM>
+__global__ __launch_bounds__(64) void leg_synth_multi_kernel(
+    const double2 *__restrict__ ab, const double *__restrict__ u, const StartInfo *__restrict__ st,
+    const int32_t *__restrict__ lfirst, int lmax, int mmax, int s, int ntheta, int nd, int npairs,
+    int nchunk, size_t dstride, typename cplxk<T>::type *__restrict__ D)
+{
+    constexpr int US = SPIN ? 4 : 2;
+    constexpr int UD = NM * US;  // doubles per degree
+    int m, chunk;
+    xcd_map(nchunk, m, chunk);
+    if (m > mmax)
+        return;
+    const int lane = threadIdx.x;
+    const StartInfo si = st[m];
+    const int l0 = si.l0;
+    const bool live = (l0 <= lmax) && (lfirst[m * nchunk + chunk] <= lmax);
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+
+    Ring rg[R];
+    double c[R][NM][8];
+    bool all_in = true;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = chunk * 64 * R + 64 * r + lane;
+        rg[r] = ring_init<SYN_IN_EXP>(si, q, ntheta, live && q < npairs, SPIN);
+#pragma unroll
+        for (int k = 0; k < NM; ++k)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                c[r][k][j] = 0.0;
+        all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+    }
+    auto masked_block = [&](int lb, auto tail) {
+        constexpr bool TAIL = decltype(tail)::value;
+        double wa[R], wb[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            wa[r] = rg[r].ea == 0 ? 1.0 : 0.0;
+            wb[r] = (SPIN && rg[r].eb == 0) ? 1.0 : 0.0;
+        }
+#pragma unroll 1
+        for (int b = 0; b < LB; b += 2) {
+            const int l = lb + b;
+            if (TAIL && l > lmax)
+                break;
+            const double2 c0 = ab[base + l];
+            const double *u0 = u + UD * (base + l);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double va = rg[r].a1 * wa[r], vb = rg[r].b1 * wb[r];
+#pragma unroll
+                for (int k = 0; k < NM; ++k)
+                    synth_acc<SPIN, 1>(c[r][k], va, vb, u0 + US * k);
+                ring_advance<SPIN>(rg[r], c0.x, c0.y);
+            }
+            if (TAIL && l + 1 > lmax)
+                break;
+            const double2 c1 = ab[base + l + 1];
+            const double *u1 = u0 + UD;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double va = rg[r].a1 * wa[r], vb = rg[r].b1 * wb[r];
+#pragma unroll
+                for (int k = 0; k < NM; ++k)
+                    synth_acc<SPIN, -1>(c[r][k], va, vb, u1 + US * k);
+                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+            }
+        }
+        all_in = true;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ring_rescale<SPIN, SYN_IN_EXP>(rg[r]);
+            all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+        }
+    };
+    if (live) {
+        int lb = l0;
+        for (; lb + LB - 1 <= lmax && !all_in; lb += LB)
+            masked_block(lb, flag<false>());
+        const int lend = lb + ((lmax - lb + 1) / LB) * LB;
+#pragma unroll 1
+        for (; lb < lend; lb += 2) {
+            const double2 c0 = ab[base + lb], c1 = ab[base + lb + 1];
+            const double *u0 = u + UD * (base + lb);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+                for (int k = 0; k < NM; ++k)
+                    synth_acc<SPIN, 1>(c[r][k], rg[r].a1, rg[r].b1, u0 + US * k);
+                ring_advance<SPIN>(rg[r], c0.x, c0.y);
+#pragma unroll
+                for (int k = 0; k < NM; ++k)
+                    synth_acc<SPIN, -1>(c[r][k], rg[r].a1, rg[r].b1, u0 + UD + US * k);
+                ring_advance<SPIN>(rg[r], c1.x, c1.y);
+            }
+        }
+        if (lb <= lmax)
+            masked_block(lb, flag<true>());
+    }
+    const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
+    const double ms = ((s + m) & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int q = chunk * 64 * R + 64 * r + lane;
+        if (q >= npairs)
+            continue;
+        const int jn = q, js = ntheta - 1 - q;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            typename cplxk<T>::type *Dk = D + k * dstride;
+            typename cplxk<T>::type *colp = Dk + (size_t)(SPIN ? m + mmax : m) * nd;
+            put_ring<T>(colp, jn, ntheta, nd, ms, c[r][k][0], c[r][k][1]);
+            if (js != jn)
+                put_ring<T>(colp, js, ntheta, nd, ms, sfix * c[r][k][2], sfix * c[r][k][3]);
+            if (SPIN && m > 0) {
+                typename cplxk<T>::type *colm = Dk + (size_t)(mmax - m) * nd;
+                put_ring<T>(colm, jn, ntheta, nd, ms, c[r][k][4], c[r][k][5]);
+                if (js != jn)
+                    put_ring<T>(colm, js, ntheta, nd, ms, sfix * c[r][k][6], sfix * c[r][k][7]);
+            }
+        }
+    }
+}
+
+template <int R, int NM>
+static void synth_multi_launch(const gsht_plan &p, const double *u, void *Dout, size_t dstride,
+                               hipStream_t s)
+{
+    dim3 blk(64), grd(xcd_grid(p.mmax, p.syn_nchunk));
+#define GSHT_LEG_SYNTH_M(T, SP, C)                                                               \
+    hipLaunchKernelGGL((leg_synth_multi_kernel<T, SP, R, NM>), grd, blk, 0, s, p.leg.ab, u,      \
+                       p.leg.start, p.leg.lfirst_syn, p.lmax, p.mmax, p.spin, p.ntheta, p.nd,     \
+                       p.npairs, p.syn_nchunk, dstride, (C *)Dout)
+    if (p.prec == GSHT_F64) {
+        if (p.spin) GSHT_LEG_SYNTH_M(double, true, double2);
+        else GSHT_LEG_SYNTH_M(double, false, double2);
+    } else {
+        if (p.spin) GSHT_LEG_SYNTH_M(float, true, float2);
+        else GSHT_LEG_SYNTH_M(float, false, float2);
+    }
+#undef GSHT_LEG_SYNTH_M
+}
+
+// nm maps (2 or 4) at once; slices per lane as the plan's synthesis (1 or 2).
+hipError_t launch_leg_synth_multi(const gsht_plan &p, int nm, const double *u, void *Dout,
+                                  size_t dstride, hipStream_t s)
+{
+    const int key = 10 * p.syn_r + nm;
+    switch (key) {
+    case 12: synth_multi_launch<1, 2>(p, u, Dout, dstride, s); break;
+    case 14: synth_multi_launch<1, 4>(p, u, Dout, dstride, s); break;
+    case 22: synth_multi_launch<2, 2>(p, u, Dout, dstride, s); break;
+    case 24: synth_multi_launch<2, 4>(p, u, Dout, dstride, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---- adjoint -----------------------------------------------------------------------
 
 template <typename T>

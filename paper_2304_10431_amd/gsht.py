@@ -60,6 +60,7 @@ _SIGS = {
     "gsht_plan_synth": [_vp, _vp, _vp, _vp],
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_grad": [_vp, _vp, _vp, _vp],
+    "gsht_plan_synth_many": [_vp, _i, _vp, _vp, _vp],
     "gsht_plan_adjoint_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_deriv": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gsht_plan_synth_vjp": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -207,6 +208,16 @@ class Plan:
                               device=self.device)
         _need(out, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "out")
         _check(_lib.gsht_plan_adjoint(self._h, _ptr(maps), _ptr(out), _stream()))
+        return out
+
+    def synth_many(self, alm, out=None):
+        """Several maps on the plan's points: alm [nmaps][ncomp][nalm] -> [nmaps][ncomp][npts]."""
+        nm = alm.shape[0]
+        _need(alm, _CDT[self.prec], (nm, self.ncomp, nalm(self.lmax, self.mmax)), "alm")
+        if out is None:
+            out = torch.empty((nm, self.ncomp, self.npts), dtype=_RDT[self.prec], device=self.device)
+        _need(out, _RDT[self.prec], (nm, self.ncomp, self.npts), "out")
+        _check(_lib.gsht_plan_synth_many(self._h, nm, _ptr(alm), _ptr(out), _stream()))
         return out
 
     def synth_grad(self, glm, out=None):

@@ -1,0 +1,69 @@
+"""Several maps on one plan (gsht_plan_synth_many): the group Legendre kernel shares
+the recurrence between up to four maps; every map must equal its own single-map
+synthesis up to rounding, for group sizes 4, 2 and 1 and both synthesis launch
+shapes that have a group kernel (and the fallback for the other), and stay within
+epsilon of the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2304_10431_amd import gsht
+    return gsht
+
+
+def _alms(nmaps, spin, lmax, mmax, seed):
+    rng = np.random.default_rng(seed)
+    nc = oracle.ncomp(spin)
+    a = (rng.standard_normal((nmaps, nc, oracle.nalm(lmax, mmax)))
+         + 1j * rng.standard_normal((nmaps, nc, oracle.nalm(lmax, mmax)))) / math.sqrt(2)
+    for m in range(mmax + 1):
+        i0 = oracle.alm_index(m, m, lmax)
+        if m == 0:
+            a[..., i0:i0 + lmax + 1] = a[..., i0:i0 + lmax + 1].real
+        a[..., i0:i0 + max(0, spin - m)] = 0
+    return a
+
+
+@pytest.mark.parametrize("syn_r", [1, 2, 4])
+@pytest.mark.parametrize("prec,eps,tol", [("f64", 1e-10, 1e-13), ("f32", 1e-5, 1e-6)])
+@pytest.mark.parametrize("spin,lmax,mmax,npts", [(2, 260, 200, 20000), (0, 300, 300, 20000)])
+def test_many_equals_single(G, monkeypatch, syn_r, prec, eps, tol, spin, lmax, mmax, npts):
+    say("synth_many", syn_r, prec, spin, lmax, mmax)
+    monkeypatch.setenv("GSHT_SYN_R", str(syn_r))
+    rng = np.random.default_rng(lmax + spin)
+    th = np.arccos(rng.uniform(-1, 1, npts))
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    th[:2] = [0.0, np.pi]
+    nmaps = 7                                   # groups of 4, 2 and 1
+    a = _alms(nmaps, spin, lmax, mmax, 77)
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    plan = G.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), lmax, mmax, spin, eps,
+                  prec)
+    ad = torch.from_numpy(a).cuda().to(cdt)
+    many = plan.synth_many(ad).double().cpu().numpy()
+    worst = 0.0
+    for k in range(nmaps):
+        one = plan.synth(ad[k].contiguous()).double().cpu().numpy()
+        worst = max(worst, oracle.eps_eff(many[k], one))
+    ref = oracle.synth(a[5], lmax, mmax, spin, th, ph)
+    e_o = oracle.eps_eff(many[5], ref)
+    plan.close()
+    say("  worst vs single %.3e, map 5 vs oracle %.3e" % (worst, e_o))
+    assert worst <= tol
+    assert e_o <= eps
