@@ -77,11 +77,13 @@ def legendre_flops(lmax, mmax, spin, npairs):
     return per * units * npairs
 
 
-def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0):
+def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, autotune=False):
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     cdt = torch.complex128 if prec == "f64" else torch.complex64
     t0 = time.time()
     plan = gsht.Plan(th, ph, lmax, mmax, spin, eps, prec)
+    if autotune:
+        plan.autotune()
     torch.cuda.synchronize()
     t_plan = time.time() - t0
     a = alm.to(cdt)
@@ -241,6 +243,8 @@ def main():
     ap.add_argument("--workload", default="pollens_thin6144")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let each plan time the Legendre launch shapes and keep the fastest")
     ap.add_argument("--many", type=int, default=4,
                     help="maps per call for the several-map synthesis timing (FP32 form; 0: off)")
     ap.add_argument("--cpu-nufft", action="store_true",
@@ -301,7 +305,7 @@ def main():
     for prec, eps in forms:
         log("timing %s eps %.0e" % (prec, eps))
         plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
-                               many=args.many if prec == "f32" else 0)
+                               many=args.many if prec == "f32" else 0, autotune=args.autotune)
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
         maps[key] = m.detach().to(torch.float64).cpu().numpy()
@@ -344,6 +348,7 @@ def main():
                       "adjoint_ms": v["adjoint_ms"], "plan_s": v["plan_s"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
                       "column_mode": v["info"]["column_mode"],
+                      "legendre_shapes": [v["info"]["syn_r"], v["info"]["adj_r"], v["info"]["adj_b"]],
                       "gradient_only_ms": v.get("gradient_only"),
                       "synth_many": v.get("synth_many"),
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}

@@ -145,6 +145,14 @@ int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
  */
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream);
 
+/* Launch-shape autotuning: times the Legendre synthesis for 1, 2 and 4 slices of 64
+ * ring pairs per wave and the adjoint for every supported (slices, degrees per
+ * reduction block) pair on this plan's sizes, and keeps the fastest of each (the
+ * results of every shape are the same up to rounding).  Overwrites the plan's
+ * internal work buffers only; allocates two small tables; synchronises hip_stream.
+ * The chosen shapes are reported by gsht_plan_get_info. */
+int gsht_plan_autotune(gsht_plan *p, void *hip_stream);
+
 /* Adjoint with a plan: map -> alm.  Does not allocate and does not synchronise. */
 int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream);
 
@@ -305,6 +313,8 @@ typedef struct {
     int spread_colors;  /* > 0: spreading runs tile by tile in this many launches of
                            mutually disjoint patches, flushed without atomics; 0: one
                            workgroup per chunk with an atomic flush */
+    int syn_r;          /* Legendre synthesis: slices of 64 ring pairs per wave */
+    int adj_r, adj_b;   /* Legendre adjoint: slices per wave, degrees per reduction block */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */

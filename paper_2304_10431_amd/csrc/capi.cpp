@@ -755,6 +755,86 @@ int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream
     return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
 }
 
+int gsht_plan_autotune(gsht_plan *p, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (!p->D || !p->uprep)
+        return fail(GSHT_EINVAL, "plan has no Legendre buffers");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nck1 = (p->npairs + 63) / 64;  // chunks at one slice per wave (the most)
+    int32_t *ls = nullptr, *la = nullptr;
+    int rc;
+    if ((rc = dev_alloc(p, &ls, sizeof(int32_t) * (size_t)(p->mmax + 1) * nck1)) != GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &la, sizeof(int32_t) * (size_t)(p->mmax + 1) * nck1)) != GSHT_OK)
+        return rc;
+    HIP_TRY(launch_zero(p->uprep, sizeof(double) * 2 * p->ncomp * (size_t)p->nalm, s));
+    HIP_TRY(launch_zero(p->D, (size_t)p->ncol * p->nd * csize(p->prec), s));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GSHT_EHIP, "hipEventCreate failed");
+    }
+    auto set_shape = [&](int sr, int ar, int ab) {
+        p->syn_r = sr;
+        p->adj_r = ar;
+        p->adj_b = ab;
+        p->syn_nchunk = (p->npairs + 64 * sr - 1) / (64 * sr);
+        p->adj_nchunk = (p->npairs + 64 * ar - 1) / (64 * ar);
+        p->leg.lfirst_syn = ls;
+        p->leg.lfirst_adj = la;
+        return launch_leg_live(*p, s);
+    };
+    // best of two runs of one launch, in ms (negative on a launch error)
+    auto time_ms = [&](auto launch) {
+        float best = -1.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess || launch() != hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return -1.0f;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                return -1.0f;
+            best = (best < 0 || ms < best) ? ms : best;
+        }
+        return best;
+    };
+    const int ar0 = p->adj_r, ab0 = p->adj_b;
+    int best_sr = p->syn_r;
+    float best_t = -1.0f;
+    for (int sr : {1, 2, 4}) {
+        if (set_shape(sr, ar0, ab0) != hipSuccess)
+            break;
+        const float t = time_ms([&] { return launch_leg_synth(*p, p->D, false, s); });
+        if (t >= 0 && (best_t < 0 || t < best_t)) {
+            best_t = t;
+            best_sr = sr;
+        }
+    }
+    int best_ar = ar0, best_ab = ab0;
+    best_t = -1.0f;
+    const int shapes[7][2] = {{1, 8}, {2, 8}, {2, 4}, {4, 4}, {3, 8}, {3, 4}, {4, 8}};
+    for (const auto &sh : shapes) {
+        if (set_shape(best_sr, sh[0], sh[1]) != hipSuccess)
+            break;
+        const float t = time_ms([&] { return launch_leg_adjoint(*p, p->D, false, s); });
+        if (t >= 0 && (best_t < 0 || t < best_t)) {
+            best_t = t;
+            best_ar = sh[0];
+            best_ab = sh[1];
+        }
+    }
+    const hipError_t e = set_shape(best_sr, best_ar, best_ab);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return fail(GSHT_EHIP, "autotune: %s", hipGetErrorString(e));
+    return ok();
+}
+
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream)
 {
     if (!p)
@@ -1042,6 +1122,9 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->workspace_bytes = p->workspace_bytes;
     info->column_mode = p->colmode;
     info->spread_colors = p->ncolors;
+    info->syn_r = p->syn_r;
+    info->adj_r = p->adj_r;
+    info->adj_b = p->adj_b;
     return ok();
 }
 

@@ -46,7 +46,8 @@ class PlanInfo(ctypes.Structure):
                 ("tile1", ctypes.c_int), ("tile2", ctypes.c_int), ("ntile1", ctypes.c_int),
                 ("ntile2", ctypes.c_int), ("nchunks", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("column_mode", ctypes.c_int),
-                ("spread_colors", ctypes.c_int)]
+                ("spread_colors", ctypes.c_int), ("syn_r", ctypes.c_int), ("adj_r", ctypes.c_int),
+                ("adj_b", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -61,6 +62,7 @@ _SIGS = {
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_many": [_vp, _i, _vp, _vp, _vp],
+    "gsht_plan_autotune": [_vp, _vp],
     "gsht_plan_adjoint_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_deriv": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gsht_plan_synth_vjp": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -209,6 +211,13 @@ class Plan:
         _need(out, _CDT[self.prec], (self.ncomp, nalm(self.lmax, self.mmax)), "out")
         _check(_lib.gsht_plan_adjoint(self._h, _ptr(maps), _ptr(out), _stream()))
         return out
+
+    def autotune(self):
+        """Time the Legendre launch shapes on this plan and keep the fastest; returns
+        (syn_r, adj_r, adj_b)."""
+        _check(_lib.gsht_plan_autotune(self._h, _stream()))
+        inf = self.info()
+        return inf["syn_r"], inf["adj_r"], inf["adj_b"]
 
     def synth_many(self, alm, out=None):
         """Several maps on the plan's points: alm [nmaps][ncomp][nalm] -> [nmaps][ncomp][npts]."""
