@@ -258,6 +258,11 @@ void choose_sizes(gsht_plan *p)
     p->nrows = p->n1 / 2 + p->w + 2;
     p->t1 = 32;
     p->t2 = 32;
+    if (const char *e = getenv("GSHT_PATCH_PAD"))
+        p->patch_pad = std::max(0, std::min(16, atoi(e)));
+    p->spread_order = 1;
+    if (const char *e = getenv("GSHT_SPREAD_ORDER"))
+        p->spread_order = atoi(e) ? 1 : 0;
     p->nt1 = (p->nrows + p->t1 - 1) / p->t1;
     p->nt2 = (p->n2 + p->t2 - 1) / p->t2;
     p->ntiles = (int64_t)p->nt1 * p->nt2;

@@ -95,6 +95,8 @@ struct gsht_plan {
     double beta = 0;
     int nrows = 0, a_min = 0;
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
+    int patch_pad = 0;     // extra cells per LDS patch row (bank spreading)
+    int spread_order = 1;  // spreading visit order inside a chunk (see nufft.hip)
     int64_t ntiles = 0, nchunks = 0;
     int ncol = 0, npairs = 0;
     int syn_r = 2;       // ring pairs per lane, Legendre synthesis (slices of 64)

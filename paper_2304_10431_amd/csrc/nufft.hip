@@ -462,6 +462,8 @@ template <> __device__ inline double es_kernel<double>(double z, double beta)
 struct GridGeom {
     double c1, c2, half;
     int a_min, n2, stride, nrows, t1, t2, nt2;
+    int ps;      // row stride of a tile's LDS patch in cells (>= t2 + w - 1)
+    int sorder;  // spreading visit order: 0 = stride coprime to the chunk, 1 = sorted
     int64_t npts;
 };
 
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
         V v{};
         if (r < g.nrows)
             v = grid[(size_t)r * g.stride + c];
-        patch[idx] = v;
+        patch[pr * g.ps + pc] = v;
     }
     __syncthreads();
     for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
         T ar = 0, ai = 0;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const V *rowp = patch + (lr + i) * PC + lc;
+            const V *rowp = patch + (lr + i) * g.ps + lc;
             T sr = 0, si = 0;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_deriv_kernel(
         V v{};
         if (r < g.nrows)
             v = grid[(size_t)r * g.stride + c];
-        patch[idx] = v;
+        patch[pr * g.ps + pc] = v;
     }
     __syncthreads();
     const T cu = (T)g.c1, cv = (T)g.c2;
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_deriv_kernel(
         for (int i = 0; i < W; ++i) {
             T wxi, dwxi;
             es_weight_d<T, W>((fx - (T)i) * sc, beta, wxi, dwxi);
-            const V *rowp = patch + (lr + i) * PC + lc;
+            const V *rowp = patch + (lr + i) * g.ps + lc;
             T s0[NC] = {}, s1[NC] = {};
 #pragma unroll
             for (int j = 0; j < W; ++j) {
@@ -671,7 +673,11 @@ template <> struct SpreadAcc<double> {
     __device__ static U quant(double q) { return (U)__double2ll_rn(q); }
 };
 
-// Type-1 spreading of one chunk.  The chunk's patch accumulates in fixed point:
+// Type-1 spreading of one chunk.  The patch holds the real parts and the imaginary
+// parts in separate planes (row stride g.ps cells), so that the lanes of one atomic
+// instruction, which visit the chunk's points in sorted order and therefore
+// neighbouring cells, fall on distinct LDS banks.  The chunk's patch accumulates in
+// fixed point:
 // every contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with
 // S = sum over the chunk's points of |Re y| + |Im y|, which bounds every cell sum,
 // so the two's-complement integer adds never wrap; the quantisation step is
@@ -691,8 +697,9 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
     const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
     const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    const int plane = PR * g.ps;  // real parts, then imaginary parts (one plane each)
     const int n = ck.z - ck.y;
-    for (int idx = threadIdx.x; idx < PR * PC * NC; idx += NUFFT_THREADS)
+    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
         patch[idx] = 0;
     // bound S of every cell sum
     double s = 0.0;
@@ -716,12 +723,12 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
     if (!(S > 0.0) || !isfinite(S))
         return;  // nothing (finite) to spread; uniform over the block
     const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
-    // Neighbouring sorted points have overlapping windows; visiting the chunk with a
-    // stride coprime to its length keeps the lanes of a wave on distant points, so
-    // that the LDS atomics of one instruction rarely hit the same cell.
+    // Visit order: sorted (default; neighbouring lanes on neighbouring cells, hence
+    // distinct banks), or with a stride coprime to the chunk length (lanes on
+    // distant points: fewer same-cell collisions, more bank conflicts).
     const int stride = (n % 97 == 0) ? 89 : 97;
     for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
-        const int p = ck.y + (int)(((int64_t)k * stride) % n);
+        const int p = ck.y + (g.sorder ? k : (int)(((int64_t)k * stride) % n));
         T wx[W], wy[W];
         int lr, lc;
         point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
@@ -737,12 +744,12 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             const double fr = (double)wx[i] * yr, fi = (double)wx[i] * yi;
-            U *rowp = patch + ((lr + i) * PC + lc) * NC;
+            U *rowp = patch + (lr + i) * g.ps + lc;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                atomicAdd(rowp + NC * j, A::quant(fr * dy[j]));
+                atomicAdd(rowp + j, A::quant(fr * dy[j]));
                 if constexpr (CPLX)
-                    atomicAdd(rowp + NC * j + 1, A::quant(fi * dy[j]));
+                    atomicAdd(rowp + plane + j, A::quant(fi * dy[j]));
             }
         }
     }
@@ -757,8 +764,9 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
         if (c >= g.n2)
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
-        const typename A::S qr = (typename A::S)patch[idx * NC];
-        const typename A::S qi = CPLX ? (typename A::S)patch[idx * NC + 1] : 0;
+        const int pidx = pr * g.ps + pc;
+        const typename A::S qr = (typename A::S)patch[pidx];
+        const typename A::S qi = CPLX ? (typename A::S)patch[plane + pidx] : 0;
         if (ATOMIC) {
             if (qr != 0)
                 unsafeAtomicAdd(dst, (T)((double)qr * inv));
@@ -825,6 +833,8 @@ static GridGeom make_geom(const gsht_plan &p)
     g.t1 = p.t1;
     g.t2 = p.t2;
     g.nt2 = p.nt2;
+    g.ps = p.t2 + p.w - 1 + p.patch_pad;
+    g.sorder = p.spread_order;
     g.npts = p.npts;
     return g;
 }
@@ -833,14 +843,14 @@ template <typename T, int W>
 static hipError_t interp_w(const gsht_plan &p, void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
     if (p.spin) {
-        const size_t sm = (size_t)PR * PC * sizeof(typename cpl<T>::type);
+        const size_t sm = (size_t)PR * PS * sizeof(typename cpl<T>::type);
         hipLaunchKernelGGL((interp_kernel<T, W, true>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm, p.G, g,
                            (T)p.beta, (T *)map);
     } else {
-        const size_t sm = (size_t)PR * PC * sizeof(T);
+        const size_t sm = (size_t)PR * PS * sizeof(T);
         hipLaunchKernelGGL((interp_kernel<T, W, false>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm, p.g, g,
                            (T)p.beta, (T *)map);
@@ -858,13 +868,13 @@ template <typename T, int W>
 static hipError_t interp_deriv_w(const gsht_plan &p, const DerivOut &o, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
     const bool vjp = o.gin != nullptr;
     const dim3 grd((unsigned)p.nchunks), blk(NUFFT_THREADS);
     T *map = (T *)o.map, *dth = (T *)o.dth, *dph = (T *)o.dph;
     const T *gin = (const T *)o.gin;
     if (p.spin) {
-        const size_t sm = (size_t)PR * PC * sizeof(typename cpl<T>::type);
+        const size_t sm = (size_t)PR * PS * sizeof(typename cpl<T>::type);
         if (vjp)
             hipLaunchKernelGGL((interp_deriv_kernel<T, W, true, true>), grd, blk, sm, s, p.chunks,
                                p.sth, p.sph, p.perm, p.G, g, (T)p.beta, map, dth, dph, gin, o.gth,
@@ -874,7 +884,7 @@ static hipError_t interp_deriv_w(const gsht_plan &p, const DerivOut &o, hipStrea
                                p.sth, p.sph, p.perm, p.G, g, (T)p.beta, map, dth, dph, gin, o.gth,
                                o.gph);
     } else {
-        const size_t sm = (size_t)PR * PC * sizeof(T);
+        const size_t sm = (size_t)PR * PS * sizeof(T);
         if (vjp)
             hipLaunchKernelGGL((interp_deriv_kernel<T, W, false, true>), grd, blk, sm, s, p.chunks,
                                p.sth, p.sph, p.perm, p.g, g, (T)p.beta, map, dth, dph, gin, o.gth,
@@ -891,9 +901,9 @@ template <typename T, int W>
 static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PC = p.t2 + W - 1;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
     if (p.ncolors > 0) {
-        const size_t sm = (size_t)PR * PC * (p.spin ? 2 : 1) * sizeof(typename SpreadAcc<T>::U);
+        const size_t sm = (size_t)PR * PS * (p.spin ? 2 : 1) * sizeof(typename SpreadAcc<T>::U);
         for (int c = 0; c < p.ncolors; ++c) {
             const int n = p.color_start[c + 1] - p.color_start[c];
             if (n == 0)
@@ -911,12 +921,12 @@ static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
         return hipGetLastError();
     }
     if (p.spin) {
-        const size_t sm = (size_t)PR * PC * 2 * sizeof(typename SpreadAcc<T>::U);
+        const size_t sm = (size_t)PR * PS * 2 * sizeof(typename SpreadAcc<T>::U);
         hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.G);
     } else {
-        const size_t sm = (size_t)PR * PC * sizeof(typename SpreadAcc<T>::U);
+        const size_t sm = (size_t)PR * PS * sizeof(typename SpreadAcc<T>::U);
         hipLaunchKernelGGL((spread_kernel<T, W, false>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.g);
