@@ -315,6 +315,8 @@ typedef struct {
                            workgroup per chunk with an atomic flush */
     int syn_r;          /* Legendre synthesis: slices of 64 ring pairs per wave */
     int adj_r, adj_b;   /* Legendre adjoint: slices per wave, degrees per reduction block */
+    int row_mode;       /* phi transforms of the grid rows: 1 = in-LDS kernels split by
+                           output parity (complex grids), 0 = library FFT */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */

@@ -373,6 +373,7 @@ int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
         return fail(GSHT_EINVAL, "length %d cannot run as an in-LDS transform", n);
     f.n = n;
     f.npass = (int)rad.size();
+    f.psh = p->lds_psh;
     const long double twopi = 6.283185307179586476925286766559005768L;
     std::vector<long double> re, im;
     int L = n;
@@ -425,6 +426,74 @@ int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
     return GSHT_OK;
 }
 
+// exp(-2 pi i k / n), k < n, in the plan precision.
+int make_twist(gsht_plan *p, void **out, int n, hipStream_t s)
+{
+    const long double twopi = 6.283185307179586476925286766559005768L;
+    int rc;
+    if (p->prec == GSHT_F64) {
+        std::vector<double2> t((size_t)n);
+        for (int k = 0; k < n; ++k) {
+            const long double ang = twopi * (long double)k / (long double)n;
+            t[(size_t)k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+        }
+        if ((rc = dev_alloc(p, out, sizeof(double2) * (size_t)n)) != GSHT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(*out, t.data(), sizeof(double2) * (size_t)n, hipMemcpyHostToDevice, s));
+    } else {
+        std::vector<float2> t((size_t)n);
+        for (int k = 0; k < n; ++k) {
+            const long double ang = twopi * (long double)k / (long double)n;
+            t[(size_t)k] = make_float2((float)cosl(ang), (float)-sinl(ang));
+        }
+        if ((rc = dev_alloc(p, out, sizeof(float2) * (size_t)n)) != GSHT_OK) return rc;
+        HIP_TRY(hipMemcpyAsync(*out, t.data(), sizeof(float2) * (size_t)n, hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSHT_OK;
+}
+
+// Default LDS padding shift of the in-LDS transforms.
+constexpr int kLdsPadShift = 4;
+
+// phi transforms of the grid rows in LDS (complex grids): n2 / 2 > mmax and both
+// n2 / 2 and the 2 mmax + 1 modes within the per-thread capacity of the split kernels.
+// GSHT_ROW_MODE (0, 1) forces a mode for testing.
+int setup_rows(gsht_plan *p, hipStream_t s)
+{
+    int dev = 0, maxsh = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lim = std::min((size_t)maxsh, COL_MAX_BYTES);
+    std::vector<int> rad;
+    const int nh = p->n2 / 2, cap = column_half_maxn(p->prec);
+    const bool fit = p->spin > 0 && p->n2 % 2 == 0 && nh > p->mmax && nh <= cap &&
+                     2 * p->mmax + 1 <= cap && row_lds_bytes(*p) <= lim && col_radices(nh, rad);
+    // The library FFT is the default: the in-LDS row kernels measured slower at lmax
+    // 4096 (FP32 1.04 vs 0.59 ms, FP64 2.2 vs 1.5 ms per direction).
+    int mode = 0;
+    if (const char *e = getenv("GSHT_ROW_MODE")) {
+        const int want = atoi(e);
+        if (want < 0 || want > 1 || (want == 1 && !fit))
+            return fail(GSHT_EINVAL, "GSHT_ROW_MODE=%s is not possible for this plan", e);
+        mode = want;
+    }
+    if (mode == 1 && row_set_lds(p->prec) != hipSuccess) {
+        (void)hipGetLastError();
+        mode = 0;
+    }
+    p->rowmode = mode;
+    if (mode == 0)
+        return GSHT_OK;
+    int rc;
+    if (p->colmode == 2 && p->n1 == p->n2) {
+        p->cf_p = p->cf_h;       // same length, same tables
+        p->twist2 = p->twist;
+        return GSHT_OK;
+    }
+    if ((rc = setup_colfft(p, p->cf_p, nh, s)) != GSHT_OK) return rc;
+    return make_twist(p, &p->twist2, p->n2, s);
+}
+
 // Per-column FFT stage: fuse as much as fits in one workgroup's LDS.  The
 // environment variable GSHT_COLUMN_MODE (0, 1, 2) forces a mode for testing.
 int setup_columns(gsht_plan *p, hipStream_t s)
@@ -433,12 +502,22 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t lim = std::min((size_t)maxsh, COL_MAX_BYTES), cs = csize(p->prec);
+    // LDS padding of the in-LDS transforms: one slot per 2^psh elements (GSHT_LDS_PAD
+    // sets psh for testing; 0 turns the padding off)
+    p->lds_psh = kLdsPadShift;
+    if (const char *pe = getenv("GSHT_LDS_PAD")) {
+        const int v = atoi(pe);
+        if (v != 0 && (v < 2 || v > 30))
+            return fail(GSHT_EINVAL, "GSHT_LDS_PAD=%s is not 0 or in 2..30", pe);
+        p->lds_psh = v == 0 ? 31 : v;
+    }
+    const int psh = p->lds_psh;
     std::vector<int> rad;
     const int nh = p->n1 / 2;
-    const bool fit_d = (size_t)p->nd * cs <= lim && col_radices(p->nd, rad);
+    const bool fit_d = (size_t)lds_pad_n(p->nd, psh) * cs <= lim && col_radices(p->nd, rad);
     const int novl = std::max(0, 2 * p->lmax - nh + 1);  // fold overlap kept in LDS
     const bool fit_2 = fit_d && p->n1 % 2 == 0 && nh > p->lmax &&
-                       (size_t)(std::max(p->nd, nh) + novl) * cs <= lim &&
+                       (size_t)(lds_pad_n(std::max(p->nd, nh), psh) + novl) * cs <= lim &&
                        std::max(p->nd, nh) <= column_half_maxn(p->prec) && col_radices(nh, rad);
     int mode = fit_2 ? 2 : fit_d ? 1 : 0;
     const char *e = getenv("GSHT_COLUMN_MODE");
@@ -545,6 +624,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     }
     // per-column stage, then the rocFFT plans it leaves to rocFFT
     if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
+    if ((rc = setup_rows(p, s)) != GSHT_OK) { free_plan(p); return rc; }
     const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;
     rc = GSHT_OK;
     if (p->colmode == 0) {
@@ -555,7 +635,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
         rc = make_fft(p->fT_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n1, p->ncol);
         if (rc == GSHT_OK) rc = make_fft(p->fT_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n1, p->ncol);
     }
-    if (rc == GSHT_OK) {
+    if (rc == GSHT_OK && p->rowmode == 0) {
         if (spin) {
             rc = make_fft(p->fP_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n2, p->nrows);
             if (rc == GSHT_OK) rc = make_fft(p->fP_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n2, p->nrows);
@@ -658,7 +738,9 @@ int plan_synth_from_D(gsht_plan *p, hipStream_t s)
     if (p->colmode < 2)
         RUNFFT(ST_FFT_THETA_INV, run_fft(p->fT_inv, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
     RUN(ST_TRANSPOSE_FWD, launch_transpose_fwd(*p, s));
-    if (p->spin)
+    if (p->spin && p->rowmode)
+        RUN(ST_FFT_PHI_INV, launch_row_inv(*p, s));
+    else if (p->spin)
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
     else
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, p->g, p->fftwork, p->fftwork_bytes, s));
@@ -696,7 +778,9 @@ int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
     else
         RUN(ST_ZERO_GRID, launch_zero(p->g, (size_t)p->nrows * p->n2 * (cs / 2), s));
     RUN(ST_SPREAD, launch_spread(*p, map, s));
-    if (p->spin)
+    if (p->spin && p->rowmode)
+        RUN(ST_FFT_PHI_FWD, launch_row_fwd(*p, s));
+    else if (p->spin)
         RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
     else
         RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->g, p->G, p->fftwork, p->fftwork_bytes, s));
@@ -1130,6 +1214,7 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->syn_r = p->syn_r;
     info->adj_r = p->adj_r;
     info->adj_b = p->adj_b;
+    info->row_mode = p->rowmode;
     return ok();
 }
 

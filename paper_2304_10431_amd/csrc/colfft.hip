@@ -200,7 +200,7 @@ __device__ inline void dft(C (&v)[R])
 // sub L + j + t s, t < R, and its twiddles w_L^(q j) from tw[j (R - 1) + q - 1]
 // (conjugated for DIR > 0).
 template <typename C, int R, int DIR, int NT>
-__device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s)
+__device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s, int sh)
 {
     const int L = R * s, nb = n / R;
     const double rs = 1.0 / (double)s;  // b / s by an FP64 product: exact for b < 2^26
@@ -210,7 +210,7 @@ __device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s)
         C v[R];
 #pragma unroll
         for (int t = 0; t < R; ++t)
-            v[t] = X[base + t * s];
+            v[t] = X[lds_pos(base + t * s, sh)];
         dft<C, R, DIR>(v);
         if (j != 0) {
             const C *wt = tw + j * (R - 1);
@@ -226,7 +226,7 @@ __device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s)
         }
 #pragma unroll
         for (int t = 0; t < R; ++t)
-            X[base + t * s] = v[t];
+            X[lds_pos(base + t * s, sh)] = v[t];
     }
 }
 
@@ -241,13 +241,13 @@ __device__ void lds_fft(C *X, const ColFFT &f)
         const int s = L / r;
         const C *tw = reinterpret_cast<const C *>(f.tw) + f.twoff[p];
         switch (r) {
-        case 16: dif_pass<C, 16, DIR, NT>(X, tw, f.n, s); break;
-        case 8: dif_pass<C, 8, DIR, NT>(X, tw, f.n, s); break;
-        case 4: dif_pass<C, 4, DIR, NT>(X, tw, f.n, s); break;
-        case 2: dif_pass<C, 2, DIR, NT>(X, tw, f.n, s); break;
-        case 3: dif_pass<C, 3, DIR, NT>(X, tw, f.n, s); break;
-        case 5: dif_pass<C, 5, DIR, NT>(X, tw, f.n, s); break;
-        case 7: dif_pass<C, 7, DIR, NT>(X, tw, f.n, s); break;
+        case 16: dif_pass<C, 16, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 8: dif_pass<C, 8, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 4: dif_pass<C, 4, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 2: dif_pass<C, 2, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 3: dif_pass<C, 3, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 5: dif_pass<C, 5, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 7: dif_pass<C, 7, DIR, NT>(X, tw, f.n, s, f.psh); break;
         default: break;
         }
         L = s;
@@ -321,25 +321,26 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
     constexpr int MAXV = col_half_maxn<T>() / NT;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fd.psh;  // LDS padding shift
     const int col = blockIdx.x, tid = threadIdx.x, nh = fh.n;
     const int m = col_m(a, col);
     const double fm = a.kf2[m < 0 ? -m : m];
     const C *dc = D + (size_t)col * a.nd;
     C *ec = E + (size_t)col * a.n1;
     for (int i = tid; i < a.nd; i += NT)
-        X[i] = dc[i];
+        X[lds_pos(i, sh)] = dc[i];
     __syncthreads();
     lds_fft<C, -1, NT>(X, fd);
     auto chat = [&](int k) {
         const int ak = k < 0 ? -k : k;
-        return scale_c(X[fd.perm[k < 0 ? k + a.nd : k]], a.kf1[ak] * fm);
+        return scale_c(X[lds_pos(fd.perm[k < 0 ? k + a.nd : k], sh)], a.kf1[ak] * fm);
     };
     // Fold: residue i < nh receives c_i (i <= lmax) and c_{i - nh} (i >= nh - lmax).
     // Only the even-row input ye = c_i + c_{i-nh} stays in registers: the odd-row
     // input is t^i (c_i - c_{i-nh}) (t^{-nh} = -1), i.e. t^i (+-ye) where only one
     // term exists; the few residues with both keep c_i - c_{i-nh} in LDS (ovl).
     const int ov0 = nh - a.lmax;
-    C *ovl = X + col_half_lds_n(a.nd, nh);
+    C *ovl = X + lds_pad_n(col_half_lds_n(a.nd, nh), sh);
     C ye[MAXV];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
@@ -371,27 +372,27 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
                 d.x = -d.x;
                 d.y = -d.y;
             }
-            X[i] = cmulc(d, twist[i]);
+            X[lds_pos(i, sh)] = cmulc(d, twist[i]);
         }
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fh);
     for (int i = tid; i < nh; i += NT)
         if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
-            ec[2 * i + 1] = X[fh.perm[i]];
+            ec[2 * i + 1] = X[lds_pos(fh.perm[i], sh)];
     __syncthreads();
     // even rows
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
         const int i = tid + v * NT;
         if (i < nh)
-            X[i] = ye[v];
+            X[lds_pos(i, sh)] = ye[v];
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fh);
     for (int i = tid; i < nh; i += NT)
         if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
-            ec[2 * i] = X[fh.perm[i]];
+            ec[2 * i] = X[lds_pos(fh.perm[i], sh)];
 }
 
 // Mode 2, E column (kept rows; the rest counts as zero) -> D column: the transpose
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
     constexpr int MAXV = col_half_maxn<T>() / NT;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fd.psh;  // LDS padding shift
     const int col = blockIdx.x, tid = threadIdx.x, nh = fh.n;
     const int m = col_m(a, col);
     const double fm = a.kf2[m < 0 ? -m : m];
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
         v.x = v.y = 0;
         if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
             v = ec[2 * i + 1];
-        X[i] = v;
+        X[lds_pos(i, sh)] = v;
     }
     __syncthreads();
     lds_fft<C, -1, NT>(X, fh);
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
         acc[v].x = acc[v].y = 0;
         int k, kh;
         if (i < a.nd && freq(i, k, kh))
-            acc[v] = cmul(X[fh.perm[kh]], twist[k < 0 ? k + a.n1 : k]);
+            acc[v] = cmul(X[lds_pos(fh.perm[kh], sh)], twist[k < 0 ? k + a.n1 : k]);
     }
     __syncthreads();
     // even rows
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
         v.x = v.y = 0;
         if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
             v = ec[2 * i];
-        X[i] = v;
+        X[lds_pos(i, sh)] = v;
     }
     __syncthreads();
     lds_fft<C, -1, NT>(X, fh);
@@ -454,19 +456,147 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
         const int i = tid + v * NT;
         int k, kh;
         if (i < a.nd && freq(i, k, kh))
-            acc[v] = scale_c(cadd(acc[v], X[fh.perm[kh]]), a.kf1[k < 0 ? -k : k] * fm);
+            acc[v] = scale_c(cadd(acc[v], X[lds_pos(fh.perm[kh], sh)]), a.kf1[k < 0 ? -k : k] * fm);
     }
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
         const int i = tid + v * NT;
         if (i < a.nd)
-            X[i] = acc[v];
+            X[lds_pos(i, sh)] = acc[v];
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fd);
     for (int i = tid; i < a.nd; i += NT)
-        dc[i] = X[fd.perm[i]];
+        dc[i] = X[lds_pos(fd.perm[i], sh)];
+}
+
+// ---- phi transforms of the grid rows (complex grids, spin > 0) ---------------------
+
+struct RowArgs {
+    int mmax, n2, nrows;
+};
+
+// Row a of the torus, in place: G[a][b] = sum_{|m| <= mmax} G[a][m mod n2] e^{2 pi i m b / n2}
+// for every b < n2 (only the 2 mmax + 1 mode entries are read).  Split by output
+// parity exactly as column_fwd_half_kernel: with nh = n2 / 2 the even outputs are the
+// length-nh transform of the modes folded modulo nh, the odd outputs that of the
+// folded modes times t^m, t = e^{2 pi i / n2}.  twist[k] = e^{-2 pi i k / n2}.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, col_half_waves<T>()) void row_inv_half_kernel(
+    typename cx<T>::type *__restrict__ G, RowArgs a, ColFFT fh,
+    const typename cx<T>::type *__restrict__ twist)
+{
+    using C = typename cx<T>::type;
+    constexpr int MAXV = col_half_maxn<T>() / NT;
+    extern __shared__ unsigned char smem_raw[];
+    C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fh.psh;  // LDS padding shift
+    const int tid = threadIdx.x, nh = fh.n;
+    C *g = G + (size_t)blockIdx.x * a.n2;
+    const int ov0 = nh - a.mmax;
+    C *ovl = X + lds_pad_n(nh, sh);
+    C ye[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        ye[v].x = ye[v].y = 0;
+        if (i < nh) {
+            C c1, c2;
+            c1.x = c1.y = 0;
+            c2 = c1;
+            if (i <= a.mmax)
+                c1 = g[i];            // m = i
+            if (i >= ov0)
+                c2 = g[i + nh];       // m = i - nh, stored at i - nh + n2
+            ye[v] = cadd(c1, c2);
+            if (i >= ov0 && i <= a.mmax)
+                ovl[i - ov0] = csub(c1, c2);
+        }
+    }
+    __syncthreads();  // every input is read before the row is overwritten
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh) {
+            C d = ye[v];
+            if (i >= ov0 && i <= a.mmax) {
+                d = ovl[i - ov0];
+            } else if (i > a.mmax) {
+                d.x = -d.x;
+                d.y = -d.y;
+            }
+            X[lds_pos(i, sh)] = cmulc(d, twist[i]);
+        }
+    }
+    __syncthreads();
+    lds_fft<C, 1, NT>(X, fh);
+    for (int i = tid; i < nh; i += NT)
+        g[2 * i + 1] = X[lds_pos(fh.perm[i], sh)];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh)
+            X[lds_pos(i, sh)] = ye[v];
+    }
+    __syncthreads();
+    lds_fft<C, 1, NT>(X, fh);
+    for (int i = tid; i < nh; i += NT)
+        g[2 * i] = X[lds_pos(fh.perm[i], sh)];
+}
+
+// Transpose of row_inv_half_kernel, in place: the modes |m| <= mmax of the row,
+// G[a][m mod n2] = sum_b G[a][b] e^{-2 pi i m b / n2} (other entries left as they were).
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, col_half_waves<T>()) void row_fwd_half_kernel(
+    typename cx<T>::type *__restrict__ G, RowArgs a, ColFFT fh,
+    const typename cx<T>::type *__restrict__ twist)
+{
+    using C = typename cx<T>::type;
+    constexpr int MAXV = col_half_maxn<T>() / NT;
+    extern __shared__ unsigned char smem_raw[];
+    C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fh.psh;  // LDS padding shift
+    const int tid = threadIdx.x, nh = fh.n, nm = 2 * a.mmax + 1;
+    C *g = G + (size_t)blockIdx.x * a.n2;
+    for (int i = tid; i < nh; i += NT)
+        X[lds_pos(i, sh)] = g[2 * i + 1];
+    __syncthreads();
+    lds_fft<C, -1, NT>(X, fh);
+    C acc[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int j = tid + v * NT;
+        acc[v].x = acc[v].y = 0;
+        if (j < nm) {
+            const int m = j - a.mmax;
+            const int mh = m < 0 ? m + nh : m;           // |m| < nh
+            acc[v] = cmul(X[lds_pos(fh.perm[mh], sh)], twist[m < 0 ? m + a.n2 : m]);
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nh; i += NT)
+        X[lds_pos(i, sh)] = g[2 * i];
+    __syncthreads();
+    lds_fft<C, -1, NT>(X, fh);
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int j = tid + v * NT;
+        if (j < nm) {
+            const int m = j - a.mmax;
+            acc[v] = cadd(acc[v], X[lds_pos(fh.perm[m < 0 ? m + nh : m], sh)]);
+        }
+    }
+    __syncthreads();  // every input is read before the modes are written
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int j = tid + v * NT;
+        if (j < nm) {
+            const int m = j - a.mmax;
+            g[m < 0 ? m + a.n2 : m] = acc[v];
+        }
+    }
 }
 
 // Mode 1, D column -> zero-padded, deconvolved spectrum over all n1 entries (the
@@ -479,13 +609,14 @@ __global__ __launch_bounds__(COL_THREADS) void column_fwd_kernel(
     using C = typename cx<T>::type;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fd.psh;  // LDS padding shift
     const int col = blockIdx.x, tid = threadIdx.x;
     const int m = col_m(a, col);
     const double fm = a.kf2[m < 0 ? -m : m];
     const C *dc = D + (size_t)col * a.nd;
     C *ec = E + (size_t)col * a.n1;
     for (int i = tid; i < a.nd; i += COL_THREADS)
-        X[i] = dc[i];
+        X[lds_pos(i, sh)] = dc[i];
     __syncthreads();
     lds_fft<C, -1, COL_THREADS>(X, fd);
     for (int i = tid; i < a.n1; i += COL_THREADS) {
@@ -495,7 +626,7 @@ __global__ __launch_bounds__(COL_THREADS) void column_fwd_kernel(
         const int k = (i <= a.n1 / 2) ? i : i - a.n1;
         const int ak = k < 0 ? -k : k;
         if (ak <= a.lmax)
-            o = scale_c(X[fd.perm[k < 0 ? k + a.nd : k]], a.kf1[ak] * fm);
+            o = scale_c(X[lds_pos(fd.perm[k < 0 ? k + a.nd : k], sh)], a.kf1[ak] * fm);
         ec[i] = o;
     }
 }
@@ -509,6 +640,7 @@ __global__ __launch_bounds__(COL_THREADS) void column_adj_kernel(
     using C = typename cx<T>::type;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
+    const int sh = fd.psh;  // LDS padding shift
     const int col = blockIdx.x, tid = threadIdx.x;
     const int m = col_m(a, col);
     const double fm = a.kf2[m < 0 ? -m : m];
@@ -522,12 +654,12 @@ __global__ __launch_bounds__(COL_THREADS) void column_adj_kernel(
         const int ak = k < 0 ? -k : k;
         if (ak <= a.lmax)
             o = scale_c(ec[k < 0 ? k + a.n1 : k], a.kf1[ak] * fm);
-        X[i] = o;
+        X[lds_pos(i, sh)] = o;
     }
     __syncthreads();
     lds_fft<C, 1, COL_THREADS>(X, fd);
     for (int i = tid; i < a.nd; i += COL_THREADS)
-        dc[i] = X[fd.perm[i]];
+        dc[i] = X[lds_pos(fd.perm[i], sh)];
 }
 
 ColArgs col_args(const gsht_plan &p)
@@ -548,8 +680,10 @@ ColArgs col_args(const gsht_plan &p)
 template <typename T>
 size_t col_lds(const gsht_plan &p)
 {
-    const int n = p.colmode == 2 ? col_half_lds_n(p.nd, p.n1 / 2) + col_half_ovl(p.lmax, p.n1 / 2)
-                                 : p.nd;
+    const int sh = p.lds_psh;
+    const int n = p.colmode == 2
+                      ? lds_pad_n(col_half_lds_n(p.nd, p.n1 / 2), sh) + col_half_ovl(p.lmax, p.n1 / 2)
+                      : lds_pad_n(p.nd, sh);
     return sizeof(typename cx<T>::type) * (size_t)n;
 }
 
@@ -607,6 +741,60 @@ void launch_adj(const gsht_plan &p, hipStream_t s)
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t row_set_lds()
+{
+    constexpr int NT = col_half_threads<T>();
+    const int bytes = (int)std::min<size_t>(COL_MAX_BYTES, 163840);
+    hipError_t e = hipFuncSetAttribute((const void *)row_inv_half_kernel<T, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)row_fwd_half_kernel<T, NT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t row_set_lds(int prec) { return prec == GSHT_F64 ? row_set_lds<double>() : row_set_lds<float>(); }
+
+size_t row_lds_bytes(const gsht_plan &p)
+{
+    const int nh = p.n2 / 2;
+    const int novl = std::max(0, 2 * p.mmax - nh + 1);
+    return (size_t)(lds_pad_n(nh, p.lds_psh) + novl) * (p.prec == GSHT_F64 ? 16 : 8);
+}
+
+template <typename T>
+static void launch_rows(const gsht_plan &p, bool inverse, hipStream_t s)
+{
+    constexpr int NT = col_half_threads<T>();
+    using C = typename cx<T>::type;
+    const RowArgs a{p.mmax, p.n2, p.nrows};
+    if (inverse)
+        hipLaunchKernelGGL((row_inv_half_kernel<T, NT>), dim3((unsigned)p.nrows), dim3(NT),
+                           row_lds_bytes(p), s, (C *)p.G, a, p.cf_p, (const C *)p.twist2);
+    else
+        hipLaunchKernelGGL((row_fwd_half_kernel<T, NT>), dim3((unsigned)p.nrows), dim3(NT),
+                           row_lds_bytes(p), s, (C *)p.G, a, p.cf_p, (const C *)p.twist2);
+}
+
+hipError_t launch_row_inv(const gsht_plan &p, hipStream_t s)
+{
+    if (p.prec == GSHT_F64)
+        launch_rows<double>(p, true, s);
+    else
+        launch_rows<float>(p, true, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_fwd(const gsht_plan &p, hipStream_t s)
+{
+    if (p.prec == GSHT_F64)
+        launch_rows<double>(p, false, s);
+    else
+        launch_rows<float>(p, false, s);
+    return hipGetLastError();
+}
 
 hipError_t column_set_lds(const gsht_plan &p)
 {

@@ -43,11 +43,17 @@ struct LegendreTables {
 constexpr int COL_MAXP = 16;
 struct ColFFT {
     int n = 0, npass = 0;
+    int psh = 31;  // LDS padding: one free slot after every 2^psh elements (31: none)
     int radix[COL_MAXP] = {};
     int twoff[COL_MAXP] = {};
     const void *tw = nullptr;
     const int32_t *perm = nullptr;
 };
+// Position of element i of an in-LDS transform buffer with one padding slot after
+// every 2^sh elements (spreads the small-stride passes over the LDS banks), and the
+// slots an n-element buffer then takes.
+__host__ __device__ inline int lds_pos(int i, int sh) { return i + (i >> sh); }
+__host__ __device__ inline int lds_pad_n(int n, int sh) { return sh >= 31 ? n : n + (n >> sh) + 1; }
 // Largest LDS buffer a column workgroup may use.
 constexpr size_t COL_MAX_BYTES = 163840;
 
@@ -132,8 +138,14 @@ struct gsht_plan {
     // 2 = doubled transform, deconvolution and theta transform (split into its
     // even and odd output rows, two transforms of length n1 / 2) in one kernel
     int colmode = 0;
+    int lds_psh = 31;         // LDS padding shift of the in-LDS transforms (31: none)
     gsht::ColFFT cf_d, cf_h;  // lengths nd and n1 / 2
     void *twist = nullptr;    // [n1] exp(-2 pi i k / n1), plan precision (mode 2)
+    // phi transforms of the grid rows: 1 = in-LDS kernels split by output parity
+    // (complex grids only), 0 = library FFT
+    int rowmode = 0;
+    gsht::ColFFT cf_p;        // length n2 / 2
+    void *twist2 = nullptr;   // [n2] exp(-2 pi i k / n2), plan precision
     // FFT plans
     gsht::FFTPlan fD_fwd, fD_inv, fT_inv, fT_fwd, fP_inv, fP_fwd;
     void *fftwork = nullptr;
@@ -176,6 +188,10 @@ hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
 
 // ---- per-column FFT stage (colfft.hip) ------------------------------------
 hipError_t column_set_lds(const gsht_plan &p);                    // once per plan
+hipError_t row_set_lds(int prec);                                  // row kernels' LDS limit
+size_t row_lds_bytes(const gsht_plan &p);
+hipError_t launch_row_inv(const gsht_plan &p, hipStream_t s);     // G rows: modes -> grid
+hipError_t launch_row_fwd(const gsht_plan &p, hipStream_t s);     // G rows: grid -> modes
 int column_half_maxn(int prec);  // largest nd or n1 / 2 of mode 2
 size_t column_lds_bytes(const gsht_plan &p);  // LDS per workgroup of the plan's mode
 hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s);  // D -> E

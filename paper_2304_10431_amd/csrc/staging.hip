@@ -135,7 +135,7 @@ constexpr int TR = 8;
 template <typename T>
 __global__ void transpose_fwd_kernel(const typename cplx2<T>::type *__restrict__ E, int mmax,
                                      int spin, int n1, int n2, int gcols, int nrows, int a_min,
-                                     typename cplx2<T>::type *__restrict__ G)
+                                     int modes_only, typename cplx2<T>::type *__restrict__ G)
 {
     __shared__ typename cplx2<T>::type tile[TT][TT + 1];
     const int b0 = blockIdx.x * TT, r0 = blockIdx.y * TT;
@@ -163,8 +163,12 @@ __global__ void transpose_fwd_kernel(const typename cplx2<T>::type *__restrict__
     __syncthreads();
     for (int yy = ty; yy < TT; yy += TR) {
         const int r = r0 + yy, b = b0 + tx;
-        if (r < nrows && b < gcols)
+        if (r < nrows && b < gcols) {
+            // the in-LDS row transform reads the 2 mmax + 1 mode entries only
+            if (modes_only && b > mmax && b < n2 - mmax)
+                continue;
             G[(size_t)r * gcols + b] = tile[tx][yy];
+        }
     }
 }
 
@@ -221,10 +225,12 @@ hipError_t launch_transpose_fwd(const gsht_plan &p, hipStream_t s)
     dim3 blk(TT, TR), grd((gc + TT - 1) / TT, (p.nrows + TT - 1) / TT);
     if (p.prec == GSHT_F64)
         hipLaunchKernelGGL(transpose_fwd_kernel<double>, grd, blk, 0, s, (const double2 *)p.E,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, (double2 *)p.G);
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.rowmode,
+                           (double2 *)p.G);
     else
         hipLaunchKernelGGL(transpose_fwd_kernel<float>, grd, blk, 0, s, (const float2 *)p.E,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, (float2 *)p.G);
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.rowmode,
+                           (float2 *)p.G);
     return hipGetLastError();
 }
 
