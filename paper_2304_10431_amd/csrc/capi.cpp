@@ -924,6 +924,52 @@ int gsht_plan_autotune(gsht_plan *p, void *hip_stream)
     return ok();
 }
 
+// The matrix-core Legendre step serves FP32 plans (epsilon >= 1e-5) with lmax <= 8192,
+// where every Legendre value times 2^7 fits FP16 (|p_l| <= sqrt((2 l + 1) / 4 pi) / N_l
+// with N_l >= 0.14); GSHT_MANY_MFMA=0 turns it off.
+static bool use_mfma(const gsht_plan *p)
+{
+    if (p->prec != GSHT_F32 || p->lmax > 8192)
+        return false;
+    const char *e = getenv("GSHT_MANY_MFMA");
+    return !(e && atoi(e) == 0);
+}
+
+// Buffers of the matrix-core step, sized for 16 maps: tile offsets per m (16 degrees
+// per block from l0 = max(m, s)), tiles, scales, doubled columns, dead-chunk table.
+static int setup_mfma(gsht_plan *p, hipStream_t s)
+{
+    if (p->mfma_tiles)
+        return GSHT_OK;
+    int rc;
+    std::vector<int64_t> boff((size_t)p->mmax + 1);
+    int64_t nblk = 0;
+    for (int m = 0; m <= p->mmax; ++m) {
+        boff[(size_t)m] = nblk;
+        const int l0 = std::max(m, p->spin);
+        if (l0 <= p->lmax)
+            nblk += (p->lmax - l0 + 16) / 16;
+    }
+    const size_t nt = p->spin ? 2 : 1;
+    const size_t tile_bytes = (size_t)nblk * nt * 2 /* column blocks */ * 2 /* hi, lo */ * 64 * 16;
+    const size_t dstride = (size_t)p->ncol * p->nd;
+    const int nchunk = (p->npairs + 63) / 64;
+    if ((rc = dev_alloc(p, &p->mfma_boff, sizeof(int64_t) * boff.size())) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->mfma_scale, sizeof(float) * 16 * boff.size())) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->mfma_live, sizeof(int32_t) * (size_t)nchunk * boff.size())) != GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &p->Dmfma, 16 * dstride * csize(p->prec))) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->mfma_tiles, tile_bytes)) != GSHT_OK) {
+        p->mfma_tiles = nullptr;
+        return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(p->mfma_boff, boff.data(), sizeof(int64_t) * boff.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_leg_live_r1(*p, p->mfma_live, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSHT_OK;
+}
+
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream)
 {
     if (!p)
@@ -938,7 +984,29 @@ int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, vo
     const size_t mstride = (size_t)p->ncomp * p->npts * (cs / 2);
     const size_t dstride = (size_t)p->ncol * p->nd;  // complex elements per map
     int rc;
+    const bool mfma = use_mfma(p);
     for (int k = 0; k < nmaps;) {
+        if (mfma && nmaps - k >= 8) {  // matrix-core Legendre step, up to 16 maps
+            const int nm = std::min(16, nmaps - k);
+            if ((rc = setup_mfma(p, s)) != GSHT_OK)
+                return rc;
+            const char *ak = (const char *)alm + k * astride;
+            char *mk = (char *)map + (map ? k * mstride : 0);
+            RUN(ST_PREP, launch_prep_mfma(*p, ak, nm, p->mfma_boff, p->mfma_tiles, p->mfma_scale, s));
+            RUN(ST_LEG_SYNTH, launch_leg_synth_mfma(*p, nm, p->mfma_tiles, p->mfma_scale,
+                                                    p->mfma_boff, p->mfma_live, p->Dmfma, dstride, s));
+            for (int j = 0; j < nm; ++j) {
+                void *dsave = p->D;
+                p->D = (char *)p->Dmfma + j * dstride * cs;
+                rc = plan_synth_from_D(p, s);
+                p->D = dsave;
+                if (rc != GSHT_OK)
+                    return rc;
+                RUN(ST_INTERP, launch_interp(*p, mk + j * mstride, s));
+            }
+            k += nm;
+            continue;
+        }
         int nm = nmaps - k >= 4 ? 4 : (nmaps - k >= 2 ? 2 : 1);
         if (p->syn_r > 2)
             nm = 1;

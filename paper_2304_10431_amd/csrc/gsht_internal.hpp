@@ -133,6 +133,12 @@ struct gsht_plan {
     double *acc = nullptr; // adjoint accumulators [nalm][2 * ncomp]
     double *umulti = nullptr;  // several-map coefficients [nalm][4][2 or 4] (on first use)
     void *Dmulti = nullptr;    // several-map doubled columns [4][ncol][nd] (on first use)
+    // matrix-core synthesis of up to 16 maps (FP32 plans, on first use)
+    void *Dmfma = nullptr;         // doubled columns [16][ncol][nd]
+    void *mfma_tiles = nullptr;    // FP16 coefficient tiles (16 maps)
+    int64_t *mfma_boff = nullptr;  // [mmax + 1] first tile block of each m
+    float *mfma_scale = nullptr;   // [mmax + 1][16] output scales
+    int32_t *mfma_live = nullptr;  // dead-chunk table for slices of 64 ring pairs
     // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
     // transform and deconvolution in one kernel (theta transform by rocFFT),
     // 2 = doubled transform, deconvolution and theta transform (split into its
@@ -174,6 +180,15 @@ hipError_t launch_leg_synth(const gsht_plan &p, void *Dout, bool grad, hipStream
 hipError_t launch_prep_multi(const gsht_plan &p, const void *alm, int nm, double *u, hipStream_t s);
 hipError_t launch_leg_synth_multi(const gsht_plan &p, int nm, const double *u, void *Dout,
                                   size_t dstride, hipStream_t s);
+// matrix-core synthesis of nm <= 16 maps (FP32 plans): coefficient tiles and scales,
+// the dead-chunk table of its 64-pair chunks, and the Legendre step itself
+hipError_t launch_prep_mfma(const gsht_plan &p, const void *alm, int nm, const int64_t *boff,
+                            void *tiles, float *oscale, hipStream_t s);
+hipError_t launch_leg_live_r1(const gsht_plan &p, int32_t *lfirst1, hipStream_t s);
+hipError_t launch_leg_synth_mfma(const gsht_plan &p, int nm, const void *tiles,
+                                 const float *oscale, const int64_t *boff,
+                                 const int32_t *lfirst1, void *Dout, size_t dstride,
+                                 hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s);
 hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
                                hipStream_t s);

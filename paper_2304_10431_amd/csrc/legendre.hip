@@ -233,6 +233,128 @@ hipError_t launch_prep_multi(const gsht_plan &p, const void *alm, int nm, double
     return hipGetLastError();
 }
 
+// Coefficient tiles of the matrix-core synthesis of NM = 8 NCB maps (FP32 plans),
+// one workgroup per m.  First the largest |u| of each map's column m gives its
+// scale 2^e (largest scaled value in [2^7, 2^8)) and oscale[m][map] = 2^-e;
+// then every block kb of 16 degrees from l0 = max(m, s) gets, per type t (channel
+// +s, -s), column block c, hi/lo part and lane, the 8 FP16 values of column
+// n = lane % 32 (map 8 c + n / 4, entry n % 4) at degrees l0 + 16 kb + 8 (lane / 32) + j:
+// channel +s: u0, u1, SG u2, SG u3; channel -s: u2, u3, SG u0, SG u1; spin 0: u0, u1,
+// SG u0, SG u1 (u as prep_multi_kernel, SG = (-1)^(l - l0), zero past lmax and for maps
+// >= nm).  The hi part is the FP16 rounding of the scaled value (through FP32), the lo
+// part that of the remainder, both rounded towards zero.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline void mfma_u(const float2 *__restrict__ alm, const double *__restrict__ norm,
+                              int lmax, int m, int s, int64_t nalm, int map, int l, double *u)
+{
+    const int64_t i = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+    const double n = (l < s) ? 0.0 : norm[i];
+    const int ncomp = s ? 2 : 1;
+    const float2 *a = alm + (int64_t)map * ncomp * nalm;
+    if (s == 0) {
+        const float2 c = a[i];
+        u[0] = n * (double)c.x;
+        u[1] = (m == 0) ? 0.0 : n * (double)c.y;
+        u[2] = u[3] = 0.0;
+    } else {
+        const float2 gc = a[i], cc = a[nalm + i];
+        const double gr = gc.x, gi = (m == 0) ? 0.0 : (double)gc.y;
+        const double cr = cc.x, ci = (m == 0) ? 0.0 : (double)cc.y;
+        const double sg = (s & 1) ? -1.0 : 1.0;
+        u[0] = -n * (gr - ci);
+        u[1] = -n * (gi + cr);
+        u[2] = -sg * n * (gr + ci);
+        u[3] = -sg * n * (cr - gi);
+    }
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256) void prep_mfma_kernel(const float2 *__restrict__ alm,
+                                                        const double *__restrict__ norm, int lmax,
+                                                        int s, int64_t nalm, int nm,
+                                                        const int64_t *__restrict__ boff,
+                                                        half8_t *__restrict__ Bt,
+                                                        float *__restrict__ oscale)
+{
+    constexpr int NMX = 8 * NCB;
+    const int m = blockIdx.x;
+    const int l0 = m > s ? m : s;
+    const int nt = s ? 2 : 1;
+    __shared__ unsigned mx[NMX];
+    __shared__ double sc[NMX];
+    if (threadIdx.x < NMX)
+        mx[threadIdx.x] = 0u;
+    __syncthreads();
+    if (l0 <= lmax) {
+        for (int k = 0; k < nm; ++k) {
+            float lm = 0.f;
+            for (int l = l0 + (int)threadIdx.x; l <= lmax; l += blockDim.x) {
+                double u[4];
+                mfma_u(alm, norm, lmax, m, s, nalm, k, l, u);
+                for (int c = 0; c < 4; ++c)
+                    lm = fmaxf(lm, (float)fabs(u[c]));
+            }
+            atomicMax(&mx[k], __float_as_uint(lm));  // non-negative floats order as integers
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NMX) {
+        const float v = __uint_as_float(mx[threadIdx.x]);
+        int e = 0;
+        if (v > 0.f) {
+            e = 7 - ilogbf(v);
+            e = e < -100 ? -100 : (e > 100 ? 100 : e);
+        }
+        sc[threadIdx.x] = ldexp(1.0, e);
+        oscale[m * NMX + threadIdx.x] = ldexpf(1.f, -e);
+    }
+    __syncthreads();
+    if (l0 > lmax)
+        return;
+    const int nkb = (lmax - l0 + 16) / 16;
+    const int per = nt * NCB * 2 * 64;
+    half8_t *out = Bt + boff[m] * per;
+    for (int idx = threadIdx.x; idx < nkb * NCB * 64; idx += blockDim.x) {
+        const int lane = idx % 64, c = (idx / 64) % NCB, kb = idx / (64 * NCB);
+        const int n = lane % 32, map = 8 * c + n / 4, e = n % 4;
+        half8_t v[2][2];
+        for (int j = 0; j < 8; ++j) {
+            const int l = l0 + 16 * kb + 8 * (lane / 32) + j;
+            double u[4] = {0.0, 0.0, 0.0, 0.0};
+            if (map < nm && l <= lmax)
+                mfma_u(alm, norm, lmax, m, s, nalm, map, l, u);
+            const double w = (e < 2 ? 1.0 : (((l - l0) & 1) ? -1.0 : 1.0)) * sc[map];
+            for (int t = 0; t < nt; ++t) {
+                const int src = s == 0 ? (e & 1) : (t == 0 ? e : (e ^ 2));
+                const float f = (float)(w * u[src]);
+                const auto hp = __builtin_amdgcn_cvt_pkrtz(f, 0.f);
+                const auto lp = __builtin_amdgcn_cvt_pkrtz(f - (float)hp[0], 0.f);
+                v[t][0][j] = hp[0];
+                v[t][1][j] = lp[0];
+            }
+        }
+        for (int t = 0; t < nt; ++t)
+            for (int hl = 0; hl < 2; ++hl)
+                out[(int64_t)kb * per + ((t * NCB + c) * 2 + hl) * 64 + lane] = v[t][hl];
+    }
+}
+
+hipError_t launch_prep_mfma(const gsht_plan &p, const void *alm, int nm, const int64_t *boff,
+                            void *Bt, float *oscale, hipStream_t s)
+{
+    if (p.prec != GSHT_F32 || nm < 1 || nm > 16)
+        return hipErrorInvalidValue;
+    dim3 blk(256), grd(p.mmax + 1);
+    if (nm > 8)
+        hipLaunchKernelGGL(prep_mfma_kernel<2>, grd, blk, 0, s, (const float2 *)alm, p.leg.norm,
+                           p.lmax, p.spin, p.nalm, nm, boff, (half8_t *)Bt, oscale);
+    else
+        hipLaunchKernelGGL(prep_mfma_kernel<1>, grd, blk, 0, s, (const float2 *)alm, p.leg.norm,
+                           p.lmax, p.spin, p.nalm, nm, boff, (half8_t *)Bt, oscale);
+    return hipGetLastError();
+}
+
 // S+-, N_l -> output coefficients (gradient/curl split for spin s).
 template <typename TC>
 __global__ void leg_finalize_kernel(const double *__restrict__ acc, const double *__restrict__ norm,

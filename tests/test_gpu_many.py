@@ -67,3 +67,55 @@ def test_many_equals_single(G, monkeypatch, syn_r, prec, eps, tol, spin, lmax, m
     say("  worst vs single %.3e, map 5 vs oracle %.3e" % (worst, e_o))
     assert worst <= tol
     assert e_o <= eps
+
+
+def _spectrum_alms(nmaps, spin, lmax, mmax, seed):
+    """Gaussian a_lm with C_l = 1 / (l + 1)^2 (large dynamic range over l), map
+    amplitudes spread over eight decades, and one all-zero map."""
+    a = _alms(nmaps, spin, lmax, mmax, seed)
+    for m in range(mmax + 1):
+        i0 = oracle.alm_index(m, m, lmax)
+        a[..., i0:i0 + lmax + 1 - m] /= np.arange(m, lmax + 1) + 1.0
+    a *= np.logspace(-4, 4, nmaps)[:, None, None]
+    a[3] = 0
+    return a
+
+
+@pytest.mark.parametrize("spin,lmax,mmax,npts,nmaps", [(2, 260, 200, 20000, 16),
+                                                       (0, 300, 300, 20000, 16),
+                                                       (1, 131, 131, 8000, 8),
+                                                       (3, 77, 50, 6000, 21),
+                                                       (2, 40, 40, 3000, 11)])
+def test_many_mfma(G, monkeypatch, spin, lmax, mmax, npts, nmaps):
+    """FP32 plans run groups of 8 to 16 maps through the matrix-core Legendre step
+    (FP16 hi/lo products, FP32 accumulation); every map must stay within a few
+    1e-7 of its own single-map synthesis (FP64 Legendre step) and within epsilon of
+    the oracle, whatever its amplitude; GSHT_MANY_MFMA=0 falls back to the FP64
+    group kernel."""
+    say("synth_many mfma", spin, lmax, mmax, npts, nmaps)
+    rng = np.random.default_rng(lmax + 10 * spin)
+    th = np.arccos(rng.uniform(-1, 1, npts))
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    th[:2] = [0.0, np.pi]
+    a = _spectrum_alms(nmaps, spin, lmax, mmax, 91)
+    plan = G.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), lmax, mmax, spin, 1e-5,
+                  "f32")
+    ad = torch.from_numpy(a).cuda().to(torch.complex64)
+    many = plan.synth_many(ad).double().cpu().numpy()
+    monkeypatch.setenv("GSHT_MANY_MFMA", "0")
+    valu = plan.synth_many(ad).double().cpu().numpy()
+    worst = worst_valu = 0.0
+    for k in range(nmaps):
+        one = plan.synth(ad[k].contiguous()).double().cpu().numpy()
+        if k == 3:
+            assert np.all(many[k] == 0) and np.all(one == 0)
+            continue
+        worst = max(worst, oracle.eps_eff(many[k], one))
+        worst_valu = max(worst_valu, oracle.eps_eff(valu[k], one))
+    plan.close()
+    e_o = [oracle.eps_eff(many[k], oracle.synth(a[k], lmax, mmax, spin, th, ph)) for k in (0, nmaps - 1)]
+    say("  worst vs single: mfma %.3e, fp64 group %.3e; vs oracle %.3e %.3e"
+        % (worst, worst_valu, e_o[0], e_o[1]))
+    assert worst <= 1e-6
+    assert worst_valu <= 1e-6
+    assert max(e_o) <= 1e-5
