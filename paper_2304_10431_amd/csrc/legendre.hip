@@ -242,7 +242,9 @@ hipError_t launch_prep_multi(const gsht_plan &p, const void *alm, int nm, double
 // channel +s: u0, u1, SG u2, SG u3; channel -s: u2, u3, SG u0, SG u1; spin 0: u0, u1,
 // SG u0, SG u1 (u as prep_multi_kernel, SG = (-1)^(l - l0), zero past lmax and for maps
 // >= nm).  The hi part is the FP16 rounding of the scaled value (through FP32), the lo
-// part that of the remainder, both rounded towards zero.
+// part that of the remainder, both rounded towards zero.  Per block the 16 x 16
+// (degree, map) coefficients are formed once (16 threads per map, consecutive
+// degrees, so the reads coalesce) and staged in LDS for the tile writes.
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
 __device__ inline void mfma_u(const float2 *__restrict__ alm, const double *__restrict__ norm,
@@ -281,33 +283,36 @@ __global__ __launch_bounds__(256) void prep_mfma_kernel(const float2 *__restrict
     const int m = blockIdx.x;
     const int l0 = m > s ? m : s;
     const int nt = s ? 2 : 1;
+    const int tid = threadIdx.x;
+    // thread -> (map, degree offset): 16 consecutive threads read 16 consecutive
+    // degrees of one map
+    const int tmap = tid / 16, tk = tid % 16;
     __shared__ unsigned mx[NMX];
     __shared__ double sc[NMX];
-    if (threadIdx.x < NMX)
-        mx[threadIdx.x] = 0u;
+    __shared__ float U[NMX][4][16];  // scaled u of one block of 16 degrees
+    if (tid < NMX)
+        mx[tid] = 0u;
     __syncthreads();
-    if (l0 <= lmax) {
-        for (int k = 0; k < nm; ++k) {
-            float lm = 0.f;
-            for (int l = l0 + (int)threadIdx.x; l <= lmax; l += blockDim.x) {
-                double u[4];
-                mfma_u(alm, norm, lmax, m, s, nalm, k, l, u);
-                for (int c = 0; c < 4; ++c)
-                    lm = fmaxf(lm, (float)fabs(u[c]));
-            }
-            atomicMax(&mx[k], __float_as_uint(lm));  // non-negative floats order as integers
+    if (l0 <= lmax && tmap < nm) {
+        float lm = 0.f;
+        for (int l = l0 + tk; l <= lmax; l += 16) {
+            double u[4];
+            mfma_u(alm, norm, lmax, m, s, nalm, tmap, l, u);
+            for (int c = 0; c < 4; ++c)
+                lm = fmaxf(lm, (float)fabs(u[c]));
         }
+        atomicMax(&mx[tmap], __float_as_uint(lm));  // non-negative floats order as integers
     }
     __syncthreads();
-    if (threadIdx.x < NMX) {
-        const float v = __uint_as_float(mx[threadIdx.x]);
+    if (tid < NMX) {
+        const float v = __uint_as_float(mx[tid]);
         int e = 0;
         if (v > 0.f) {
             e = 7 - ilogbf(v);
             e = e < -100 ? -100 : (e > 100 ? 100 : e);
         }
-        sc[threadIdx.x] = ldexp(1.0, e);
-        oscale[m * NMX + threadIdx.x] = ldexpf(1.f, -e);
+        sc[tid] = ldexp(1.0, e);
+        oscale[m * NMX + tid] = ldexpf(1.f, -e);
     }
     __syncthreads();
     if (l0 > lmax)
@@ -315,28 +320,32 @@ __global__ __launch_bounds__(256) void prep_mfma_kernel(const float2 *__restrict
     const int nkb = (lmax - l0 + 16) / 16;
     const int per = nt * NCB * 2 * 64;
     half8_t *out = Bt + boff[m] * per;
-    for (int idx = threadIdx.x; idx < nkb * NCB * 64; idx += blockDim.x) {
-        const int lane = idx % 64, c = (idx / 64) % NCB, kb = idx / (64 * NCB);
-        const int n = lane % 32, map = 8 * c + n / 4, e = n % 4;
-        half8_t v[2][2];
-        for (int j = 0; j < 8; ++j) {
-            const int l = l0 + 16 * kb + 8 * (lane / 32) + j;
+    for (int kb = 0; kb < nkb; ++kb) {
+        const int lb = l0 + 16 * kb;
+        if (tmap < NMX) {
             double u[4] = {0.0, 0.0, 0.0, 0.0};
-            if (map < nm && l <= lmax)
-                mfma_u(alm, norm, lmax, m, s, nalm, map, l, u);
-            const double w = (e < 2 ? 1.0 : (((l - l0) & 1) ? -1.0 : 1.0)) * sc[map];
-            for (int t = 0; t < nt; ++t) {
-                const int src = s == 0 ? (e & 1) : (t == 0 ? e : (e ^ 2));
-                const float f = (float)(w * u[src]);
-                const auto hp = __builtin_amdgcn_cvt_pkrtz(f, 0.f);
-                const auto lp = __builtin_amdgcn_cvt_pkrtz(f - (float)hp[0], 0.f);
-                v[t][0][j] = hp[0];
-                v[t][1][j] = lp[0];
-            }
+            if (tmap < nm && lb + tk <= lmax)
+                mfma_u(alm, norm, lmax, m, s, nalm, tmap, lb + tk, u);
+            for (int c = 0; c < 4; ++c)
+                U[tmap][c][tk] = (float)(u[c] * sc[tmap]);
         }
-        for (int t = 0; t < nt; ++t)
-            for (int hl = 0; hl < 2; ++hl)
-                out[(int64_t)kb * per + ((t * NCB + c) * 2 + hl) * 64 + lane] = v[t][hl];
+        __syncthreads();
+        for (int idx = tid; idx < per; idx += blockDim.x) {
+            const int lane = idx % 64, hl = (idx / 64) % 2, c = (idx / 128) % NCB;
+            const int t = idx / (128 * NCB);
+            const int n = lane % 32, map = 8 * c + n / 4, e = n % 4;
+            const int src = s == 0 ? (e & 1) : (t == 0 ? e : (e ^ 2));
+            half8_t v;
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * (lane / 32) + j;
+                const float sg = (e >= 2 && ((lb + k - l0) & 1)) ? -1.f : 1.f;
+                const float f = sg * U[map][src][k];
+                const auto hp = __builtin_amdgcn_cvt_pkrtz(f, 0.f);
+                v[j] = hl == 0 ? hp[0] : __builtin_amdgcn_cvt_pkrtz(f - (float)hp[0], 0.f)[0];
+            }
+            out[(int64_t)kb * per + idx] = v;
+        }
+        __syncthreads();
     }
 }
 
