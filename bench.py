@@ -133,8 +133,10 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
             "adjoint_ms": sum(e[1].elapsed_time(e[2]) for e in evg) / steps}
         m = plan.synth(a, out=m)
     if many > 1:
-        # several maps on the same plan (one group Legendre kernel per four maps)
+        # several maps on the same plan: FP32 plans take groups of 8..16 maps through the
+        # matrix-core Legendre step, smaller groups (and FP64) through the FP64 group kernel
         am = a.unsqueeze(0).repeat(many, 1, 1).contiguous()
+        am *= torch.linspace(0.5, 2.0, many, device=am.device).to(am.dtype)[:, None, None]
         mm = plan.synth_many(am)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -143,8 +145,19 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
             plan.synth_many(am, out=mm)
         e1.record()
         torch.cuda.synchronize()
-        r["synth_many"] = {"maps": many, "synth_ms_per_map": e0.elapsed_time(e1) / steps / many}
-        del am, mm
+        r["synth_many"] = {"maps": many, "synth_ms_per_map": e0.elapsed_time(e1) / steps / many,
+                           "legendre": "mfma" if (prec == "f32" and many >= 8) else "fp64"}
+        plan.set_profiling(True)
+        plan.synth_many(am, out=mm)
+        st = plan.stage_times()
+        plan.set_profiling(False)
+        r["synth_many"]["legendre_ms_per_map"] = st["legendre_synth"][0] / many
+        r["synth_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
+        # accuracy of the last map against its own single-map synthesis
+        one = plan.synth(am[many - 1].contiguous())
+        r["synth_many"]["eps_vs_single"] = float(torch.linalg.norm((mm[many - 1] - one).double())
+                                                 / torch.linalg.norm(one.double()))
+        del am, mm, one
     return plan, m, r
 
 
@@ -245,7 +258,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="let each plan time the Legendre launch shapes and keep the fastest")
-    ap.add_argument("--many", type=int, default=4,
+    ap.add_argument("--many", type=int, default=16,
                     help="maps per call for the several-map synthesis timing (FP32 form; 0: off)")
     ap.add_argument("--cpu-nufft", action="store_true",
                     help="also time the plain CPU NUFFT-based SHT on the whole workload "

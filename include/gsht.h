@@ -137,11 +137,17 @@ int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
 /*
  * Synthesis of nmaps maps sharing the plan's geometry (Sect. 4: many maps deflected
  * with one set of angles): alm [nmaps][ncomp][nalm] -> map [nmaps][ncomp][npts].
- * Maps are taken in groups of up to four whose Legendre step runs in one kernel, the
- * recurrence shared by the group (each map's values as from gsht_plan_synth, up to
- * rounding); the later steps run per map.  The first call with nmaps >= 2 allocates
- * the group buffers (about 4 (nalm 4 ncomp 8 + ncol nd csize) bytes), kept until
- * gsht_plan_destroy; later calls do not allocate.  Does not synchronise.
+ * Maps are taken in groups whose Legendre step runs in one kernel, the recurrence
+ * shared by the group; the later steps run per map.  FP32 plans with lmax <= 8192
+ * take groups of 8 to 16 maps through the matrix cores (FP16 hi/lo split products,
+ * FP32 accumulation: each map within about 1e-6 relative of its gsht_plan_synth
+ * result); remaining maps, and FP64 plans, go in groups of up to four through the
+ * FP64 kernel (each map's values as from gsht_plan_synth, up to rounding).  The
+ * environment variable GSHT_MANY_MFMA=0 turns the matrix-core path off.  The first
+ * call needing a group kind allocates its buffers (FP64 groups: about
+ * 4 (nalm 4 ncomp 8 + ncol nd csize) bytes; matrix-core groups: about
+ * 16 ncol nd 8 + nalm ncomp 64 bytes), kept until gsht_plan_destroy; later calls do
+ * not allocate.  Does not synchronise.
  */
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream);
 
