@@ -146,7 +146,7 @@ int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
  * environment variable GSHT_MANY_MFMA=0 turns the matrix-core path off.  The first
  * call needing a group kind allocates its buffers (FP64 groups: about
  * 4 (nalm 4 ncomp 8 + ncol nd csize) bytes; matrix-core groups: about
- * 16 ncol nd 8 + nalm ncomp 64 bytes), kept until gsht_plan_destroy; later calls do
+ * 16 ncol nd 8 + nalm ncomp 256 bytes), kept until gsht_plan_destroy; later calls do
  * not allocate.  Does not synchronise.
  */
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream);
