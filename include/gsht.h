@@ -131,7 +131,12 @@ int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin,
                      double epsilon, gsht_precision prec, void *hip_stream);
 
 /* Synthesis with a plan: alm -> map (layouts as in gsht_synth_general).  Does not
- * allocate and does not synchronise.  Calls on one plan must not overlap. */
+ * allocate and does not synchronise.  Calls on one plan must not overlap.
+ * Graph capture: gsht_plan_synth, gsht_plan_adjoint and, once a first call has
+ * allocated their buffers, the other plan transforms issue only kernel launches and
+ * library FFT launches on hip_stream (no copies, fills or synchronisation), so a
+ * caller may capture them into a HIP graph and replay it while the plan lives; a
+ * replay reads the buffers captured, at their contents at replay time. */
 int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream);
 
 /*
