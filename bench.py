@@ -41,7 +41,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 1 << 30            # plain copy used to calibrate the HBM byte counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_legendre_synth_pollens_thin6144.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_10431_amd", "csrc", "legendre_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_10431_amd", "csrc", f)
+                  for f in ("legendre_kernels.hip", "legendre_device.hpp")]
 
 
 def measured_traffic(workload):
@@ -51,7 +52,7 @@ def measured_traffic(workload):
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != sha or rec.get("workload", "").split()[0] != workload:

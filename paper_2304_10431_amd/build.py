@@ -18,8 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsht.so")
-SOURCES = ["capi.cpp", "legendre.hip", "legendre_kernels.hip", "staging.hip", "colfft.hip",
-           "nufft.hip", "lensing.hip", "analysis.hip"]
+SOURCES = ["capi.cpp", "legendre.hip", "legendre_kernels.hip", "legendre_mfma.hip", "staging.hip",
+           "colfft.hip", "nufft.hip", "lensing.hip", "analysis.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -25,99 +25,9 @@
 // blocks run without masks or checks, and only a final partial block checks the
 // degree bound.  Chunks whose most equatorial ring stays below 2^-900 up to lmax
 // are skipped outright.
-#include "gsht_internal.hpp"
+#include "legendre_device.hpp"
 
 namespace gsht {
-
-template <typename T> struct cplxk;
-template <> struct cplxk<float> { using type = float2; };
-template <> struct cplxk<double> { using type = double2; };
-
-// ---- start values -----------------------------------------------------------------
-
-struct XD {
-    double m;
-    int e;
-};
-
-__device__ inline void xnorm(XD &x)
-{
-    int k;
-    x.m = frexp(x.m, &k);
-    x.e += k;
-}
-
-// base^n (base >= 0, n >= 0) with a separate binary exponent; 0^0 = 1.
-__device__ inline XD xpow(double base, int n)
-{
-    XD r{1.0, 0};
-    if (n == 0)
-        return r;
-    if (base == 0.0)
-        return XD{0.0, 0};
-    XD b{base, 0};
-    xnorm(b);
-    while (n) {
-        if (n & 1) {
-            r.m *= b.m;
-            r.e += b.e;
-            xnorm(r);
-        }
-        b.m *= b.m;
-        b.e *= 2;
-        xnorm(b);
-        n >>= 1;
-    }
-    return r;
-}
-
-// One channel's value at l0: mant 2^ex0 sin(theta/2)^a cos(theta/2)^b.
-__device__ inline XD start_value(double mant, int ex0, int a, int b, double sh, double ch)
-{
-    XD v{mant, ex0};
-    const XD ps = xpow(sh, a), pc = xpow(ch, b);
-    v.m *= ps.m;
-    v.e += ps.e;
-    xnorm(v);
-    v.m *= pc.m;
-    v.e += pc.e;
-    xnorm(v);
-    return v;
-}
-
-constexpr double TWO_P256 = 0x1p256;
-constexpr double TWO_M512 = 0x1p-512;
-// In-range thresholds 2^INX: values from there up are held unscaled (normal
-// doubles; in the decaying region the recurrence only grows them).  The synthesis
-// takes 2^-900, which ends its masked phase early; the adjoint takes 2^-256, which
-// spares it the lane reductions of blocks that hold only negligible terms.
-constexpr int SYN_IN_EXP = -900;
-constexpr int ADJ_IN_EXP = -256;
-
-// true value = p 2^ex, ex a non-positive multiple of 512, ex == 0 <=> in range.
-template <int INX>
-__device__ inline void to_scaled(const XD &v, double &p, int &ex)
-{
-    if (v.m == 0.0) {
-        p = 0.0;
-        ex = 0;
-    } else if (v.e >= INX + 1) {
-        p = ldexp(v.m, v.e);
-        ex = 0;
-    } else {
-        const int t = v.e + 256;              // < 0
-        ex = 512 * (-((-t + 511) / 512));     // 512 floor(t / 512)
-        p = ldexp(v.m, v.e - ex);
-    }
-}
-
-__device__ inline void ring_geom(int q, int ntheta, double &x, double &sh, double &ch)
-{
-    const double t = (double)q / (double)(ntheta - 1);
-    x = cospi(t);
-    sh = sinpi(0.5 * t);
-    ch = cospi(0.5 * t);
-}
 
 // ---- live-chunk table -------------------------------------------------------------
 
@@ -203,132 +113,6 @@ hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s)
     live_launch(p, p.syn_r, p.syn_nchunk, p.leg.lfirst_syn, s);
     live_launch(p, p.adj_r, p.adj_nchunk, p.leg.lfirst_adj, s);
     return hipGetLastError();
-}
-
-// ---- work mapping -------------------------------------------------------------------
-
-// Workgroups are dispatched round-robin over the MI355X's 8 XCDs.  All chunks of one
-// m are kept on one XCD, so that XCD's L2 serves the m's coefficient stream to all of
-// them (spread over every XCD, each 4 MB L2 would hold dozens of streams and thrash),
-// and the m values are dealt to the XCDs round-robin, largest work first on each.
-constexpr int NXCD = 8;
-
-__device__ inline void xcd_map(int nchunk, int &m, int &chunk)
-{
-    const int x = blockIdx.x % NXCD, k = blockIdx.x / NXCD;
-    const int g = k / nchunk;
-    chunk = k - g * nchunk;
-    m = x + NXCD * g;
-}
-
-static unsigned xcd_grid(int mmax, int nchunk)
-{
-    return (unsigned)(NXCD * ((mmax + NXCD) / NXCD) * nchunk);
-}
-
-// ---- per-ring recurrence state ------------------------------------------------------
-
-struct Ring {
-    double x;
-    double a0, a1, b0, b1;  // p_{l-1}, p_l of channels +s and -s
-    int ea, eb;             // exponent offsets
-};
-
-template <int INX>
-__device__ inline Ring ring_init(const StartInfo &si, int q, int ntheta, bool active, bool spin)
-{
-    Ring r;
-    double sh, ch;
-    ring_geom(active ? q : 0, ntheta, r.x, sh, ch);
-    r.a0 = r.b0 = 0.0;
-    to_scaled<INX>(start_value(si.mant_p, si.ex_p, si.a_p, si.b_p, sh, ch), r.a1, r.ea);
-    if (spin)
-        to_scaled<INX>(start_value(si.mant_m, si.ex_m, si.a_m, si.b_m, sh, ch), r.b1, r.eb);
-    else {
-        r.b1 = 0.0;
-        r.eb = 0;
-    }
-    if (!active) {
-        r.a1 = r.b1 = 0.0;
-        r.ea = r.eb = 0;
-    }
-    return r;
-}
-
-template <bool SPIN>
-__device__ inline void ring_advance(Ring &r, double a, double b)
-{
-    const double ta = fma(a, r.x, b);
-    const double na = fma(ta, r.a1, -r.a0);
-    r.a0 = r.a1;
-    r.a1 = na;
-    if (SPIN) {
-        const double tb = fma(a, r.x, -b);
-        const double nb = fma(tb, r.b1, -r.b0);
-        r.b0 = r.b1;
-        r.b1 = nb;
-    }
-}
-
-// A scaled channel whose true value p 2^e has reached 2^INX is folded to e = 0;
-// otherwise it is rescaled by 2^-512 once |p| reaches 2^256.
-template <int INX>
-__device__ inline void rescale_channel(double &p0, double &p1, int &e)
-{
-    if (e >= 0)
-        return;
-    if (fabs(p1) >= ldexp(1.0, INX - e)) {
-        p0 = ldexp(p0, e);
-        p1 = ldexp(p1, e);
-        e = 0;
-    } else if (fabs(p1) >= TWO_P256) {
-        p0 *= TWO_M512;
-        p1 *= TWO_M512;
-        e += 512;
-    }
-}
-
-template <bool SPIN, int INX>
-__device__ inline void ring_rescale(Ring &r)
-{
-    rescale_channel<INX>(r.a0, r.a1, r.ea);
-    if (SPIN)
-        rescale_channel<INX>(r.b0, r.b1, r.eb);
-}
-
-// Wave-uniform slice state: 0 = no lane in range, 1 = some, 2 = all.
-template <bool SPIN>
-__device__ inline int slice_phase(const Ring &r)
-{
-    const bool in = (r.ea == 0) && (!SPIN || r.eb == 0);
-    const bool some = (r.ea == 0 && r.a1 != 0.0) || (SPIN && r.eb == 0 && r.b1 != 0.0);
-    if (__all(in))
-        return 2;
-    return __any(some) ? 1 : 0;
-}
-
-template <bool B>
-using flag = std::integral_constant<bool, B>;
-
-// ---- synthesis -------------------------------------------------------------------
-
-template <typename T>
-__device__ inline void store_c(typename cplxk<T>::type *p, double re, double im)
-{
-    typename cplxk<T>::type v;
-    v.x = (T)re;
-    v.y = (T)im;
-    *p = v;
-}
-
-// Ring value and, for interior rings, its doubled mirror with sign ms.
-template <typename T>
-__device__ inline void put_ring(typename cplxk<T>::type *col, int j, int ntheta, int nd, double ms,
-                                double re, double im)
-{
-    store_c<T>(col + j, re, im);
-    if (j > 0 && j < ntheta - 1)
-        store_c<T>(col + (nd - j), ms * re, ms * im);
 }
 
 // Accumulators of one ring pair: spin s -> N+ (0,1), S+ (2,3), N- (4,5), S- (6,7);
@@ -1086,287 +870,6 @@ static void adj_launch(const gsht_plan &p, const void *Din, bool grad, hipStream
 #undef GSHT_LEG_ADJ
 }
 
-// ---- several maps on the matrix cores (FP32 form) ------------------------------------
-
-// For NM = 8 NCB maps sharing one geometry, the degree sums of one m are matrix
-// products: per block of 16 degrees, the [64 ring pairs x 16 degrees] Legendre values
-// of a channel times [16 degrees x 32 NCB] coefficient columns.  The recurrence runs
-// in FP64 exactly as above (one slice of 64 ring pairs per wave); its values (|p_l| <=
-// sqrt((2 l + 1) / 4 pi) / N_l, within FP16 range for lmax <= 8192) and the
-// coefficients, scaled per (m, map) so that the largest lies in [2^7, 2^8), are split
-// into FP16 pairs hi + lo (hi the value rounded towards zero, lo the remainder,
-// likewise) and multiplied on the matrix cores (v_mfma_f32_32x32x16_f16) with FP32
-// accumulation as hi hi + hi lo + lo hi; the dropped lo lo term and the split are
-// below 2^-21 relative.  Values of a channel still carrying an exponent offset enter
-// as 0.  Columns 4k..4k+3 of map k: channel +s ("a"): Re, Im of u+ (N+) and SG Re, Im
-// u- (S-); channel -s ("b"): Re, Im u- (N-) and SG Re, Im u+ (S+); spin 0: u (N) and
-// SG u (S), SG = (-1)^(l - l0).  Operand layouts of the 32x32x16 product: A row =
-// lane % 32, B column = lane % 32, degree 8 (lane / 32) + j in element j of both;
-// result element r of lane i is row 8 (r / 4) + 4 (i / 32) + r % 4, column i % 32.
-// The loop is software-pipelined: the recurrence and conversion of block kb + 1 and
-// the loads of its coefficient tiles are independent of block kb's products, so the
-// vector and matrix units overlap.
-
-typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
-typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-
-constexpr int MK = 16;  // degrees per matrix step
-
-// hi (x, y) rounded towards zero to FP16, lo the FP16 remainder
-__device__ inline void split_pair(float x, float y, unsigned &hi, unsigned &lo)
-{
-    const half2_t h = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(x, y));
-    hi = __builtin_bit_cast(unsigned, h);
-    lo = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(x - (float)h[0], y - (float)h[1]));
-}
-
-// Lane L holds degrees 0..7 of its ring in x and 8..15 in y.  Afterwards x is the A
-// operand of ring pairs 0..31 (lanes 32..63 carrying degrees 8..15 of ring L - 32)
-// and y that of ring pairs 32..63.
-__device__ inline void to_operands(u32x4_t &x, u32x4_t &y)
-{
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const auto r = __builtin_amdgcn_permlane32_swap(x[d], y[d], false, false);
-        x[d] = r[0];
-        y[d] = r[1];
-    }
-}
-
-// rescale_channel without branches (selects only, so that the block's matrix
-// products can be scheduled among the recurrence steps).  A fold happens only at
-// e = -512 or -1024 (values reach at most 2^288 before the next check), where 2^e is
-// still a double.
-template <int INX>
-__device__ inline void rescale_channel_sel(double &p0, double &p1, int &e)
-{
-    const bool neg = e < 0;
-    const bool fold = neg && fabs(p1) >= ldexp(1.0, INX - e);
-    const bool down = neg && !fold && fabs(p1) >= TWO_P256;
-    const double f = fold ? ldexp(1.0, e) : (down ? TWO_M512 : 1.0);
-    p0 *= f;
-    p1 *= f;
-    e = fold ? 0 : (down ? e + 512 : e);
-}
-
-// One channel's operands: [0] hi rings 0..31, [1] hi rings 32..63, [2], [3] lo.
-struct AOps {
-    u32x4_t v[4];
-};
-
-// Values of degrees lb .. lb + 15 of both channels as operands, advancing the
-// recurrence by 16 degrees (coefficients past lmax read the zero entry at lmax).
-template <bool SPIN>
-__device__ inline void make_a(Ring &rg, const double2 *__restrict__ abm, int lb, int lmax,
-                              AOps &A, AOps &B)
-{
-    const bool ia = rg.ea == 0, ib = SPIN && rg.eb == 0;
-    float fa[MK], fb[MK];
-#pragma unroll
-    for (int j = 0; j < MK; ++j) {
-        fa[j] = ia ? (float)rg.a1 : 0.f;
-        fb[j] = ib ? (float)rg.b1 : 0.f;
-        const int l = lb + j;
-        const double2 c = abm[l < lmax ? l : lmax];
-        ring_advance<SPIN>(rg, c.x, c.y);
-    }
-    rescale_channel_sel<SYN_IN_EXP>(rg.a0, rg.a1, rg.ea);
-    if (SPIN)
-        rescale_channel_sel<SYN_IN_EXP>(rg.b0, rg.b1, rg.eb);
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        unsigned hi, lo;
-        split_pair(fa[2 * d], fa[2 * d + 1], hi, lo);
-        A.v[d / 4][d % 4] = hi;
-        A.v[2 + d / 4][d % 4] = lo;
-        if (SPIN) {
-            split_pair(fb[2 * d], fb[2 * d + 1], hi, lo);
-            B.v[d / 4][d % 4] = hi;
-            B.v[2 + d / 4][d % 4] = lo;
-        }
-    }
-    to_operands(A.v[0], A.v[1]);
-    to_operands(A.v[2], A.v[3]);
-    if (SPIN) {
-        to_operands(B.v[0], B.v[1]);
-        to_operands(B.v[2], B.v[3]);
-    }
-}
-
-__device__ inline f32x16_t mma(const u32x4_t &a, const u32x4_t &b, const f32x16_t &c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8_t, a),
-                                                  __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
-}
-
-// Coefficient tiles: per m, nkb(m) = ceil((lmax - l0 + 1) / 16) blocks starting at
-// boff[m]; block kb holds [type][cb][hi, lo][lane] half8 entries for degrees
-// l0 + 16 kb + 8 (lane / 32) + j.  oscale[m][map] undoes the coefficient scaling.
-template <bool SPIN, int NCB>
-__global__ __launch_bounds__(64) void leg_synth_mfma_kernel(
-    const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
-    const int32_t *__restrict__ lfirst, const int64_t *__restrict__ boff,
-    const u32x4_t *__restrict__ Bt, const float *__restrict__ oscale, int nm, int lmax, int mmax,
-    int s, int ntheta, int nd, int npairs, int nchunk, size_t dstride, float2 *__restrict__ D)
-{
-    constexpr int NT = SPIN ? 2 : 1;
-    constexpr int NMX = 8 * NCB;
-    constexpr int BLK = NT * NCB * 2 * 64;  // 16-byte entries per block
-    __shared__ float tile[64][33];
-    int m, chunk;
-    xcd_map(nchunk, m, chunk);
-    if (m > mmax)
-        return;
-    const int lane = threadIdx.x;
-    const StartInfo si = st[m];
-    const int l0 = si.l0;
-    const bool live = (l0 <= lmax) && (lfirst[m * nchunk + chunk] <= lmax);
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double2 *abm = ab + base;
-    const int q = chunk * 64 + lane;
-    Ring rg = ring_init<SYN_IN_EXP>(si, q, ntheta, live && q < npairs, SPIN);
-    f32x16_t acc[2][NT][NCB];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int c = 0; c < NCB; ++c)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    acc[h][t][c][r] = 0.f;
-    if (live) {
-        const u32x4_t *bm = Bt + boff[m] * BLK + lane;
-        const int nkb = (lmax - l0 + MK) / MK;
-        int kb = 0;
-        // blocks before any lane is in range: recurrence only
-        while (kb < nkb && slice_phase<SPIN>(rg) == 0) {
-#pragma unroll 4
-            for (int j = 0; j < MK; ++j) {
-                const int l = l0 + MK * kb + j;
-                const double2 c = abm[l < lmax ? l : lmax];
-                ring_advance<SPIN>(rg, c.x, c.y);
-            }
-            ring_rescale<SPIN, SYN_IN_EXP>(rg);
-            ++kb;
-        }
-        if (kb < nkb) {
-            AOps A[NT], An[NT];
-            u32x4_t Bc[NT][NCB][2], Bn[NT][NCB][2];
-            auto load_b = [&](int k, u32x4_t (&Bx)[NT][NCB][2]) {
-                const u32x4_t *bb = bm + (int64_t)k * BLK;
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int c = 0; c < NCB; ++c)
-#pragma unroll
-                        for (int hl = 0; hl < 2; ++hl)
-                            Bx[t][c][hl] = bb[((t * NCB + c) * 2 + hl) * 64];
-            };
-            load_b(kb, Bc);
-            make_a<SPIN>(rg, abm, l0 + MK * kb, lmax, A[0], A[NT - 1]);
-            for (; kb < nkb; ++kb) {
-                // next block (past the end: a harmless repeat of the last tile and
-                // recurrence steps on zero coefficients)
-                load_b(kb + 1 < nkb ? kb + 1 : kb, Bn);
-                make_a<SPIN>(rg, abm, l0 + MK * (kb + 1), lmax, An[0], An[NT - 1]);
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int c = 0; c < NCB; ++c)
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            f32x16_t x = acc[h][t][c];
-                            x = mma(A[t].v[h], Bc[t][c][0], x);
-                            x = mma(A[t].v[h], Bc[t][c][1], x);
-                            x = mma(A[t].v[2 + h], Bc[t][c][0], x);
-                            acc[h][t][c] = x;
-                        }
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    A[t] = An[t];
-#pragma unroll
-                    for (int c = 0; c < NCB; ++c) {
-                        Bc[t][c][0] = Bn[t][c][0];
-                        Bc[t][c][1] = Bn[t][c][1];
-                    }
-                }
-            }
-        }
-    }
-    // Results through LDS, one (type, column block) at a time: lane L then holds the
-    // 32 columns of ring pair L.
-    const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
-    const double ms = ((s + m) & 1) ? -1.0 : 1.0;
-    const int jn = q, js = ntheta - 1 - q;
-    const int rbase = 4 * (lane / 32), col = lane % 32;
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    tile[32 * h + 8 * (r / 4) + rbase + r % 4][col] = acc[h][t][c][r];
-            __syncthreads();
-            if (q < npairs) {
-#pragma unroll 1
-                for (int k = 0; k < 8; ++k) {
-                    const int map = 8 * c + k;
-                    if (map >= nm)
-                        break;
-                    const double f = oscale[m * NMX + map];
-                    const double v0 = f * tile[lane][4 * k], v1 = f * tile[lane][4 * k + 1];
-                    const double v2 = f * tile[lane][4 * k + 2], v3 = f * tile[lane][4 * k + 3];
-                    float2 *Dk = D + (size_t)map * dstride;
-                    if (!SPIN) {
-                        float2 *colp = Dk + (size_t)m * nd;
-                        put_ring<float>(colp, jn, ntheta, nd, ms, v0, v1);
-                        if (js != jn)
-                            put_ring<float>(colp, js, ntheta, nd, ms, sfix * v2, sfix * v3);
-                    } else if (t == 0) {  // N+, S-
-                        put_ring<float>(Dk + (size_t)(m + mmax) * nd, jn, ntheta, nd, ms, v0, v1);
-                        if (m > 0 && js != jn)
-                            put_ring<float>(Dk + (size_t)(mmax - m) * nd, js, ntheta, nd, ms,
-                                            sfix * v2, sfix * v3);
-                    } else {  // N-, S+
-                        if (m > 0)
-                            put_ring<float>(Dk + (size_t)(mmax - m) * nd, jn, ntheta, nd, ms, v0, v1);
-                        if (js != jn)
-                            put_ring<float>(Dk + (size_t)(m + mmax) * nd, js, ntheta, nd, ms,
-                                            sfix * v2, sfix * v3);
-                    }
-                }
-            }
-            __syncthreads();
-        }
-}
-
-hipError_t launch_leg_synth_mfma(const gsht_plan &p, int nm, const void *Bt, const float *oscale,
-                                 const int64_t *boff, const int32_t *lfirst1, void *Dout,
-                                 size_t dstride, hipStream_t s)
-{
-    if (p.prec != GSHT_F32 || nm < 1 || nm > 16)
-        return hipErrorInvalidValue;
-    const int nchunk = (p.npairs + 63) / 64;
-    dim3 blk(64), grd(xcd_grid(p.mmax, nchunk));
-#define GSHT_LEG_MFMA(SP, NCB)                                                                   \
-    hipLaunchKernelGGL((leg_synth_mfma_kernel<SP, NCB>), grd, blk, 0, s, p.leg.ab, p.leg.start,  \
-                       lfirst1, boff, (const u32x4_t *)Bt, oscale, nm, p.lmax, p.mmax, p.spin,    \
-                       p.ntheta, p.nd, p.npairs, nchunk, dstride, (float2 *)Dout)
-    if (p.spin) {
-        if (nm > 8) GSHT_LEG_MFMA(true, 2);
-        else GSHT_LEG_MFMA(true, 1);
-    } else {
-        if (nm > 8) GSHT_LEG_MFMA(false, 2);
-        else GSHT_LEG_MFMA(false, 1);
-    }
-#undef GSHT_LEG_MFMA
-    return hipGetLastError();
-}
 
 hipError_t launch_leg_live_r1(const gsht_plan &p, int32_t *lfirst1, hipStream_t s)
 {
