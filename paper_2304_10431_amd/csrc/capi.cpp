@@ -769,8 +769,8 @@ int plan_deriv_impl(gsht_plan *p, const void *alm, void *map, void *dth, void *d
     return ok();
 }
 
-int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
-                      double mscale = 1.0, bool grad = false)
+// Adjoint from the map down to the doubled columns D (before the Legendre step).
+int plan_adjoint_to_D(gsht_plan *p, const void *map, hipStream_t s)
 {
     const size_t cs = csize(p->prec);
     if (p->spin)
@@ -793,6 +793,15 @@ int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
     } else {
         RUN(ST_COLUMN_ADJ, launch_column_adj(*p, s));
     }
+    return ok();
+}
+
+int plan_adjoint_impl(gsht_plan *p, const void *map, void *alm, hipStream_t s,
+                      double mscale = 1.0, bool grad = false)
+{
+    const int rc = plan_adjoint_to_D(p, map, s);
+    if (rc != GSHT_OK)
+        return rc;
     RUN(ST_LEG_ADJ, launch_leg_adjoint(*p, p->D, grad, s));
     RUN(ST_FINALIZE, launch_leg_finalize(*p, alm, mscale, grad, s));
     return ok();
@@ -968,6 +977,90 @@ static int setup_mfma(gsht_plan *p, hipStream_t s)
     HIP_TRY(launch_leg_live_r1(*p, p->mfma_live, s));
     HIP_TRY(hipStreamSynchronize(s));
     return GSHT_OK;
+}
+
+// Buffers of the matrix-core adjoint (16 maps): ring-input tiles per (m, slice, 32-ring
+// step), scales, sums; the doubled columns and the dead-chunk table are shared with
+// the matrix-core synthesis.
+static int setup_mfma_adj(gsht_plan *p, hipStream_t s)
+{
+    int rc;
+    if ((rc = setup_mfma(p, s)) != GSHT_OK)
+        return rc;
+    if (p->mfma_atiles)
+        return GSHT_OK;
+    const size_t nslice = (size_t)(p->npairs + 63) / 64, nm1 = (size_t)p->mmax + 1;
+    const size_t nt = p->spin ? 2 : 1;
+    const size_t tile_bytes = nm1 * nslice * 2 * nt * 4 /* column blocks */ * 2 * 64 * 16;
+    if ((rc = dev_alloc(p, &p->mfma_ascale, sizeof(float) * 16 * nm1)) != GSHT_OK) return rc;
+    if ((rc = dev_alloc(p, &p->mfma_acc, sizeof(double) * 16 * (size_t)p->nalm * 2 * p->ncomp)) !=
+        GSHT_OK)
+        return rc;
+    if ((rc = dev_alloc(p, &p->mfma_atiles, tile_bytes)) != GSHT_OK) {
+        p->mfma_atiles = nullptr;
+        return rc;
+    }
+    return GSHT_OK;
+}
+
+static bool use_mfma_adj(const gsht_plan *p)
+{
+    int S, W;
+    adj_mfma_shape(*p, S, W);
+    return use_mfma(p) && S > 0;
+}
+
+int gsht_plan_adjoint_many(gsht_plan *p, int nmaps, const void *map, void *alm, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (nmaps < 0)
+        return fail(GSHT_EINVAL, "nmaps must be >= 0, got %d", nmaps);
+    if (nmaps > 0 && (!alm || (!map && p->npts > 0)))
+        return fail(GSHT_EINVAL, "map/alm must not be NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t cs = csize(p->prec);
+    const size_t astride = (size_t)p->ncomp * p->nalm * cs;
+    const size_t mstride = (size_t)p->ncomp * p->npts * (cs / 2);
+    const size_t dstride = (size_t)p->ncol * p->nd;
+    const size_t nr = (size_t)2 * p->ncomp;
+    int rc;
+    const bool mfma = use_mfma_adj(p);
+    for (int k = 0; k < nmaps;) {
+        const char *mk = (const char *)map + (map ? k * mstride : 0);
+        char *ak = (char *)alm + k * astride;
+        if (mfma && nmaps - k >= 8) {
+            const int nm = std::min(16, nmaps - k);
+            if ((rc = setup_mfma_adj(p, s)) != GSHT_OK)
+                return rc;
+            for (int j = 0; j < nm; ++j) {
+                void *dsave = p->D;
+                p->D = (char *)p->Dmfma + j * dstride * cs;
+                rc = plan_adjoint_to_D(p, mk + j * mstride, s);
+                p->D = dsave;
+                if (rc != GSHT_OK)
+                    return rc;
+            }
+            RUN(ST_PREP, launch_prep_adj_mfma(*p, nm, p->Dmfma, dstride, p->mfma_atiles,
+                                              p->mfma_ascale, s));
+            RUN(ST_LEG_ADJ, launch_leg_adjoint_mfma(*p, nm, p->mfma_atiles, p->mfma_ascale,
+                                                    p->mfma_live, p->mfma_acc, s));
+            for (int j = 0; j < nm; ++j) {
+                double *asave = p->acc;
+                p->acc = p->mfma_acc + j * (size_t)p->nalm * nr;
+                const hipError_t he = launch_leg_finalize(*p, ak + j * astride, 1.0, false, s);
+                p->acc = asave;
+                if ((rc = check_launch(he, "launch_leg_finalize")) != GSHT_OK)
+                    return rc;
+            }
+            k += nm;
+            continue;
+        }
+        if ((rc = plan_adjoint_impl(p, mk, ak, s)) != GSHT_OK)
+            return rc;
+        k += 1;
+    }
+    return ok();
 }
 
 int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, void *hip_stream)

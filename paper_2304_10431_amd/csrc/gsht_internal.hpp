@@ -139,6 +139,9 @@ struct gsht_plan {
     int64_t *mfma_boff = nullptr;  // [mmax + 1] first tile block of each m
     float *mfma_scale = nullptr;   // [mmax + 1][16] output scales
     int32_t *mfma_live = nullptr;  // dead-chunk table for slices of 64 ring pairs
+    void *mfma_atiles = nullptr;   // FP16 ring-input tiles of the matrix-core adjoint
+    float *mfma_ascale = nullptr;  // [mmax + 1][16] their output scales
+    double *mfma_acc = nullptr;    // [16][nalm][2 ncomp] adjoint sums of the group
     // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
     // transform and deconvolution in one kernel (theta transform by rocFFT),
     // 2 = doubled transform, deconvolution and theta transform (split into its
@@ -189,6 +192,14 @@ hipError_t launch_leg_synth_mfma(const gsht_plan &p, int nm, const void *tiles,
                                  const float *oscale, const int64_t *boff,
                                  const int32_t *lfirst1, void *Dout, size_t dstride,
                                  hipStream_t s);
+// matrix-core adjoint of nm <= 16 maps (FP32 plans) from their doubled columns
+// (map k at Din + k dstride): ring-input tiles, then the sums into accm [nm][nalm][NR]
+void adj_mfma_shape(const gsht_plan &p, int &S, int &W);  // S = 0: not possible
+hipError_t launch_prep_adj_mfma(const gsht_plan &p, int nm, const void *Din, size_t dstride,
+                                void *tiles, float *oscale, hipStream_t s);
+hipError_t launch_leg_adjoint_mfma(const gsht_plan &p, int nm, const void *tiles,
+                                   const float *oscale, const int32_t *lfirst1, double *accm,
+                                   hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s);
 hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
                                hipStream_t s);

@@ -226,4 +226,25 @@ __device__ inline void put_ring(typename cplxk<T>::type *col, int j, int ntheta,
         store_c<T>(col + (nd - j), ms * re, ms * im);
 }
 
+template <typename T>
+__device__ inline double2 ld_c(const typename cplxk<T>::type *p)
+{
+    const typename cplxk<T>::type v = *p;
+    return make_double2((double)v.x, (double)v.y);
+}
+
+// Undoubled ring value H(j) from the doubled column.
+template <typename T>
+__device__ inline double2 ring_in(const typename cplxk<T>::type *col, int j, int ntheta, int nd,
+                                  double ms)
+{
+    double2 v = ld_c<T>(col + j);
+    if (j > 0 && j < ntheta - 1) {
+        const double2 w = ld_c<T>(col + (nd - j));
+        v.x += ms * w.x;
+        v.y += ms * w.y;
+    }
+    return v;
+}
+
 }  // namespace gsht

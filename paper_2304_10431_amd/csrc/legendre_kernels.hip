@@ -531,27 +531,6 @@ hipError_t launch_leg_synth_multi(const gsht_plan &p, int nm, const double *u, v
 
 // ---- adjoint -----------------------------------------------------------------------
 
-template <typename T>
-__device__ inline double2 ld_c(const typename cplxk<T>::type *p)
-{
-    const typename cplxk<T>::type v = *p;
-    return make_double2((double)v.x, (double)v.y);
-}
-
-// Undoubled ring value H(j) from the doubled column.
-template <typename T>
-__device__ inline double2 ring_in(const typename cplxk<T>::type *col, int j, int ntheta, int nd,
-                                  double ms)
-{
-    double2 v = ld_c<T>(col + j);
-    if (j > 0 && j < ntheta - 1) {
-        const double2 w = ld_c<T>(col + (nd - j));
-        v.x += ms * w.x;
-        v.y += ms * w.y;
-    }
-    return v;
-}
-
 // Per-ring adjoint inputs.  Spin 0: e = F(N) + F(S'), o = F(N) - F(S') (even / odd
 // l - l0).  Spin s: F+(N), F+(S'), conj F-(N), conj F-(S'), S' = (-1)^(l0+m) S.
 struct RingIn {

@@ -287,4 +287,381 @@ hipError_t launch_leg_synth_mfma(const gsht_plan &p, int nm, const void *Bt, con
     return hipGetLastError();
 }
 
+// ---- adjoint of several maps on the matrix cores (FP32 form) ------------------------
+
+// The adjoint sums of one m are products over ring pairs: for a block of 16 degrees,
+// C_t[column][degree] = sum_q F_t[q][column] p_t,l(q) with the per-ring inputs F
+// (columns per map: channel +s: Re, Im F+(N), Re, Im conj F-(S'); channel -s: Re, Im
+// conj F-(N), Re, Im F+(S'); spin 0: Re, Im F(N), Re, Im F(S'), S' the south ring
+// times (-1)^(l0+m), exactly the inputs of leg_adjoint_kernel) and then
+//   S+ = C_a[F+(N)] + SG C_b[F+(S')],  S- = C_b[conj F-(N)] + SG C_a[conj F-(S')],
+//   spin 0: b = C[F(N)] + SG C[F(S')],  SG = (-1)^(l - l0).
+// One workgroup per m; its W waves split the ring slices (64 pairs each, S slices per
+// wave, recurrence state in registers, FP64, threshold 2^-256 as the FP64 adjoint).
+// Per block a wave writes the FP16 hi/lo parts of its slice's Legendre values to an
+// LDS slab [hi, lo][16 degrees][64 rings (+4 pad)] as (channel +s, channel -s) pairs,
+// reads them back in the B layout of v_mfma_f32_16x16x32_f16 (degree = lane % 16,
+// rings 8 (lane / 16) + j of a 32-ring step) and multiplies the F tiles (A layout:
+// column = lane % 16, same rings), hi hi + hi lo + lo hi.  The W partial results of a
+// block are summed through LDS (the slabs' space) and written once, so the output
+// needs no atomics.  Result element r of lane i is column 4 (i / 16) + r (map
+// 4 cb + i / 16, entry r), degree i % 16.
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int AK = 16;    // degrees per block
+constexpr int PROW = 68;  // LDS slab row: 64 rings + 4 words of padding
+
+__device__ inline f32x4_t mma16(const u32x4_t &a, const u32x4_t &b, const f32x4_t &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a),
+                                                  __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+}
+
+// low (SEL 0) or high (SEL 1) FP16 halves of two words, packed
+template <int SEL>
+__device__ inline unsigned halves(unsigned x, unsigned y)
+{
+    return SEL == 0 ? __builtin_amdgcn_perm(y, x, 0x05040100u) : __builtin_amdgcn_perm(y, x, 0x07060302u);
+}
+
+// The eight per-ring adjoint inputs of ring pair q from one map's doubled columns.
+__device__ inline void adj_inputs(const float2 *__restrict__ D, int m, int mmax, int spin, int q,
+                                  int ntheta, int nd, int npairs, float (&v)[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        v[k] = 0.f;
+    if (q >= npairs)
+        return;
+    const double ms = ((spin + m) & 1) ? -1.0 : 1.0;
+    const int l0 = m > spin ? m : spin;
+    const double sfix = ((l0 + m) & 1) ? -1.0 : 1.0;
+    const int jn = q, js = ntheta - 1 - q;
+    const float2 *colp = D + (size_t)(spin ? m + mmax : m) * nd;
+    double2 n = ring_in<float>(colp, jn, ntheta, nd, ms), so = make_double2(0.0, 0.0);
+    if (js != jn) {
+        so = ring_in<float>(colp, js, ntheta, nd, ms);
+        so.x *= sfix;
+        so.y *= sfix;
+    }
+    v[0] = (float)n.x; v[1] = (float)n.y; v[2] = (float)so.x; v[3] = (float)so.y;
+    if (spin) {
+        const float2 *colm = D + (size_t)(mmax - m) * nd;
+        double2 mn = ring_in<float>(colm, jn, ntheta, nd, ms), msn = make_double2(0.0, 0.0);
+        if (js != jn) {
+            msn = ring_in<float>(colm, js, ntheta, nd, ms);
+            msn.x *= sfix;
+            msn.y *= sfix;
+        }
+        v[4] = (float)mn.x; v[5] = (float)-mn.y; v[6] = (float)msn.x; v[7] = (float)-msn.y;
+    }
+}
+
+// F tiles: per (m, slice, 32-ring step ks) [type][cb][hi, lo][lane] half8 entries,
+// column lane % 16 (map 4 cb + (lane % 16) / 4, entry lane % 4), ring pairs
+// 64 slice + 32 ks + 8 (lane / 16) + j; per (m, map) scale 2^e (largest scaled input in
+// [2^7, 2^8)), oscale[m][map] = 2^-e.  One workgroup per m.
+template <int NCB>
+__global__ __launch_bounds__(256) void prep_adj_mfma_kernel(
+    const float2 *__restrict__ D, size_t dstride, int mmax, int spin, int ntheta, int nd,
+    int npairs, int nslice, int nm, u32x4_t *__restrict__ At, float *__restrict__ oscale)
+{
+    constexpr int NMX = 4 * NCB;
+    const int m = blockIdx.x, tid = threadIdx.x;
+    const int nt = spin ? 2 : 1;
+    const int tmap = tid / 16, tq = tid % 16;
+    __shared__ unsigned mx[NMX];
+    __shared__ float sc[NMX];
+    __shared__ float V[NMX][8][33];
+    if (tid < NMX)
+        mx[tid] = 0u;
+    __syncthreads();
+    if (tmap < nm) {
+        float lm = 0.f;
+        for (int q = tq; q < npairs; q += 16) {
+            float v[8];
+            adj_inputs(D + (size_t)tmap * dstride, m, mmax, spin, q, ntheta, nd, npairs, v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                lm = fmaxf(lm, fabsf(v[k]));
+        }
+        atomicMax(&mx[tmap], __float_as_uint(lm));  // non-negative floats order as integers
+    }
+    __syncthreads();
+    if (tid < NMX) {
+        const float v = __uint_as_float(mx[tid]);
+        int e = 0;
+        if (v > 0.f) {
+            e = 7 - ilogbf(v);
+            e = e < -100 ? -100 : (e > 100 ? 100 : e);
+        }
+        sc[tid] = ldexpf(1.f, e);
+        oscale[m * NMX + tid] = ldexpf(1.f, -e);
+    }
+    __syncthreads();
+    const int per = nt * NCB * 2 * 64;
+    for (int step = 0; step < 2 * nslice; ++step) {
+        const int qb = 32 * step;
+        if (tmap < NMX) {
+            for (int h = 0; h < 2; ++h) {
+                float v[8];
+                adj_inputs(D + (size_t)(tmap < nm ? tmap : 0) * dstride, m, mmax, spin,
+                           tmap < nm ? qb + tq + 16 * h : npairs, ntheta, nd, npairs, v);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    V[tmap][k][tq + 16 * h] = v[k] * sc[tmap];
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < per; idx += blockDim.x) {
+            const int lane = idx % 64, hl = (idx / 64) % 2, cb = (idx / 128) % NCB;
+            const int t = idx / (128 * NCB);
+            const int col = lane % 16, map = 4 * cb + col / 4, e = col % 4;
+            // entry e of type t -> input index
+            const int src = spin == 0 ? e : (t == 0 ? (e < 2 ? e : e + 4) : (e < 2 ? e + 4 : e));
+            half8_t v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float f = V[map][src][8 * (lane / 16) + j];
+                const auto hp = __builtin_amdgcn_cvt_pkrtz(f, 0.f);
+                v[j] = hl == 0 ? hp[0] : __builtin_amdgcn_cvt_pkrtz(f - (float)hp[0], 0.f)[0];
+            }
+            At[((int64_t)m * 2 * nslice + step) * per + idx] = __builtin_bit_cast(u32x4_t, v);
+        }
+        __syncthreads();
+    }
+}
+
+template <bool SPIN, int NCB, int S>
+__global__ __launch_bounds__(1024) void leg_adjoint_mfma_kernel(
+    const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
+    const int32_t *__restrict__ lfirst, const u32x4_t *__restrict__ At,
+    const float *__restrict__ oscale, int nm, int lmax, int mmax, int ntheta, int npairs,
+    int nslice, int64_t nalm, double *__restrict__ accm)
+{
+    constexpr int NT = SPIN ? 2 : 1;
+    constexpr int NR = SPIN ? 4 : 2;
+    constexpr int NMX = 4 * NCB;
+    constexpr int PER = NT * NCB * 2 * 64;  // tile entries per 32-ring step
+    extern __shared__ unsigned smem[];
+    const int W = blockDim.x / 64;
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int m = blockIdx.x;
+    if (m > mmax)
+        return;
+    const StartInfo si = st[m];
+    const int l0 = si.l0;
+    if (l0 > lmax)
+        return;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double2 *abm = ab + base;
+    unsigned *slab = smem + w * (2 * AK * PROW);
+    f32x4_t *red = reinterpret_cast<f32x4_t *>(smem);  // [W][NT][NCB][64], after a barrier
+    Ring rg[S];
+    bool act[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int sl = w + W * i;
+        act[i] = sl < nslice && lfirst[m * nslice + sl] <= lmax;
+        const int q = 64 * sl + lane;
+        rg[i] = ring_init<ADJ_IN_EXP>(si, q, ntheta, act[i] && q < npairs, SPIN);
+    }
+    const int n = lane % 16, g = lane / 16;
+    for (int lb = l0; lb <= lmax; lb += AK) {
+        f32x4_t acc[NT][NCB];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c)
+                acc[t][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (!act[i])
+                continue;
+            if (slice_phase<SPIN>(rg[i]) == 0) {  // nothing in range: recurrence only
+#pragma unroll 4
+                for (int j = 0; j < AK; ++j) {
+                    const int l = lb + j;
+                    const double2 c = abm[l < lmax ? l : lmax];
+                    ring_advance<SPIN>(rg[i], c.x, c.y);
+                }
+                rescale_channel_sel<ADJ_IN_EXP>(rg[i].a0, rg[i].a1, rg[i].ea);
+                if (SPIN)
+                    rescale_channel_sel<ADJ_IN_EXP>(rg[i].b0, rg[i].b1, rg[i].eb);
+                continue;
+            }
+            // Legendre values of degrees lb .. lb + 15 -> slab (hi, lo planes)
+            const bool ia = rg[i].ea == 0, ib = SPIN && rg[i].eb == 0;
+#pragma unroll
+            for (int j = 0; j < AK; ++j) {
+                const float fa = ia ? (float)rg[i].a1 : 0.f;
+                const float fb = ib ? (float)rg[i].b1 : 0.f;
+                const half2_t h = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fa, fb));
+                const auto lo = __builtin_amdgcn_cvt_pkrtz(fa - (float)h[0], fb - (float)h[1]);
+                slab[j * PROW + lane] = __builtin_bit_cast(unsigned, h);
+                slab[(AK + j) * PROW + lane] = __builtin_bit_cast(unsigned, lo);
+                const int l = lb + j;
+                const double2 c = abm[l < lmax ? l : lmax];
+                ring_advance<SPIN>(rg[i], c.x, c.y);
+            }
+            rescale_channel_sel<ADJ_IN_EXP>(rg[i].a0, rg[i].a1, rg[i].ea);
+            if (SPIN)
+                rescale_channel_sel<ADJ_IN_EXP>(rg[i].b0, rg[i].b1, rg[i].eb);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int sl = w + W * i;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                // B operands: degree n, ring pairs 32 ks + 8 g + j, both channels packed
+                const unsigned *ph = slab + n * PROW + 32 * ks + 8 * g;
+                const unsigned *pl = ph + AK * PROW;
+                const u32x4_t h0 = *reinterpret_cast<const u32x4_t *>(ph);
+                const u32x4_t h1 = *reinterpret_cast<const u32x4_t *>(ph + 4);
+                const u32x4_t q0 = *reinterpret_cast<const u32x4_t *>(pl);
+                const u32x4_t q1 = *reinterpret_cast<const u32x4_t *>(pl + 4);
+                u32x4_t bh[NT], bl[NT];
+                bh[0] = u32x4_t{halves<0>(h0[0], h0[1]), halves<0>(h0[2], h0[3]),
+                                halves<0>(h1[0], h1[1]), halves<0>(h1[2], h1[3])};
+                bl[0] = u32x4_t{halves<0>(q0[0], q0[1]), halves<0>(q0[2], q0[3]),
+                                halves<0>(q1[0], q1[1]), halves<0>(q1[2], q1[3])};
+                if (SPIN) {
+                    bh[NT - 1] = u32x4_t{halves<1>(h0[0], h0[1]), halves<1>(h0[2], h0[3]),
+                                         halves<1>(h1[0], h1[1]), halves<1>(h1[2], h1[3])};
+                    bl[NT - 1] = u32x4_t{halves<1>(q0[0], q0[1]), halves<1>(q0[2], q0[3]),
+                                         halves<1>(q1[0], q1[1]), halves<1>(q1[2], q1[3])};
+                }
+                const u32x4_t *ap = At + ((int64_t)m * 2 * nslice + 2 * sl + ks) * PER + lane;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NCB; ++c) {
+                        const u32x4_t ah = ap[((t * NCB + c) * 2 + 0) * 64];
+                        const u32x4_t al = ap[((t * NCB + c) * 2 + 1) * 64];
+                        f32x4_t x = acc[t][c];
+                        x = mma16(ah, bh[t], x);
+                        x = mma16(ah, bl[t], x);
+                        x = mma16(al, bh[t], x);
+                        acc[t][c] = x;
+                    }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // sum the waves' partial products and write the block's coefficients
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c)
+                red[((w * NT + t) * NCB + c) * 64 + lane] = acc[t][c];
+        __syncthreads();
+        for (int o = threadIdx.x; o < NCB * 64; o += blockDim.x) {
+            const int c = o / 64, ln = o % 64;
+            const int map = 4 * c + ln / 16, deg = ln % 16;
+            const int l = lb + deg;
+            if (map >= nm || l > lmax)
+                continue;
+            f32x4_t A = f32x4_t{0.f, 0.f, 0.f, 0.f}, B = A;
+            for (int ww = 0; ww < W; ++ww) {
+                A += red[((ww * NT + 0) * NCB + c) * 64 + ln];
+                if (SPIN)
+                    B += red[((ww * NT + NT - 1) * NCB + c) * 64 + ln];
+            }
+            const double f = oscale[m * NMX + map];
+            const double sg = ((l - l0) & 1) ? -1.0 : 1.0;
+            double *out = accm + (int64_t)map * nalm * NR + (base + l) * NR;
+            if (SPIN) {
+                out[0] = f * ((double)A[0] + sg * (double)B[2]);
+                out[1] = f * ((double)A[1] + sg * (double)B[3]);
+                out[2] = f * ((double)B[0] + sg * (double)A[2]);
+                out[3] = f * ((double)B[1] + sg * (double)A[3]);
+            } else {
+                out[0] = f * ((double)A[0] + sg * (double)A[2]);
+                out[1] = f * ((double)A[1] + sg * (double)A[3]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Slices per wave and waves per workgroup of the adjoint kernel (at most 16 waves,
+// at most 5 slices each); 0 if the plan has more ring slices than that.
+void adj_mfma_shape(const gsht_plan &p, int &S, int &W)
+{
+    const int nslice = (p.npairs + 63) / 64;
+    S = (nslice + 15) / 16;
+    W = S > 0 ? (nslice + S - 1) / S : 0;
+    if (S > 5)
+        S = W = 0;
+}
+
+size_t adj_mfma_lds(int W) { return (size_t)W * 2 * AK * PROW * 4; }
+
+hipError_t launch_prep_adj_mfma(const gsht_plan &p, int nm, const void *Din, size_t dstride,
+                                void *tiles, float *oscale, hipStream_t s)
+{
+    if (p.prec != GSHT_F32 || nm < 1 || nm > 16)
+        return hipErrorInvalidValue;
+    const int nslice = (p.npairs + 63) / 64;
+    dim3 blk(256), grd(p.mmax + 1);
+    if (nm > 8)
+        hipLaunchKernelGGL(prep_adj_mfma_kernel<4>, grd, blk, 0, s, (const float2 *)Din, dstride,
+                           p.mmax, p.spin, p.ntheta, p.nd, p.npairs, nslice, nm, (u32x4_t *)tiles,
+                           oscale);
+    else
+        hipLaunchKernelGGL(prep_adj_mfma_kernel<2>, grd, blk, 0, s, (const float2 *)Din, dstride,
+                           p.mmax, p.spin, p.ntheta, p.nd, p.npairs, nslice, nm, (u32x4_t *)tiles,
+                           oscale);
+    return hipGetLastError();
+}
+
+template <bool SP, int NCB, int S>
+static hipError_t adj_mfma_go(const gsht_plan &p, int nm, int W, const void *tiles,
+                              const float *oscale, const int32_t *lfirst1, double *accm,
+                              hipStream_t s)
+{
+    const size_t lds = adj_mfma_lds(W);
+    hipError_t e = hipFuncSetAttribute((const void *)leg_adjoint_mfma_kernel<SP, NCB, S>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((leg_adjoint_mfma_kernel<SP, NCB, S>), dim3(p.mmax + 1), dim3(64 * W), lds,
+                       s, p.leg.ab, p.leg.start, lfirst1, (const u32x4_t *)tiles, oscale, nm,
+                       p.lmax, p.mmax, p.ntheta, p.npairs, (p.npairs + 63) / 64, p.nalm, accm);
+    return hipGetLastError();
+}
+
+template <bool SP, int NCB>
+static hipError_t adj_mfma_s(const gsht_plan &p, int nm, int S, int W, const void *tiles,
+                             const float *oscale, const int32_t *lfirst1, double *accm,
+                             hipStream_t s)
+{
+    switch (S) {
+    case 1: return adj_mfma_go<SP, NCB, 1>(p, nm, W, tiles, oscale, lfirst1, accm, s);
+    case 2: return adj_mfma_go<SP, NCB, 2>(p, nm, W, tiles, oscale, lfirst1, accm, s);
+    case 3: return adj_mfma_go<SP, NCB, 3>(p, nm, W, tiles, oscale, lfirst1, accm, s);
+    case 4: return adj_mfma_go<SP, NCB, 4>(p, nm, W, tiles, oscale, lfirst1, accm, s);
+    case 5: return adj_mfma_go<SP, NCB, 5>(p, nm, W, tiles, oscale, lfirst1, accm, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_leg_adjoint_mfma(const gsht_plan &p, int nm, const void *tiles,
+                                   const float *oscale, const int32_t *lfirst1, double *accm,
+                                   hipStream_t s)
+{
+    int S, W;
+    adj_mfma_shape(p, S, W);
+    if (p.prec != GSHT_F32 || nm < 1 || nm > 16 || S == 0)
+        return hipErrorInvalidValue;
+    if (p.spin)
+        return nm > 8 ? adj_mfma_s<true, 4>(p, nm, S, W, tiles, oscale, lfirst1, accm, s)
+                      : adj_mfma_s<true, 2>(p, nm, S, W, tiles, oscale, lfirst1, accm, s);
+    return nm > 8 ? adj_mfma_s<false, 4>(p, nm, S, W, tiles, oscale, lfirst1, accm, s)
+                  : adj_mfma_s<false, 2>(p, nm, S, W, tiles, oscale, lfirst1, accm, s);
+}
+
 }  // namespace gsht

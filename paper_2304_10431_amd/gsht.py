@@ -62,6 +62,7 @@ _SIGS = {
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_many": [_vp, _i, _vp, _vp, _vp],
+    "gsht_plan_adjoint_many": [_vp, _i, _vp, _vp, _vp],
     "gsht_plan_autotune": [_vp, _vp],
     "gsht_plan_adjoint_grad": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_deriv": [_vp, _vp, _vp, _vp, _vp, _vp],
@@ -227,6 +228,17 @@ class Plan:
             out = torch.empty((nm, self.ncomp, self.npts), dtype=_RDT[self.prec], device=self.device)
         _need(out, _RDT[self.prec], (nm, self.ncomp, self.npts), "out")
         _check(_lib.gsht_plan_synth_many(self._h, nm, _ptr(alm), _ptr(out), _stream()))
+        return out
+
+    def adjoint_many(self, maps, out=None):
+        """Adjoint of several maps on the plan's points: [nmaps][ncomp][npts] -> [nmaps][ncomp][nalm]."""
+        nm = maps.shape[0]
+        _need(maps, _RDT[self.prec], (nm, self.ncomp, self.npts), "maps")
+        if out is None:
+            out = torch.empty((nm, self.ncomp, nalm(self.lmax, self.mmax)), dtype=_CDT[self.prec],
+                              device=self.device)
+        _need(out, _CDT[self.prec], (nm, self.ncomp, nalm(self.lmax, self.mmax)), "out")
+        _check(_lib.gsht_plan_adjoint_many(self._h, nm, _ptr(maps), _ptr(out), _stream()))
         return out
 
     def synth_grad(self, glm, out=None):

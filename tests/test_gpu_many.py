@@ -119,3 +119,51 @@ def test_many_mfma(G, monkeypatch, spin, lmax, mmax, npts, nmaps):
     assert worst <= 1e-6
     assert worst_valu <= 1e-6
     assert max(e_o) <= 1e-5
+
+
+@pytest.mark.parametrize("spin,lmax,mmax,npts,nmaps", [(2, 260, 200, 20000, 16),
+                                                       (0, 300, 300, 20000, 16),
+                                                       (1, 131, 131, 8000, 8),
+                                                       (3, 77, 50, 6000, 21),
+                                                       (2, 40, 40, 3000, 11)])
+def test_adjoint_many_mfma(G, monkeypatch, spin, lmax, mmax, npts, nmaps):
+    """FP32 plans run the adjoint of 8 to 16 maps through the matrix-core Legendre
+    step; every map's coefficients must stay within about 1e-6 of its own adjoint
+    (FP64 Legendre step) and within epsilon of the oracle, whatever the map's
+    amplitude; GSHT_MANY_MFMA=0 gives the single-map results."""
+    say("adjoint_many mfma", spin, lmax, mmax, npts, nmaps)
+    rng = np.random.default_rng(lmax + 20 * spin)
+    th = np.arccos(rng.uniform(-1, 1, npts))
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    th[:2] = [0.0, np.pi]
+    nc = oracle.ncomp(spin)
+    y = rng.standard_normal((nmaps, nc, npts)) * np.logspace(-4, 4, nmaps)[:, None, None]
+    y[3] = 0
+    plan = G.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), lmax, mmax, spin, 1e-5,
+                  "f32")
+    yd = torch.from_numpy(y).cuda().float()
+    many = plan.adjoint_many(yd).to(torch.complex128).cpu().numpy()
+    monkeypatch.setenv("GSHT_MANY_MFMA", "0")
+    plain = plan.adjoint_many(yd).to(torch.complex128).cpu().numpy()
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    worst = worst_plain = 0.0
+    for k in range(nmaps):
+        one = plan.adjoint(yd[k].contiguous()).to(torch.complex128).cpu().numpy()
+        if k == 3:
+            assert np.all(many[k] == 0) and np.all(one == 0)
+            continue
+        worst = max(worst, oracle.eps_eff(w * many[k], w * one))
+        worst_plain = max(worst_plain, oracle.eps_eff(w * plain[k], w * one))
+    plan.close()
+    e_o = [oracle.eps_eff(w * many[k], w * oracle.adjoint(y[k], lmax, mmax, spin, th, ph))
+           for k in (0, nmaps - 1)]
+    say("  worst vs single: mfma %.3e, plain %.3e; vs oracle %.3e %.3e"
+        % (worst, worst_plain, e_o[0], e_o[1]))
+    assert worst <= 2e-6
+    assert worst_plain <= 1e-12
+    assert max(e_o) <= 1e-5
+    # m = 0 imaginary parts and l < spin entries stay exactly zero
+    for m in range(min(spin, mmax + 1)):
+        i0 = oracle.alm_index(m, m, lmax)
+        assert np.all(many[:, :, i0:i0 + spin - m] == 0)
+    assert np.all(many[:, :, :lmax + 1].imag == 0)
