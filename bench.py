@@ -158,7 +158,28 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
         one = plan.synth(am[many - 1].contiguous())
         r["synth_many"]["eps_vs_single"] = float(torch.linalg.norm((mm[many - 1] - one).double())
                                                  / torch.linalg.norm(one.double()))
-        del am, mm, one
+        del am, one
+        # adjoint of the same maps (matrix-core Legendre step for 8..16 FP32 maps)
+        bm = plan.adjoint_many(mm)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            plan.adjoint_many(mm, out=bm)
+        e1.record()
+        torch.cuda.synchronize()
+        r["adjoint_many"] = {"maps": many, "adjoint_ms_per_map": e0.elapsed_time(e1) / steps / many,
+                             "legendre": "mfma" if (prec == "f32" and many >= 8) else "fp64"}
+        plan.set_profiling(True)
+        plan.adjoint_many(mm, out=bm)
+        st = plan.stage_times()
+        plan.set_profiling(False)
+        r["adjoint_many"]["legendre_ms_per_map"] = st["legendre_adj"][0] / many
+        r["adjoint_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
+        one = plan.adjoint(mm[many - 1].contiguous())
+        r["adjoint_many"]["eps_vs_single"] = float(
+            torch.linalg.norm((bm[many - 1] - one).to(torch.complex128))
+            / torch.linalg.norm(one.to(torch.complex128)))
+        del mm, bm, one
     return plan, m, r
 
 
@@ -365,6 +386,7 @@ def main():
                       "legendre_shapes": [v["info"]["syn_r"], v["info"]["adj_r"], v["info"]["adj_b"]],
                       "gradient_only_ms": v.get("gradient_only"),
                       "synth_many": v.get("synth_many"),
+                      "adjoint_many": v.get("adjoint_many"),
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
         "roofline": {"kernel": "legendre_synth", "bound": "alu",

@@ -159,15 +159,14 @@ int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, vo
 /*
  * Adjoint of nmaps maps sharing the plan's geometry (Sect. 2, eq. adjoint, for each
  * map): map [nmaps][ncomp][npts] -> alm [nmaps][ncomp][nalm], each as from
- * gsht_plan_adjoint.  FP32 plans whose ring grid has at most 80 slices of 64 ring
- * pairs (lmax up to about 10000) take groups of 8 to 16 maps through the matrix
- * cores: the spreading and FFT steps run per map, then one kernel forms every map's
- * Legendre sums as FP16 hi/lo split products with FP32 accumulation (each map within
- * about 1e-6 relative of its gsht_plan_adjoint result).  Other maps, and FP64 plans,
- * run one at a time.  GSHT_MANY_MFMA=0 turns the matrix-core path off.  The first
- * matrix-core call allocates its buffers (the synthesis group's plus about
- * (mmax + 1) npairs ncomp 512 + 16 nalm ncomp 16 bytes), kept until
- * gsht_plan_destroy.  Does not synchronise.
+ * gsht_plan_adjoint.  FP32 plans with lmax <= 8192 take groups of 8 to 16 maps
+ * through the matrix cores: the spreading and FFT steps run per map, then one kernel
+ * forms every map's Legendre sums as FP16 hi/lo split products with FP32
+ * accumulation (each map within about 1e-6 relative of its gsht_plan_adjoint
+ * result).  Other maps, and FP64 plans, run one at a time.  GSHT_MANY_MFMA=0 turns
+ * the matrix-core path off.  The first matrix-core call allocates its buffers (the
+ * synthesis group's plus about (mmax + 1) npairs (256 ncomp + 48) + 16 nalm ncomp 16
+ * bytes), kept until gsht_plan_destroy.  Does not synchronise.
  */
 int gsht_plan_adjoint_many(gsht_plan *p, int nmaps, const void *map, void *alm, void *hip_stream);
 

@@ -996,6 +996,7 @@ static int setup_mfma_adj(gsht_plan *p, hipStream_t s)
     if ((rc = dev_alloc(p, &p->mfma_acc, sizeof(double) * 16 * (size_t)p->nalm * 2 * p->ncomp)) !=
         GSHT_OK)
         return rc;
+    if ((rc = dev_alloc(p, &p->mfma_rstate, adj_mfma_state_bytes(*p))) != GSHT_OK) return rc;
     if ((rc = dev_alloc(p, &p->mfma_atiles, tile_bytes)) != GSHT_OK) {
         p->mfma_atiles = nullptr;
         return rc;
@@ -1007,7 +1008,7 @@ static bool use_mfma_adj(const gsht_plan *p)
 {
     int S, W;
     adj_mfma_shape(*p, S, W);
-    return use_mfma(p) && S > 0;
+    return use_mfma(p) && W > 0;
 }
 
 int gsht_plan_adjoint_many(gsht_plan *p, int nmaps, const void *map, void *alm, void *hip_stream)
@@ -1044,7 +1045,7 @@ int gsht_plan_adjoint_many(gsht_plan *p, int nmaps, const void *map, void *alm, 
             RUN(ST_PREP, launch_prep_adj_mfma(*p, nm, p->Dmfma, dstride, p->mfma_atiles,
                                               p->mfma_ascale, s));
             RUN(ST_LEG_ADJ, launch_leg_adjoint_mfma(*p, nm, p->mfma_atiles, p->mfma_ascale,
-                                                    p->mfma_live, p->mfma_acc, s));
+                                                    p->mfma_live, p->mfma_rstate, p->mfma_acc, s));
             for (int j = 0; j < nm; ++j) {
                 double *asave = p->acc;
                 p->acc = p->mfma_acc + j * (size_t)p->nalm * nr;

@@ -142,6 +142,7 @@ struct gsht_plan {
     void *mfma_atiles = nullptr;   // FP16 ring-input tiles of the matrix-core adjoint
     float *mfma_ascale = nullptr;  // [mmax + 1][16] their output scales
     double *mfma_acc = nullptr;    // [16][nalm][2 ncomp] adjoint sums of the group
+    void *mfma_rstate = nullptr;   // recurrence states of the adjoint's ring slices
     // per-column FFT stage: 0 = rocFFT for both theta transforms, 1 = doubled
     // transform and deconvolution in one kernel (theta transform by rocFFT),
     // 2 = doubled transform, deconvolution and theta transform (split into its
@@ -194,12 +195,13 @@ hipError_t launch_leg_synth_mfma(const gsht_plan &p, int nm, const void *tiles,
                                  hipStream_t s);
 // matrix-core adjoint of nm <= 16 maps (FP32 plans) from their doubled columns
 // (map k at Din + k dstride): ring-input tiles, then the sums into accm [nm][nalm][NR]
-void adj_mfma_shape(const gsht_plan &p, int &S, int &W);  // S = 0: not possible
+void adj_mfma_shape(const gsht_plan &p, int &S, int &W);  // W = 0: not possible
+size_t adj_mfma_state_bytes(const gsht_plan &p);          // recurrence state buffer
 hipError_t launch_prep_adj_mfma(const gsht_plan &p, int nm, const void *Din, size_t dstride,
                                 void *tiles, float *oscale, hipStream_t s);
 hipError_t launch_leg_adjoint_mfma(const gsht_plan &p, int nm, const void *tiles,
-                                   const float *oscale, const int32_t *lfirst1, double *accm,
-                                   hipStream_t s);
+                                   const float *oscale, const int32_t *lfirst1, void *rstate,
+                                   double *accm, hipStream_t s);
 hipError_t launch_leg_adjoint(const gsht_plan &p, const void *Din, bool grad, hipStream_t s);
 hipError_t launch_leg_finalize(const gsht_plan &p, void *alm, double mscale, bool grad,
                                hipStream_t s);

@@ -1,6 +1,9 @@
 // Matrix-core forms of the Legendre step for several maps sharing one geometry (FP32
 // plans): the recurrence of legendre_kernels.hip in FP64, the degree sums as FP16
 // split products on v_mfma_f32_32x32x16_f16 with FP32 accumulation.
+#include <algorithm>
+#include <cstdlib>
+
 #include "legendre_device.hpp"
 
 namespace gsht {
@@ -433,17 +436,56 @@ __global__ __launch_bounds__(256) void prep_adj_mfma_kernel(
     }
 }
 
-template <bool SPIN, int NCB, int S>
-__global__ __launch_bounds__(1024) void leg_adjoint_mfma_kernel(
+// Most waves per workgroup with NB sub-blocks (the slabs fill the LDS budget): the
+// launch bound, so that the compiler may give each wave the registers that leaves.
+template <int NB>
+constexpr int adj_wmax()
+{
+    return (int)(COL_MAX_BYTES / (2 * AK * NB * PROW * 4)) < 16 ? (int)(COL_MAX_BYTES / (2 * AK * NB * PROW * 4)) : 16;
+}
+
+// Recurrence state of every ring of one m between blocks, structure of arrays over
+// n = 64 nslice rings: x, a0, a1, b0, b1 (double), then ea, eb (int).
+constexpr size_t RS_BYTES = 5 * sizeof(double) + 2 * sizeof(int);  // per ring
+
+__device__ inline void ring_load(Ring &r, const unsigned char *rs, int n, int idx)
+{
+    const double *d = reinterpret_cast<const double *>(rs);
+    const int *e = reinterpret_cast<const int *>(d + 5 * (size_t)n);
+    r.x = d[idx];
+    r.a0 = d[n + idx];
+    r.a1 = d[2 * n + idx];
+    r.b0 = d[3 * n + idx];
+    r.b1 = d[4 * n + idx];
+    r.ea = e[idx];
+    r.eb = e[n + idx];
+}
+
+__device__ inline void ring_store(const Ring &r, unsigned char *rs, int n, int idx)
+{
+    double *d = reinterpret_cast<double *>(rs);
+    int *e = reinterpret_cast<int *>(d + 5 * (size_t)n);
+    d[idx] = r.x;
+    d[n + idx] = r.a0;
+    d[2 * n + idx] = r.a1;
+    d[3 * n + idx] = r.b0;
+    d[4 * n + idx] = r.b1;
+    e[idx] = r.ea;
+    e[n + idx] = r.eb;
+}
+
+template <bool SPIN, int NCB, int NB>
+__global__ __launch_bounds__(64 * adj_wmax<NB>()) void leg_adjoint_mfma_kernel(
     const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, const u32x4_t *__restrict__ At,
     const float *__restrict__ oscale, int nm, int lmax, int mmax, int ntheta, int npairs,
-    int nslice, int64_t nalm, double *__restrict__ accm)
+    int nslice, int64_t nalm, unsigned char *__restrict__ rstate, double *__restrict__ accm)
 {
     constexpr int NT = SPIN ? 2 : 1;
     constexpr int NR = SPIN ? 4 : 2;
     constexpr int NMX = 4 * NCB;
     constexpr int PER = NT * NCB * 2 * 64;  // tile entries per 32-ring step
+    constexpr int BK = AK * NB;             // degrees per block
     extern __shared__ unsigned smem[];
     const int W = blockDim.x / 64;
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -456,96 +498,115 @@ __global__ __launch_bounds__(1024) void leg_adjoint_mfma_kernel(
         return;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double2 *abm = ab + base;
-    unsigned *slab = smem + w * (2 * AK * PROW);
-    f32x4_t *red = reinterpret_cast<f32x4_t *>(smem);  // [W][NT][NCB][64], after a barrier
-    Ring rg[S];
-    bool act[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-        const int sl = w + W * i;
-        act[i] = sl < nslice && lfirst[m * nslice + sl] <= lmax;
+    unsigned *slab = smem + w * (2 * BK * PROW);
+    f32x4_t *red = reinterpret_cast<f32x4_t *>(smem);  // [W][NB][NT][NCB][64], after a barrier
+    const int nr = 64 * nslice;
+    unsigned char *rs = rstate + (size_t)m * nr * RS_BYTES;
+    // slices of this wave: w, w + W, ...; live ones in a bit mask
+    unsigned live = 0;
+    for (int i = 0, sl = w; sl < nslice; ++i, sl += W) {
+        const bool act = lfirst[m * nslice + sl] <= lmax;
+        live |= act ? (1u << i) : 0u;
         const int q = 64 * sl + lane;
-        rg[i] = ring_init<ADJ_IN_EXP>(si, q, ntheta, act[i] && q < npairs, SPIN);
+        const Ring r0 = ring_init<ADJ_IN_EXP>(si, q, ntheta, act && q < npairs, SPIN);
+        ring_store(r0, rs, nr, q);
     }
     const int n = lane % 16, g = lane / 16;
-    for (int lb = l0; lb <= lmax; lb += AK) {
-        f32x4_t acc[NT][NCB];
+    for (int lb = l0; lb <= lmax; lb += BK) {
+        f32x4_t acc[NB][NT][NCB];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int c = 0; c < NCB; ++c)
-                acc[t][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            if (!act[i])
+                for (int c = 0; c < NCB; ++c)
+                    acc[b][t][c] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int i = 0, sl = w; sl < nslice; ++i, sl += W) {
+            if (!((live >> i) & 1u))
                 continue;
-            if (slice_phase<SPIN>(rg[i]) == 0) {  // nothing in range: recurrence only
+            const int q = 64 * sl + lane;
+            Ring rg;
+            ring_load(rg, rs, nr, q);
+            if (slice_phase<SPIN>(rg) == 0) {  // nothing in range: recurrence only
 #pragma unroll 4
-                for (int j = 0; j < AK; ++j) {
+                for (int j = 0; j < BK; ++j) {
                     const int l = lb + j;
                     const double2 c = abm[l < lmax ? l : lmax];
-                    ring_advance<SPIN>(rg[i], c.x, c.y);
+                    ring_advance<SPIN>(rg, c.x, c.y);
                 }
-                rescale_channel_sel<ADJ_IN_EXP>(rg[i].a0, rg[i].a1, rg[i].ea);
+                rescale_channel_sel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
                 if (SPIN)
-                    rescale_channel_sel<ADJ_IN_EXP>(rg[i].b0, rg[i].b1, rg[i].eb);
+                    rescale_channel_sel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
+                ring_store(rg, rs, nr, q);
                 continue;
             }
-            // Legendre values of degrees lb .. lb + 15 -> slab (hi, lo planes)
-            const bool ia = rg[i].ea == 0, ib = SPIN && rg[i].eb == 0;
+            // F tiles of both 32-ring steps, requested before the recurrence runs
+            const u32x4_t *ap = At + ((int64_t)m * 2 * nslice + 2 * sl) * PER + lane;
+            u32x4_t ah[2][NT][NCB], al[2][NT][NCB];
 #pragma unroll
-            for (int j = 0; j < AK; ++j) {
-                const float fa = ia ? (float)rg[i].a1 : 0.f;
-                const float fb = ib ? (float)rg[i].b1 : 0.f;
-                const half2_t h = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fa, fb));
-                const auto lo = __builtin_amdgcn_cvt_pkrtz(fa - (float)h[0], fb - (float)h[1]);
-                slab[j * PROW + lane] = __builtin_bit_cast(unsigned, h);
-                slab[(AK + j) * PROW + lane] = __builtin_bit_cast(unsigned, lo);
-                const int l = lb + j;
-                const double2 c = abm[l < lmax ? l : lmax];
-                ring_advance<SPIN>(rg[i], c.x, c.y);
-            }
-            rescale_channel_sel<ADJ_IN_EXP>(rg[i].a0, rg[i].a1, rg[i].ea);
-            if (SPIN)
-                rescale_channel_sel<ADJ_IN_EXP>(rg[i].b0, rg[i].b1, rg[i].eb);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int sl = w + W * i;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                // B operands: degree n, ring pairs 32 ks + 8 g + j, both channels packed
-                const unsigned *ph = slab + n * PROW + 32 * ks + 8 * g;
-                const unsigned *pl = ph + AK * PROW;
-                const u32x4_t h0 = *reinterpret_cast<const u32x4_t *>(ph);
-                const u32x4_t h1 = *reinterpret_cast<const u32x4_t *>(ph + 4);
-                const u32x4_t q0 = *reinterpret_cast<const u32x4_t *>(pl);
-                const u32x4_t q1 = *reinterpret_cast<const u32x4_t *>(pl + 4);
-                u32x4_t bh[NT], bl[NT];
-                bh[0] = u32x4_t{halves<0>(h0[0], h0[1]), halves<0>(h0[2], h0[3]),
-                                halves<0>(h1[0], h1[1]), halves<0>(h1[2], h1[3])};
-                bl[0] = u32x4_t{halves<0>(q0[0], q0[1]), halves<0>(q0[2], q0[3]),
-                                halves<0>(q1[0], q1[1]), halves<0>(q1[2], q1[3])};
-                if (SPIN) {
-                    bh[NT - 1] = u32x4_t{halves<1>(h0[0], h0[1]), halves<1>(h0[2], h0[3]),
-                                         halves<1>(h1[0], h1[1]), halves<1>(h1[2], h1[3])};
-                    bl[NT - 1] = u32x4_t{halves<1>(q0[0], q0[1]), halves<1>(q0[2], q0[3]),
-                                         halves<1>(q1[0], q1[1]), halves<1>(q1[2], q1[3])};
-                }
-                const u32x4_t *ap = At + ((int64_t)m * 2 * nslice + 2 * sl + ks) * PER + lane;
+            for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
                     for (int c = 0; c < NCB; ++c) {
-                        const u32x4_t ah = ap[((t * NCB + c) * 2 + 0) * 64];
-                        const u32x4_t al = ap[((t * NCB + c) * 2 + 1) * 64];
-                        f32x4_t x = acc[t][c];
-                        x = mma16(ah, bh[t], x);
-                        x = mma16(ah, bl[t], x);
-                        x = mma16(al, bh[t], x);
-                        acc[t][c] = x;
+                        ah[ks][t][c] = ap[ks * PER + ((t * NCB + c) * 2 + 0) * 64];
+                        al[ks][t][c] = ap[ks * PER + ((t * NCB + c) * 2 + 1) * 64];
                     }
+            // Legendre values of degrees lb .. lb + BK - 1 -> slab (hi, lo planes)
+            const bool ia = rg.ea == 0, ib = SPIN && rg.eb == 0;
+#pragma unroll 4
+            for (int j = 0; j < BK; ++j) {
+                const float fa = ia ? (float)rg.a1 : 0.f;
+                const float fb = ib ? (float)rg.b1 : 0.f;
+                const half2_t h = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fa, fb));
+                const auto lo = __builtin_amdgcn_cvt_pkrtz(fa - (float)h[0], fb - (float)h[1]);
+                slab[j * PROW + lane] = __builtin_bit_cast(unsigned, h);
+                slab[(BK + j) * PROW + lane] = __builtin_bit_cast(unsigned, lo);
+                const int l = lb + j;
+                const double2 c = abm[l < lmax ? l : lmax];
+                ring_advance<SPIN>(rg, c.x, c.y);
             }
+            rescale_channel_sel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
+            if (SPIN)
+                rescale_channel_sel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
+            ring_store(rg, rs, nr, q);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    // B operands: degree 16 b + n, ring pairs 32 ks + 8 g + j, both channels
+                    const unsigned *ph = slab + (AK * b + n) * PROW + 32 * ks + 8 * g;
+                    const unsigned *pl = ph + BK * PROW;
+                    const u32x4_t h0 = *reinterpret_cast<const u32x4_t *>(ph);
+                    const u32x4_t h1 = *reinterpret_cast<const u32x4_t *>(ph + 4);
+                    const u32x4_t q0 = *reinterpret_cast<const u32x4_t *>(pl);
+                    const u32x4_t q1 = *reinterpret_cast<const u32x4_t *>(pl + 4);
+                    u32x4_t bh[NT], bl[NT];
+                    bh[0] = u32x4_t{halves<0>(h0[0], h0[1]), halves<0>(h0[2], h0[3]),
+                                    halves<0>(h1[0], h1[1]), halves<0>(h1[2], h1[3])};
+                    bl[0] = u32x4_t{halves<0>(q0[0], q0[1]), halves<0>(q0[2], q0[3]),
+                                    halves<0>(q1[0], q1[1]), halves<0>(q1[2], q1[3])};
+                    if (SPIN) {
+                        bh[NT - 1] = u32x4_t{halves<1>(h0[0], h0[1]), halves<1>(h0[2], h0[3]),
+                                             halves<1>(h1[0], h1[1]), halves<1>(h1[2], h1[3])};
+                        bl[NT - 1] = u32x4_t{halves<1>(q0[0], q0[1]), halves<1>(q0[2], q0[3]),
+                                             halves<1>(q1[0], q1[1]), halves<1>(q1[2], q1[3])};
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+#pragma unroll
+                        for (int c = 0; c < NCB; ++c) {
+                            f32x4_t x = acc[b][t][c];
+                            x = mma16(ah[ks][t][c], bh[t], x);
+                            x = mma16(ah[ks][t][c], bl[t], x);
+                            x = mma16(al[ks][t][c], bh[t], x);
+                            acc[b][t][c] = x;
+                        }
+                }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -553,22 +614,24 @@ __global__ __launch_bounds__(1024) void leg_adjoint_mfma_kernel(
         // sum the waves' partial products and write the block's coefficients
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int c = 0; c < NCB; ++c)
-                red[((w * NT + t) * NCB + c) * 64 + lane] = acc[t][c];
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int c = 0; c < NCB; ++c)
+                    red[(((w * NB + b) * NT + t) * NCB + c) * 64 + lane] = acc[b][t][c];
         __syncthreads();
-        for (int o = threadIdx.x; o < NCB * 64; o += blockDim.x) {
-            const int c = o / 64, ln = o % 64;
-            const int map = 4 * c + ln / 16, deg = ln % 16;
+        for (int o = threadIdx.x; o < NB * NCB * 64; o += blockDim.x) {
+            const int b = o / (NCB * 64), c = (o / 64) % NCB, ln = o % 64;
+            const int map = 4 * c + ln / 16, deg = AK * b + ln % 16;
             const int l = lb + deg;
             if (map >= nm || l > lmax)
                 continue;
             f32x4_t A = f32x4_t{0.f, 0.f, 0.f, 0.f}, B = A;
             for (int ww = 0; ww < W; ++ww) {
-                A += red[((ww * NT + 0) * NCB + c) * 64 + ln];
+                A += red[(((ww * NB + b) * NT + 0) * NCB + c) * 64 + ln];
                 if (SPIN)
-                    B += red[((ww * NT + NT - 1) * NCB + c) * 64 + ln];
+                    B += red[(((ww * NB + b) * NT + NT - 1) * NCB + c) * 64 + ln];
             }
             const double f = oscale[m * NMX + map];
             const double sg = ((l - l0) & 1) ? -1.0 : 1.0;
@@ -587,18 +650,34 @@ __global__ __launch_bounds__(1024) void leg_adjoint_mfma_kernel(
     }
 }
 
-// Slices per wave and waves per workgroup of the adjoint kernel (at most 16 waves,
-// at most 5 slices each); 0 if the plan has more ring slices than that.
+// Launch shape of the adjoint kernel: NB sub-blocks of 16 degrees per block (the F
+// tiles of a slice serve all of them), W waves per workgroup within the LDS (slabs of
+// 2 x 16 NB x 68 words each), at most 32 slices per wave (the live mask); W = 0 if
+// the plan has more ring slices than that.  GSHT_ADJ_NB (1, 2 or 4) selects NB.
+static int adj_nb()
+{
+    const char *e = getenv("GSHT_ADJ_NB");
+    const int v = e ? atoi(e) : 4;
+    return (v == 1 || v == 2) ? v : 4;
+}
+
+size_t adj_mfma_lds(int W, int NB) { return (size_t)W * 2 * AK * NB * PROW * 4; }
+
 void adj_mfma_shape(const gsht_plan &p, int &S, int &W)
 {
+    const int nb = adj_nb();
     const int nslice = (p.npairs + 63) / 64;
-    S = (nslice + 15) / 16;
-    W = S > 0 ? (nslice + S - 1) / S : 0;
-    if (S > 5)
+    const int wmax = nb == 1 ? adj_wmax<1>() : nb == 2 ? adj_wmax<2>() : adj_wmax<4>();
+    S = (nslice + wmax - 1) / wmax;
+    W = (nslice + S - 1) / S;
+    if (S > 32)
         S = W = 0;
 }
 
-size_t adj_mfma_lds(int W) { return (size_t)W * 2 * AK * PROW * 4; }
+size_t adj_mfma_state_bytes(const gsht_plan &p)
+{
+    return (size_t)(p.mmax + 1) * 64 * ((p.npairs + 63) / 64) * RS_BYTES;
+}
 
 hipError_t launch_prep_adj_mfma(const gsht_plan &p, int nm, const void *Din, size_t dstride,
                                 void *tiles, float *oscale, hipStream_t s)
@@ -618,50 +697,48 @@ hipError_t launch_prep_adj_mfma(const gsht_plan &p, int nm, const void *Din, siz
     return hipGetLastError();
 }
 
-template <bool SP, int NCB, int S>
+template <bool SP, int NCB, int NB>
 static hipError_t adj_mfma_go(const gsht_plan &p, int nm, int W, const void *tiles,
-                              const float *oscale, const int32_t *lfirst1, double *accm,
-                              hipStream_t s)
+                              const float *oscale, const int32_t *lfirst1, void *rstate,
+                              double *accm, hipStream_t s)
 {
-    const size_t lds = adj_mfma_lds(W);
-    hipError_t e = hipFuncSetAttribute((const void *)leg_adjoint_mfma_kernel<SP, NCB, S>,
+    const size_t lds = adj_mfma_lds(W, NB);
+    hipError_t e = hipFuncSetAttribute((const void *)leg_adjoint_mfma_kernel<SP, NCB, NB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((leg_adjoint_mfma_kernel<SP, NCB, S>), dim3(p.mmax + 1), dim3(64 * W), lds,
+    hipLaunchKernelGGL((leg_adjoint_mfma_kernel<SP, NCB, NB>), dim3(p.mmax + 1), dim3(64 * W), lds,
                        s, p.leg.ab, p.leg.start, lfirst1, (const u32x4_t *)tiles, oscale, nm,
-                       p.lmax, p.mmax, p.ntheta, p.npairs, (p.npairs + 63) / 64, p.nalm, accm);
+                       p.lmax, p.mmax, p.ntheta, p.npairs, (p.npairs + 63) / 64, p.nalm,
+                       (unsigned char *)rstate, accm);
     return hipGetLastError();
 }
 
 template <bool SP, int NCB>
-static hipError_t adj_mfma_s(const gsht_plan &p, int nm, int S, int W, const void *tiles,
-                             const float *oscale, const int32_t *lfirst1, double *accm,
-                             hipStream_t s)
+static hipError_t adj_mfma_nb(const gsht_plan &p, int nm, int W, const void *tiles,
+                              const float *oscale, const int32_t *lfirst1, void *rstate,
+                              double *accm, hipStream_t s)
 {
-    switch (S) {
-    case 1: return adj_mfma_go<SP, NCB, 1>(p, nm, W, tiles, oscale, lfirst1, accm, s);
-    case 2: return adj_mfma_go<SP, NCB, 2>(p, nm, W, tiles, oscale, lfirst1, accm, s);
-    case 3: return adj_mfma_go<SP, NCB, 3>(p, nm, W, tiles, oscale, lfirst1, accm, s);
-    case 4: return adj_mfma_go<SP, NCB, 4>(p, nm, W, tiles, oscale, lfirst1, accm, s);
-    case 5: return adj_mfma_go<SP, NCB, 5>(p, nm, W, tiles, oscale, lfirst1, accm, s);
-    default: return hipErrorInvalidValue;
+    switch (adj_nb()) {
+    case 1: return adj_mfma_go<SP, NCB, 1>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s);
+    case 2: return adj_mfma_go<SP, NCB, 2>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s);
+    default: return adj_mfma_go<SP, NCB, 4>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s);
     }
 }
 
 hipError_t launch_leg_adjoint_mfma(const gsht_plan &p, int nm, const void *tiles,
-                                   const float *oscale, const int32_t *lfirst1, double *accm,
-                                   hipStream_t s)
+                                   const float *oscale, const int32_t *lfirst1, void *rstate,
+                                   double *accm, hipStream_t s)
 {
     int S, W;
     adj_mfma_shape(p, S, W);
-    if (p.prec != GSHT_F32 || nm < 1 || nm > 16 || S == 0)
+    if (p.prec != GSHT_F32 || nm < 1 || nm > 16 || W == 0)
         return hipErrorInvalidValue;
     if (p.spin)
-        return nm > 8 ? adj_mfma_s<true, 4>(p, nm, S, W, tiles, oscale, lfirst1, accm, s)
-                      : adj_mfma_s<true, 2>(p, nm, S, W, tiles, oscale, lfirst1, accm, s);
-    return nm > 8 ? adj_mfma_s<false, 4>(p, nm, S, W, tiles, oscale, lfirst1, accm, s)
-                  : adj_mfma_s<false, 2>(p, nm, S, W, tiles, oscale, lfirst1, accm, s);
+        return nm > 8 ? adj_mfma_nb<true, 4>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s)
+                      : adj_mfma_nb<true, 2>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s);
+    return nm > 8 ? adj_mfma_nb<false, 4>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s)
+                  : adj_mfma_nb<false, 2>(p, nm, W, tiles, oscale, lfirst1, rstate, accm, s);
 }
 
 }  // namespace gsht
