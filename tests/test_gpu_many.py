@@ -167,3 +167,33 @@ def test_adjoint_many_mfma(G, monkeypatch, spin, lmax, mmax, npts, nmaps):
         i0 = oracle.alm_index(m, m, lmax)
         assert np.all(many[:, :, i0:i0 + spin - m] == 0)
     assert np.all(many[:, :, :lmax + 1].imag == 0)
+
+
+@pytest.mark.parametrize("spin,lmax,mmax,npts", [(2, 2, 2, 500), (0, 5, 0, 700), (3, 3, 1, 400),
+                                                 (1, 17, 17, 1)])
+def test_many_edge_cases(G, spin, lmax, mmax, npts):
+    """Degenerate several-map cases on the matrix-core paths: lmax = spin (one degree
+    per m, most m empty), mmax = 0, a single point, and zero maps (a no-op)."""
+    say("many edge", spin, lmax, mmax, npts)
+    rng = np.random.default_rng(5 + lmax)
+    th = np.arccos(rng.uniform(-1, 1, npts))
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    nm = 9
+    a = _spectrum_alms(nm, spin, lmax, mmax, 3)
+    plan = G.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), lmax, mmax, spin, 1e-5,
+                  "f32")
+    ad = torch.from_numpy(a).cuda().to(torch.complex64)
+    many = plan.synth_many(ad)
+    y = torch.from_numpy(rng.standard_normal((nm, oracle.ncomp(spin), npts))).cuda().float()
+    back = plan.adjoint_many(y)
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    for k in (0, 4, 8):
+        one = plan.synth(ad[k].contiguous()).double().cpu().numpy()
+        assert oracle.eps_eff(many[k].double().cpu().numpy(), one) <= 1e-6
+        ref = oracle.adjoint(y[k].double().cpu().numpy(), lmax, mmax, spin, th, ph)
+        assert oracle.eps_eff(w * back[k].to(torch.complex128).cpu().numpy(), w * ref) <= 1e-5
+    empty_a = torch.zeros((0,) + tuple(ad.shape[1:]), dtype=ad.dtype, device="cuda")
+    assert plan.synth_many(empty_a).shape[0] == 0
+    empty_m = torch.zeros((0,) + tuple(y.shape[1:]), dtype=y.dtype, device="cuda")
+    assert plan.adjoint_many(empty_m).shape[0] == 0
+    plan.close()
