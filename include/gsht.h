@@ -314,6 +314,27 @@ int gsht_magnification(const void *alpha, const void *kappa, const void *omega, 
 /* Release a plan and its workspace (NULL is ignored).  Synchronises the device. */
 void gsht_plan_destroy(gsht_plan *p);
 
+/*
+ * Batches of independent instances (many maps of uneven lmax, spin and point count):
+ * a batch owns nstreams (1..16) worker HIP streams of default priority and their
+ * events.  gsht_batch_synth / gsht_batch_adjoint run instance i (plans[i] with
+ * alms[i] -> maps[i], resp. maps[i] -> alms[i], device pointers, layouts as for the
+ * plan calls) on worker stream i mod nstreams, ordered after the work already queued
+ * on hip_stream; hip_stream then waits for all of them (event fork and join, no host
+ * synchronisation), so small instances overlap on the GPU and a caller may capture a
+ * whole batch call into one HIP graph.  The plans must be distinct (each instance
+ * uses its plan's work buffers); GSHT_EINVAL otherwise.  On an error in instance i
+ * the later instances are not started, the workers are still joined, and the error
+ * is returned.  Calls on one batch must not overlap.
+ */
+typedef struct gsht_batch gsht_batch;
+int gsht_batch_create(gsht_batch **b, int nstreams);
+int gsht_batch_synth(gsht_batch *b, int n, gsht_plan *const *plans, const void *const *alms,
+                     void *const *maps, void *hip_stream);
+int gsht_batch_adjoint(gsht_batch *b, int n, gsht_plan *const *plans, const void *const *maps,
+                       void *const *alms, void *hip_stream);
+void gsht_batch_destroy(gsht_batch *b);
+
 /* Sizes and parameters chosen by a plan (host struct filled by gsht_plan_get_info). */
 typedef struct {
     int lmax, mmax, spin, ncomp;

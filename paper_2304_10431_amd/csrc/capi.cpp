@@ -1198,6 +1198,110 @@ int gsht_plan_adjoint_vjp(gsht_plan *p, const void *galm, void *gmap, void *hip_
 
 void gsht_plan_destroy(gsht_plan *p) { free_plan(p); }
 
+// ---- batches of plans -------------------------------------------------------------
+
+struct gsht_batch {
+    std::vector<hipStream_t> streams;  // worker streams (default priority, non-blocking)
+    std::vector<hipEvent_t> joins;     // one per worker stream
+    hipEvent_t fork = nullptr;
+};
+
+static void free_batch(gsht_batch *b)
+{
+    if (!b)
+        return;
+    for (hipEvent_t e : b->joins)
+        (void)hipEventDestroy(e);
+    if (b->fork)
+        (void)hipEventDestroy(b->fork);
+    for (hipStream_t s : b->streams)
+        (void)hipStreamDestroy(s);
+    delete b;
+}
+
+int gsht_batch_create(gsht_batch **out, int nstreams)
+{
+    if (!out)
+        return fail(GSHT_EINVAL, "batch output pointer is NULL");
+    *out = nullptr;
+    if (nstreams < 1 || nstreams > 16)
+        return fail(GSHT_EINVAL, "nstreams must be in [1, 16], got %d", nstreams);
+    gsht_batch *b = new gsht_batch();
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int i = 0; i < nstreams && e == hipSuccess; ++i) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            b->streams.push_back(st);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            b->joins.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        free_batch(b);
+        return fail(GSHT_EHIP, "batch creation failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return ok();
+}
+
+void gsht_batch_destroy(gsht_batch *b) { free_batch(b); }
+
+// Instance i on worker stream i mod nstreams, after the work already queued on
+// hip_stream; hip_stream then waits for every worker.
+static int batch_run(gsht_batch *b, int n, gsht_plan *const *plans, const void *const *in,
+                     void *const *out, void *hip_stream, bool adjoint)
+{
+    if (!b)
+        return fail(GSHT_EINVAL, "batch is NULL");
+    if (n < 0)
+        return fail(GSHT_EINVAL, "n must be >= 0, got %d", n);
+    if (n == 0)
+        return ok();
+    if (!plans || !in || !out)
+        return fail(GSHT_EINVAL, "plans/inputs/outputs must not be NULL");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i])
+            return fail(GSHT_EINVAL, "plan %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i])
+                return fail(GSHT_EINVAL, "plan %d appears twice in the batch (instances %d and %d "
+                                         "would share its work buffers)", i, j, i);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int ns = (int)b->streams.size();
+    const int used = n < ns ? n : ns;
+    HIP_TRY(hipEventRecord(b->fork, s));
+    for (int k = 0; k < used; ++k)
+        HIP_TRY(hipStreamWaitEvent(b->streams[(size_t)k], b->fork, 0));
+    int rc = GSHT_OK;
+    for (int i = 0; i < n && rc == GSHT_OK; ++i) {
+        hipStream_t ws = b->streams[(size_t)(i % ns)];
+        rc = adjoint ? plan_adjoint_impl(plans[i], in[i], out[i], ws)
+                     : plan_synth_impl(plans[i], in[i], out[i], ws);
+    }
+    // join every worker that was forked, also after an error
+    for (int k = 0; k < used; ++k) {
+        HIP_TRY(hipEventRecord(b->joins[(size_t)k], b->streams[(size_t)k]));
+        HIP_TRY(hipStreamWaitEvent(s, b->joins[(size_t)k], 0));
+    }
+    return rc == GSHT_OK ? ok() : rc;
+}
+
+int gsht_batch_synth(gsht_batch *b, int n, gsht_plan *const *plans, const void *const *alms,
+                     void *const *maps, void *hip_stream)
+{
+    return batch_run(b, n, plans, alms, maps, hip_stream, false);
+}
+
+int gsht_batch_adjoint(gsht_batch *b, int n, gsht_plan *const *plans, const void *const *maps,
+                       void *const *alms, void *hip_stream)
+{
+    return batch_run(b, n, plans, maps, alms, hip_stream, true);
+}
+
 int gsht_deflect(const double *theta, const double *phi, const void *alpha, gsht_precision prec,
                  int64_t npts, double *theta_out, double *phi_out, double *chi_out,
                  void *hip_stream)

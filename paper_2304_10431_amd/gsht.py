@@ -83,6 +83,9 @@ _SIGS = {
     "gsht_alm_lfactor": [_vp, _vp, _i, _i, _i, _i, _i, _vp],
     "gsht_magnification": [_vp, _vp, _vp, _vp, _i, _i64, _vp, _vp],
     "gsht_analysis_minimal": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
+    "gsht_batch_create": [ctypes.POINTER(_vp), _i],
+    "gsht_batch_synth": [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+    "gsht_batch_adjoint": [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
     "gsht_num_stages": [],
     "gsht_stage_name": [_i],
     "gsht_last_error": [],
@@ -95,8 +98,10 @@ _lib.gsht_last_error.restype = ctypes.c_char_p
 _lib.gsht_stage_name.restype = ctypes.c_char_p
 _lib.gsht_plan_destroy.argtypes = [_vp]
 _lib.gsht_plan_destroy.restype = None
+_lib.gsht_batch_destroy.argtypes = [_vp]
+_lib.gsht_batch_destroy.restype = None
 
-EXPORTED = list(_SIGS) + ["gsht_plan_destroy"]
+EXPORTED = list(_SIGS) + ["gsht_plan_destroy", "gsht_batch_destroy"]
 
 
 def _check(rc: int):
@@ -309,6 +314,58 @@ class Plan:
         cnt = (ctypes.c_int64 * n)()
         _check(_lib.gsht_plan_get_stage_times(self._h, ms, cnt, n))
         return {_lib.gsht_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
+
+
+class Batch:
+    """Independent instances (plans of any lmax, spin, point count and precision) run
+    over ``nstreams`` worker streams of the library (gsht_batch_*): instance i on
+    worker i mod nstreams, after the work queued on torch's current stream, which then
+    waits for all of them.  A batch call can be captured in a graph."""
+
+    def __init__(self, nstreams: int = 4):
+        h = _vp()
+        _check(_lib.gsht_batch_create(ctypes.byref(h), nstreams))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gsht_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _arr(xs):
+        return (_vp * max(len(xs), 1))(*[x if isinstance(x, _vp) else _vp(x) for x in xs])
+
+    def synth(self, plans, alms, outs=None):
+        """alms[i] -> maps[i] with plans[i]; returns the list of maps."""
+        if outs is None:
+            outs = [torch.empty((p.ncomp, p.npts), dtype=_RDT[p.prec], device=p.device) for p in plans]
+        for p, a, o in zip(plans, alms, outs):
+            _need(a, _CDT[p.prec], (p.ncomp, nalm(p.lmax, p.mmax)), "alm")
+            _need(o, _RDT[p.prec], (p.ncomp, p.npts), "out")
+        _check(_lib.gsht_batch_synth(self._h, len(plans), self._arr([p._h.value for p in plans]),
+                                     self._arr([_ptr(a) for a in alms]),
+                                     self._arr([_ptr(o) for o in outs]), _stream()))
+        return outs
+
+    def adjoint(self, plans, maps, outs=None):
+        """maps[i] -> alms[i] with plans[i]; returns the list of coefficient arrays."""
+        if outs is None:
+            outs = [torch.empty((p.ncomp, nalm(p.lmax, p.mmax)), dtype=_CDT[p.prec], device=p.device)
+                    for p in plans]
+        for p, m, o in zip(plans, maps, outs):
+            _need(m, _RDT[p.prec], (p.ncomp, p.npts), "map")
+            _need(o, _CDT[p.prec], (p.ncomp, nalm(p.lmax, p.mmax)), "out")
+        _check(_lib.gsht_batch_adjoint(self._h, len(plans), self._arr([p._h.value for p in plans]),
+                                       self._arr([_ptr(m) for m in maps]),
+                                       self._arr([_ptr(o) for o in outs]), _stream()))
+        return outs
 
 
 def legendre_rings(alm, lmax: int, mmax: int, spin: int, ntheta: int, precision="f64", out=None):
