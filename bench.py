@@ -78,7 +78,8 @@ def legendre_flops(lmax, mmax, spin, npairs):
     return per * units * npairs
 
 
-def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, autotune=False):
+def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, autotune=False,
+              check=None):
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     cdt = torch.complex128 if prec == "f64" else torch.complex64
     t0 = time.time()
@@ -159,6 +160,10 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
         r["synth_many"]["eps_vs_single"] = float(torch.linalg.norm((mm[many - 1] - one).double())
                                                  / torch.linalg.norm(one.double()))
         del am, one
+        fac = torch.linspace(0.5, 2.0, many, device=mm.device)
+        if check is not None:
+            # the last map's values on the oracle's sample points, undone the scaling
+            r["many_check"] = {"synth": (mm[many - 1][:, check["idx"]] / fac[-1]).double().cpu().numpy()}
         # adjoint of the same maps (matrix-core Legendre step for 8..16 FP32 maps)
         bm = plan.adjoint_many(mm)
         torch.cuda.synchronize()
@@ -179,7 +184,14 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
         r["adjoint_many"]["eps_vs_single"] = float(
             torch.linalg.norm((bm[many - 1] - one).to(torch.complex128))
             / torch.linalg.norm(one.to(torch.complex128)))
-        del mm, bm, one
+        del bm, one
+        if check is not None:
+            # adjoint of scaled copies of the oracle's sampled input
+            ym = (check["yfull"].to(mm.dtype).unsqueeze(0) * fac[:, None, None]).contiguous()
+            bmy = plan.adjoint_many(ym)
+            r["many_check"]["adjoint"] = (bmy[many - 1] / fac[-1]).to(torch.complex128).cpu().numpy()
+            del ym, bmy
+        del mm
     return plan, m, r
 
 
@@ -212,7 +224,7 @@ def sample_points(npts, nsample, ncomp):
     return idx, y
 
 
-def cpu_baseline(spec, th_h, ph_h, alm_h, idx, y, m_gpu_h, adj_gpu_h):
+def cpu_baseline(spec, th_h, ph_h, alm_h, idx, y, m_gpu_h, adj_gpu_h, many_checks=None):
     """Oracle (FP64 direct sum, all host cores) on a bounded random sample of the
     workload's points, scaled linearly to the full point count.  Also returns the
     GPU forms' effective accuracy against it: synthesis on the sampled points, and the
@@ -233,6 +245,12 @@ def cpu_baseline(spec, th_h, ph_h, alm_h, idx, y, m_gpu_h, adj_gpu_h):
     err = {k: {"synthesis": oracle.eps_eff(v[:, idx], ref),
                "adjoint": oracle.eps_eff(wts * adj_gpu_h[k], wts * ref_adj)}
            for k, v in m_gpu_h.items()}
+    for k, mc in (many_checks or {}).items():
+        # several-map paths: the last map of the group against the same oracle values
+        if "synth" in mc:
+            err[k]["synthesis_many"] = oracle.eps_eff(mc["synth"], ref)
+        if "adjoint" in mc:
+            err[k]["adjoint_many"] = oracle.eps_eff(wts * mc["adjoint"], wts * ref_adj)
     return dict(value=per_step, unit="s", cores=cores, kind="oracle",
                 sample="%d random points of the %d-point workload: synthesis %.1f s + adjoint "
                        "%.1f s on %d threads, scaled linearly to all points" %
@@ -339,8 +357,10 @@ def main():
     maps = {}
     for prec, eps in forms:
         log("timing %s eps %.0e" % (prec, eps))
+        chk = None if args.no_cpu else {"idx": torch.from_numpy(idx).cuda(), "yfull": yfull}
         plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
-                               many=args.many if prec == "f32" else 0, autotune=args.autotune)
+                               many=args.many if prec == "f32" else 0, autotune=args.autotune,
+                               check=chk)
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
         maps[key] = m.detach().to(torch.float64).cpu().numpy()
@@ -404,7 +424,8 @@ def main():
     if not args.no_cpu:
         th_h = th.cpu().numpy()
         ph_h = ph.cpu().numpy()
-        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, idx, ysam, maps, adj_maps)
+        mchk = {k: v.pop("many_check") for k, v in results.items() if "many_check" in v}
+        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, idx, ysam, maps, adj_maps, mchk)
         out["cpu_baseline"] = cb
         out["eps_eff_on_sample"] = err
     if args.cpu_nufft:
