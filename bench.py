@@ -419,6 +419,13 @@ def main():
                         for k, v in results.items()}
     if "f64_eps1e-05" in results:
         out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / head["s_per_step"]
+        sm, am_ = head.get("synth_many"), head.get("adjoint_many")
+        if sm and am_ and sm.get("legendre") == "mfma":
+            # per map: FP32 form with the matrix-core Legendre step (16-map groups) against
+            # the plain FP64 form, synthesis + adjoint
+            out["speedup_f32_mfma_many_vs_f64_eps1e-5"] = (
+                results["f64_eps1e-05"]["s_per_step"] * 1e3
+                / (sm["synth_ms_per_map"] + am_["adjoint_ms_per_map"]))
     if "f64_eps1e-10" in results:
         out["f64_eps1e-10_s"] = results["f64_eps1e-10"]["s_per_step"]
     if not args.no_cpu:
