@@ -100,6 +100,65 @@ long fft_size(double target, long floor_n)
 const double kEsError[17] = {0, 0, 0, 0, 7.8e-4, 8.8e-5, 9.7e-6, 1.2e-6, 1.5e-7,
                              1.7e-8, 2.0e-9, 2.0e-10, 2.0e-11, 2.1e-12, 2.0e-13, 2.4e-14, 3.0e-15};
 
+// Interior-tap kernel weights of FP64 plans as polynomials.  Tap i of a point at
+// cell offset dx in (w/2 - 1, w/2] weighs psi((dx - i) 2 / w); with y = 2 dx - w + 1
+// in (-1, 1] that is a smooth function of y for 0 < i < w - 1 (the kernel's
+// square-root edges lie outside those intervals; the two edge taps keep the exact
+// formula).  Chebyshev interpolation at pdeg + 1 nodes in long double, converted to
+// monomial coefficients; accepted only if the double Horner evaluation stays within
+// 5e-15 of the kernel at 2001 points per tap (else the plan uses the exact formula).
+bool es_poly_fit(int w, double beta, std::vector<double> &coef)
+{
+    const int D = es_pdeg_rt(w), N = D + 1;
+    coef.assign((size_t)w * N, 0.0);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    auto psi = [&](long double z) {
+        long double t = 1.0L - z * z;
+        if (t < 0)
+            t = 0;
+        return expl((long double)beta * (sqrtl(t) - 1.0L));
+    };
+    auto zof = [&](long double y, int i) {
+        const long double dx = (y + 1.0L) / 2.0L + 0.5L * w - 1.0L;
+        return (dx - i) * 2.0L / w;
+    };
+    // monomial coefficients of the Chebyshev polynomials T_0 .. T_D
+    std::vector<long double> tm((size_t)N * N, 0.0L), f(N), c(N);
+    tm[0] = 1.0L;
+    if (N > 1)
+        tm[(size_t)N + 1] = 1.0L;
+    for (int k = 2; k < N; ++k)
+        for (int m = 0; m < N; ++m)
+            tm[(size_t)k * N + m] = (m > 0 ? 2.0L * tm[(size_t)(k - 1) * N + m - 1] : 0.0L) -
+                                    tm[(size_t)(k - 2) * N + m];
+    for (int i = 1; i < w - 1; ++i) {
+        for (int j = 0; j < N; ++j)
+            f[j] = psi(zof(cosl(pi * (j + 0.5L) / N), i));
+        for (int k = 0; k < N; ++k) {
+            long double acc = 0.0L;
+            for (int j = 0; j < N; ++j)
+                acc += f[j] * cosl(pi * k * (j + 0.5L) / N);
+            c[k] = 2.0L * acc / N;
+        }
+        c[0] *= 0.5L;
+        for (int m = 0; m < N; ++m) {
+            long double a = 0.0L;
+            for (int k = m; k < N; ++k)
+                a += c[k] * tm[(size_t)k * N + m];
+            coef[(size_t)i * N + m] = (double)a;
+        }
+        for (int t = 0; t <= 2000; ++t) {
+            const double y = -1.0 + t / 1000.0;
+            double v = coef[(size_t)i * N + D];
+            for (int k = D - 1; k >= 0; --k)
+                v = std::fma(v, y, coef[(size_t)i * N + k]);
+            if (fabsl((long double)v - psi(zof(y, i))) > 5e-15L)
+                return false;
+        }
+    }
+    return true;
+}
+
 int choose_w(double eps, int wmax)
 {
     for (int w = 4; w <= wmax; ++w)
@@ -623,6 +682,23 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
         }
     }
     // per-column stage, then the rocFFT plans it leaves to rocFFT
+    if (p->prec == GSHT_F64) {  // interior-tap weight polynomials (GSHT_ES_POLY=0: off)
+        const char *ep = getenv("GSHT_ES_POLY");
+        std::vector<double> coef;
+        if (!(ep && atoi(ep) == 0) && es_poly_fit(p->w, p->beta, coef)) {
+            if ((rc = dev_alloc(p, &p->es_poly, sizeof(double) * coef.size())) != GSHT_OK) {
+                free_plan(p);
+                return rc;
+            }
+            const hipError_t he = hipMemcpy(p->es_poly, coef.data(), sizeof(double) * coef.size(),
+                                            hipMemcpyHostToDevice);
+            if (he != hipSuccess) {
+                free_plan(p);
+                return fail(GSHT_EHIP, "copying the kernel polynomials failed: %s",
+                            hipGetErrorString(he));
+            }
+        }
+    }
     if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = setup_rows(p, s)) != GSHT_OK) { free_plan(p); return rc; }
     const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;

@@ -49,6 +49,14 @@ struct ColFFT {
     const void *tw = nullptr;
     const int32_t *perm = nullptr;
 };
+// Degree of the polynomials that give the FP64 kernel weights of the interior taps.
+template <int W>
+constexpr int es_pdeg()
+{
+    return W + 2 > 15 ? W + 2 : 15;
+}
+inline int es_pdeg_rt(int w) { return w + 2 > 15 ? w + 2 : 15; }
+
 // Position of element i of an in-LDS transform buffer with one padding slot after
 // every 2^sh elements (spreads the small-stride passes over the LDS banks), and the
 // slots an n-element buffer then takes.
@@ -149,6 +157,7 @@ struct gsht_plan {
     // even and odd output rows, two transforms of length n1 / 2) in one kernel
     int colmode = 0;
     int lds_psh = 31;         // LDS padding shift of the in-LDS transforms (31: none)
+    double *es_poly = nullptr;  // [w][pdeg + 1] interior-tap weight polynomials (FP64 plans)
     gsht::ColFFT cf_d, cf_h;  // lengths nd and n1 / 2
     void *twist = nullptr;    // [n1] exp(-2 pi i k / n1), plan precision (mode 2)
     // phi transforms of the grid rows: 1 = in-LDS kernels split by output parity

@@ -460,6 +460,7 @@ template <> __device__ inline double es_kernel<double>(double z, double beta)
 }
 
 struct GridGeom {
+    const double *poly;  // FP64 interior-tap kernel polynomials (or null), see point_weights
     double c1, c2, half;
     int a_min, n2, stride, nrows, t1, t2, nt2;
     int ps;      // row stride of a tile's LDS patch in cells (>= t2 + w - 1)
@@ -468,7 +469,9 @@ struct GridGeom {
 };
 
 // Cell indices and kernel weights of one point, relative to a patch origin.
-template <typename T, int W>
+// POLY: FP64 interior taps by polynomial when the plan has them (interpolation; the
+// spreading kernels keep the exact formula, which measured faster there).
+template <typename T, int W, bool POLY = false>
 __device__ inline void point_weights(double th, double ph, const GridGeom &g, int row0, int col0,
                                      T beta, int &lr, int &lc, T (&wx)[W], T (&wy)[W])
 {
@@ -478,6 +481,32 @@ __device__ inline void point_weights(double th, double ph, const GridGeom &g, in
     lc = c.bi - col0;
     const T sc = (T)(2.0 / W);
     const T fx = (T)dx, fy = (T)dy;
+    if constexpr (POLY && std::is_same<T, double>::value) {
+        if (g.poly != nullptr) {
+            // FP64: the two edge taps (whose interval ends at the kernel's square-root
+            // edge) exactly; each interior tap i by its polynomial in y = 2 dx - W + 1
+            // (the offset mapped to (-1, 1]), fitted on the host to ~1e-15 absolute.
+            constexpr int PD = es_pdeg<W>();
+            const double yx = 2.0 * dx - (double)(W - 1), yy = 2.0 * dy - (double)(W - 1);
+            wx[0] = es_kernel<T>(fx * sc, beta);
+            wy[0] = es_kernel<T>(fy * sc, beta);
+            wx[W - 1] = es_kernel<T>((fx - (T)(W - 1)) * sc, beta);
+            wy[W - 1] = es_kernel<T>((fy - (T)(W - 1)) * sc, beta);
+#pragma unroll
+            for (int i = 1; i < W - 1; ++i) {
+                const double *c = g.poly + i * (PD + 1);
+                double px = c[PD], py = c[PD];
+#pragma unroll
+                for (int k = PD - 1; k >= 0; --k) {
+                    px = fma(px, yx, c[k]);
+                    py = fma(py, yy, c[k]);
+                }
+                wx[i] = px;
+                wy[i] = py;
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < W; ++i) {
         wx[i] = es_kernel<T>((fx - (T)i) * sc, beta);
@@ -515,7 +544,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
     for (int p = ck.y + threadIdx.x; p < ck.z; p += NUFFT_THREADS) {
         T wx[W], wy[W];
         int lr, lc;
-        point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
+        point_weights<T, W, true>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
         if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
             continue;  // cannot happen for points sorted by the same arithmetic
         T ar = 0, ai = 0;
@@ -836,6 +865,7 @@ static GridGeom make_geom(const gsht_plan &p)
     g.ps = p.t2 + p.w - 1 + p.patch_pad;
     g.sorder = p.spread_order;
     g.npts = p.npts;
+    g.poly = p.es_poly;
     return g;
 }
 
