@@ -419,3 +419,24 @@ def test_lds_padding_is_bitwise_neutral(G, monkeypatch, lmax, mmax, spin, prec):
     monkeypatch.setenv("GSHT_LDS_PAD", "1")
     with pytest.raises(G.GshtError):
         G.Plan(dev(th), dev(ph), lmax, mmax, spin, 1e-5, prec)
+
+
+@pytest.mark.parametrize("spin,eps", [(2, 1e-10), (0, 1e-5), (1, 1e-13)])
+def test_interior_tap_polynomials_match_exact_weights(G, monkeypatch, spin, eps):
+    """FP64 interpolation with the host-fitted interior-tap polynomials against the
+    exact kernel formula (GSHT_ES_POLY=0): the weights differ by at most ~5e-15, so
+    the maps agree far below epsilon; both stay within epsilon of the oracle."""
+    say("es poly", spin, eps)
+    lmax = 160
+    rng = np.random.default_rng(800 + spin)
+    th, ph = wl.uniform_sphere(30000, rng)
+    a = wl.gaussian_alm(lmax, lmax, spin, rng)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("GSHT_ES_POLY", flag)
+        plan = G.Plan(dev(th), dev(ph), lmax, lmax, spin, eps, "f64")
+        outs.append(plan.synth(dev(a)).cpu().numpy())
+        plan.close()
+    assert rel_l2(outs[0], outs[1]) <= 1e-13
+    ref = oracle.synth(a, lmax, lmax, spin, th[:3000], ph[:3000])
+    assert oracle.eps_eff(outs[0][:, :3000], ref) <= eps
