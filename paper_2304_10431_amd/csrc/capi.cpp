@@ -5,6 +5,7 @@
 #include <rocfft/rocfft.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -627,9 +628,33 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     return GSHT_OK;
 }
 
+// Opt-in timing of the plan-creation phases (GSHT_PLAN_TRACE=1: one line per phase on
+// stderr; the stream is synchronised at each mark, so traced creation is slower).
+struct PlanTrace {
+    bool on;
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t;
+    explicit PlanTrace(hipStream_t s_) : s(s_), t(std::chrono::steady_clock::now())
+    {
+        const char *e = getenv("GSHT_PLAN_TRACE");
+        on = e && atoi(e) != 0;
+    }
+    void mark(const char *what)
+    {
+        if (!on)
+            return;
+        (void)hipStreamSynchronize(s);
+        const auto now = std::chrono::steady_clock::now();
+        fprintf(stderr, "gsht plan: %-18s %9.3f ms\n", what,
+                std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
+
 int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double *theta,
                      const double *phi, int64_t npts, double eps, int prec, hipStream_t s)
 {
+    PlanTrace tr(s);
     int rc;
     gsht_plan *p = new gsht_plan();
     p->lmax = lmax;
@@ -654,7 +679,9 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
                     (long long)ws);
     }
     std::call_once(g_fft_once, []() { rocfft_setup(); });
+    tr.mark("sizes");
     if ((rc = setup_legendre(p, s, true)) != GSHT_OK) { free_plan(p); return rc; }
+    tr.mark("legendre tables");
     if ((rc = dev_alloc(p, &p->D, (size_t)p->ncol * p->nd * cs)) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = dev_alloc(p, &p->E, (size_t)p->ncol * p->n1 * cs)) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = dev_alloc(p, &p->G, (size_t)p->nrows * gcols * cs)) != GSHT_OK) { free_plan(p); return rc; }
@@ -663,6 +690,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     if ((rc = dev_alloc(p, &p->sph, sizeof(double) * (size_t)std::max<int64_t>(npts, 1))) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = dev_alloc(p, &p->perm, sizeof(int32_t) * (size_t)std::max<int64_t>(npts, 1))) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = dev_alloc(p, &p->tile_start, sizeof(int32_t) * (size_t)(p->ntiles + 1))) != GSHT_OK) { free_plan(p); return rc; }
+    tr.mark("allocations");
     {
         int64_t ninv = 0;
         hipError_t e = run_binsort(*p, theta, phi, s, &ninv);
@@ -675,11 +703,13 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
             return fail(GSHT_EINVAL, "%lld point(s) have theta outside [0, pi] or non-finite phi",
                         (long long)ninv);
         }
+        tr.mark("bin sort");
         e = build_tile_colors(*p, s);
         if (e != hipSuccess) {
             free_plan(p);
             return fail(GSHT_EHIP, "tile colouring failed: %s", hipGetErrorString(e));
         }
+        tr.mark("tile colours");
     }
     // per-column stage, then the rocFFT plans it leaves to rocFFT
     if (p->prec == GSHT_F64) {  // interior-tap weight polynomials (GSHT_ES_POLY=0: off)
@@ -699,8 +729,10 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
             }
         }
     }
+    tr.mark("kernel polynomials");
     if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
     if ((rc = setup_rows(p, s)) != GSHT_OK) { free_plan(p); return rc; }
+    tr.mark("column/row setup");
     const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;
     rc = GSHT_OK;
     if (p->colmode == 0) {
@@ -732,6 +764,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
         p->fftwork_bytes = wb;
     }
     p->workspace_bytes += (int64_t)wb;
+    tr.mark("library FFT plans");
     *out = p;
     return ok();
 }

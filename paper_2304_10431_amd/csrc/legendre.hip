@@ -25,18 +25,9 @@ template <> struct cplx<double> { using type = double2; };
 
 // ---- host: start data ------------------------------------------------------
 
-// sqrt((2 l0 + 1)/(4 pi) * binom(2 l0, b)) as (mantissa, exponent), in long double.
-static void start_factor(int l0, int b, double *mant, int *ex)
+// sqrt((2 l0 + 1)/(4 pi) * X) as (mantissa, exponent) for X = v 2^e, in long double.
+static void start_factor(long double v, long e, int l0, double *mant, int *ex)
 {
-    int k = b < 2 * l0 - b ? b : 2 * l0 - b;
-    long double v = 1.0L;
-    long e = 0;
-    for (int i = 1; i <= k; ++i) {
-        int ee;
-        v *= (long double)(2 * l0 - k + i) / (long double)i;
-        v = frexpl(v, &ee);
-        e += ee;
-    }
     v *= (long double)(2 * l0 + 1) / (4.0L * 3.14159265358979323846264338327950288L);
     {
         int ee;
@@ -60,26 +51,63 @@ static void start_factor(int l0, int b, double *mant, int *ex)
 
 std::vector<StartInfo> make_start_info(int lmax, int mmax, int spin)
 {
+    // Both channels' single Goldberg term at l0 = max(m, s) carries the binomial
+    // X(m) = binom(2 l0, |m - s|) (binom(2 l0, m + s) for the channel -s is the same
+    // number).  X(s) = 1, and one ratio per step gives the others:
+    //   X(m + 1) = X(m) (2m + 2)(2m + 1) / ((m + 1 - s)(m + 1 + s))   (m >= s),
+    //   X(m - 1) = X(m) (s + m) / (s - m + 1)                        (m <= s),
+    // in long double with a separate binary exponent, O(mmax) in all.
+    std::vector<long double> xv((size_t)mmax + 1);
+    std::vector<long> xe((size_t)mmax + 1);
+    auto renorm = [](long double &v, long &e) {
+        int ee;
+        v = frexpl(v, &ee);
+        e += ee;
+    };
+    {
+        long double v = 1.0L;
+        long e = 0;
+        if (spin <= mmax) {
+            xv[(size_t)spin] = v;
+            xe[(size_t)spin] = e;
+        }
+        for (int m = spin; m < mmax; ++m) {
+            v *= (long double)(2 * m + 2) * (long double)(2 * m + 1) /
+                 ((long double)(m + 1 - spin) * (long double)(m + 1 + spin));
+            renorm(v, e);
+            xv[(size_t)m + 1] = v;
+            xe[(size_t)m + 1] = e;
+        }
+        v = 1.0L;
+        e = 0;
+        for (int m = spin; m > 0; --m) {
+            v *= (long double)(spin + m) / (long double)(spin - m + 1);
+            renorm(v, e);
+            if (m - 1 <= mmax) {
+                xv[(size_t)m - 1] = v;
+                xe[(size_t)m - 1] = e;
+            }
+        }
+    }
     std::vector<StartInfo> out((size_t)mmax + 1);
     for (int m = 0; m <= mmax; ++m) {
         StartInfo &si = out[(size_t)m];
         si.l0 = m > spin ? m : spin;
         si.pad = 0;
+        double mant;
+        int ex;
+        start_factor(xv[(size_t)m], xe[(size_t)m], si.l0, &mant, &ex);
         for (int c = 0; c < 2; ++c) {
             const int sg = c == 0 ? spin : -spin;
             // single term of the Goldberg sum at l0: index r, half-angle exponents
             const int r = (m - sg) > 0 ? (m - sg) : 0;
             const int b = 2 * r + sg - m;
             const int a = 2 * si.l0 - b;
-            double mant;
-            int ex;
-            start_factor(si.l0, b, &mant, &ex);
-            if (((m + si.l0 - r - sg) & 1) != 0)
-                mant = -mant;
+            const double mc = ((m + si.l0 - r - sg) & 1) != 0 ? -mant : mant;
             if (c == 0) {
-                si.a_p = a; si.b_p = b; si.ex_p = ex; si.mant_p = mant;
+                si.a_p = a; si.b_p = b; si.ex_p = ex; si.mant_p = mc;
             } else {
-                si.a_m = a; si.b_m = b; si.ex_m = ex; si.mant_m = mant;
+                si.a_m = a; si.b_m = b; si.ex_m = ex; si.mant_m = mc;
             }
         }
         (void)lmax;
