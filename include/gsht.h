@@ -130,6 +130,21 @@ int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin,
                      const double *theta, const double *phi, int64_t npts,
                      double epsilon, gsht_precision prec, void *hip_stream);
 
+/*
+ * New point set for an existing plan (same lmax, mmax, spin, epsilon, precision):
+ * theta/phi [npts] FP64 device pointers with npts at most the count the plan was
+ * created with.  Only the bin sort is redone (the Legendre tables, column set-up and
+ * FFT plans do not depend on the points), so moving points costs a few milliseconds
+ * instead of a plan creation: the lensing iterations of Sect. 4 deflect the same
+ * pixels differently at every step.  Synchronises hip_stream first (transforms still
+ * queued use the old points) and before returning.  GSHT_EINVAL for invalid points,
+ * after which the plan must get valid points before its next transform.  Calls on one
+ * plan must not overlap with this one, and a graph captured earlier on this plan holds
+ * the old sort's buffers: capture again after moving the points.
+ */
+int gsht_plan_set_points(gsht_plan *p, const double *theta, const double *phi, int64_t npts,
+                         void *hip_stream);
+
 /* Synthesis with a plan: alm -> map (layouts as in gsht_synth_general).  Does not
  * allocate and does not synchronise.  Calls on one plan must not overlap.
  * Graph capture: gsht_plan_synth, gsht_plan_adjoint and, once a first call has

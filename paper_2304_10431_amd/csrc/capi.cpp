@@ -661,6 +661,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     p->mmax = mmax;
     p->spin = spin;
     p->npts = npts;
+    p->npts_cap = npts;
     p->eps = eps;
     p->prec = prec;
     choose_sizes(p);
@@ -942,6 +943,44 @@ int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin, const double *
         return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
     return plan_create_impl(p, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec,
                             (hipStream_t)hip_stream);
+}
+
+int gsht_plan_set_points(gsht_plan *p, const double *theta, const double *phi, int64_t npts,
+                         void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan is NULL");
+    if (npts < 0 || npts > p->npts_cap)
+        return fail(GSHT_EINVAL, "npts must be in [0, %lld] (the plan's capacity), got %lld",
+                    (long long)p->npts_cap, (long long)npts);
+    if (npts > 0 && (!theta || !phi))
+        return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(hipStreamSynchronize(s));  // earlier transforms may still read the old sort
+    // the chunk list and tile items of the previous sort are rebuilt
+    for (void **q : {(void **)&p->chunks, (void **)&p->tile_items}) {
+        if (!*q)
+            continue;
+        auto it = std::find(p->allocations.begin(), p->allocations.end(), *q);
+        if (it != p->allocations.end())
+            p->allocations.erase(it);
+        (void)hipFree(*q);
+        *q = nullptr;
+    }
+    p->npts = npts;
+    p->nchunks = 0;
+    int64_t ninv = 0;
+    hipError_t e = run_binsort(*p, theta, phi, s, &ninv);
+    if (e != hipSuccess)
+        return fail(GSHT_EHIP, "bin sort failed: %s", hipGetErrorString(e));
+    if (ninv > 0)
+        return fail(GSHT_EINVAL, "%lld point(s) have theta outside [0, pi] or non-finite phi "
+                                 "(the plan must get valid points before its next use)",
+                    (long long)ninv);
+    e = build_tile_colors(*p, s);
+    if (e != hipSuccess)
+        return fail(GSHT_EHIP, "tile colouring failed: %s", hipGetErrorString(e));
+    return ok();
 }
 
 int gsht_plan_synth(gsht_plan *p, const void *alm, void *map, void *hip_stream)

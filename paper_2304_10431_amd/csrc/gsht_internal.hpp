@@ -101,6 +101,7 @@ struct gsht_plan {
     // problem
     int lmax = 0, mmax = 0, spin = 0, ncomp = 1;
     int64_t npts = 0;
+    int64_t npts_cap = 0;  // points the sorted-coordinate buffers hold (set at creation)
     double eps = 0;
     int prec = GSHT_F64;
     int64_t nalm = 0;

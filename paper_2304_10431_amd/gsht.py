@@ -58,6 +58,7 @@ _SIGS = {
     "gsht_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
     "gsht_adjoint_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
     "gsht_plan_create": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
+    "gsht_plan_set_points": [_vp, _vp, _vp, _i64, _vp],
     "gsht_plan_synth": [_vp, _vp, _vp, _vp],
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
     "gsht_plan_synth_grad": [_vp, _vp, _vp, _vp],
@@ -195,6 +196,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_points(self, theta, phi):
+        """Move the plan to new points (at most as many as it was created with); only
+        the bin sort is redone."""
+        npts = _coords(theta, phi)
+        _check(_lib.gsht_plan_set_points(self._h, _ptr(theta), _ptr(phi), npts, _stream()))
+        self.npts = npts
 
     def info(self) -> dict:
         inf = PlanInfo()

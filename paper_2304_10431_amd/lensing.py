@@ -50,6 +50,26 @@ class Lensing:
         self.plan.close()
         self.dplan.close()
 
+    def update(self, plm, olm=None):
+        """New lensing potential (and curl potential) on the same points: the deflection
+        is resynthesised and the lensed plan moved to the new deflected points
+        (gsht_plan_set_points), without building new plans."""
+        plm_, olm_, eps, prec = self._pot
+        cdt = gsht._CDT[gsht._PREC[prec]]
+        if (olm is None) != (olm_ is None):
+            raise ValueError("update must keep the same potentials (curl given or not)")
+        if olm is None:
+            glm = gsht.alm_lscale(plm.to(cdt).reshape(1, -1).contiguous(), self.lmax_p, self.mmax_p)
+            self.alpha = self.dplan.synth_grad(glm)
+        else:
+            glm = gsht.alm_lscale(torch.stack([plm.to(cdt), olm.to(cdt)]).contiguous(),
+                                  self.lmax_p, self.mmax_p)
+            self.alpha = self.dplan.synth(glm)
+        self._pot = (plm.to(cdt), None if olm is None else olm.to(cdt), eps, prec)
+        self.theta_d, self.phi_d, self.chi = gsht.deflect(self.theta, self.phi, self.alpha,
+                                                          want_chi=self.spin > 0)
+        self.plan.set_points(self.theta_d, self.phi_d)
+
     def forward(self, alm):
         """Lensed map [ncomp][npts]."""
         m = self.plan.synth(alm)
