@@ -79,11 +79,11 @@ def legendre_flops(lmax, mmax, spin, npairs):
 
 
 def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, autotune=False,
-              check=None):
+              check=None, sigma="tuned"):
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     cdt = torch.complex128 if prec == "f64" else torch.complex64
     t0 = time.time()
-    plan = gsht.Plan(th, ph, lmax, mmax, spin, eps, prec)
+    plan = gsht.Plan(th, ph, lmax, mmax, spin, eps, prec, sigma=sigma)
     if autotune:
         plan.autotune()
     torch.cuda.synchronize()
@@ -304,6 +304,9 @@ def main():
                     help="also time the plain CPU NUFFT-based SHT on the whole workload "
                          "(FP64, eps 1e-10; minutes at lmax 2048)")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--sigma", default="tuned",
+                    help="oversampling factor of the plans: tuned (gsht_plan_create_tuned picks "
+                         "the fastest of 2, 1.5, 1.25 at plan time) or one of 2, 1.5, 1.25")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (counter calibration)")
     args = ap.parse_args()
@@ -360,7 +363,8 @@ def main():
         chk = None if args.no_cpu else {"idx": torch.from_numpy(idx).cuda(), "yfull": yfull}
         plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
                                many=args.many if prec == "f32" else 0, autotune=args.autotune,
-                               check=chk)
+                               check=chk,
+                               sigma=args.sigma if args.sigma == "tuned" else float(args.sigma))
         key = "%s_eps%.0e" % (prec, eps)
         results[key] = r
         maps[key] = m.detach().to(torch.float64).cpu().numpy()
@@ -401,6 +405,7 @@ def main():
                    "npts": npts, "lmax": lmax, "mmax": mmax, "spin": spin},
         "forms": {k: {"s_per_step": v["s_per_step"], "synth_ms": v["synth_ms"],
                       "adjoint_ms": v["adjoint_ms"], "plan_s": v["plan_s"],
+                      "sigma": v["info"]["sigma"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
                       "column_mode": v["info"]["column_mode"],
                       "legendre_shapes": [v["info"]["syn_r"], v["info"]["adj_r"], v["info"]["adj_b"]],

@@ -124,11 +124,38 @@ const char *gsht_last_error(void);
  * gsht_plan_create validates the arguments, copies and bin-sorts the points
  * into grid tiles, builds the FFT plans and allocates all workspace; it
  * synchronises hip_stream before returning.  *p is set to NULL on failure.
- * theta/phi are only read during the call.
+ * theta/phi are only read during the call.  The oversampling factor is 2; see
+ * gsht_plan_create_sigma and gsht_plan_create_tuned for the others.
  */
 int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin,
                      const double *theta, const double *phi, int64_t npts,
                      double epsilon, gsht_precision prec, void *hip_stream);
+
+/*
+ * Plan with a chosen oversampling factor sigma (Sect. 3: about 1.2 to 2; smaller
+ * sigma means a smaller torus but a wider kernel for the same epsilon).  sigma must
+ * be 2 (what gsht_plan_create uses), 1.5 or 1.25: the kernel's support w and shape
+ * beta come from error tables calibrated for these three.  GSHT_EUNSUPPORTED if
+ * epsilon needs a wider kernel than the precision's kernels go (16 cells in FP64,
+ * 8 in FP32).  Otherwise as gsht_plan_create.
+ */
+int gsht_plan_create_sigma(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
+                           const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                           double sigma, void *hip_stream);
+
+/*
+ * Plan whose sigma is picked by measurement: builds the plan at every sigma of
+ * gsht_plan_create_sigma that reaches epsilon, times one synthesis + adjoint of each
+ * on these points (best of two after a warm-up; zero inputs, since the work does
+ * not depend on the values), keeps the fastest and frees the rest.  Holds at most two
+ * plans plus one coefficient and one map buffer at a time; a candidate that does not
+ * fit is skipped (the sigma = 2 plan must build).  Takes a few transforms' time and,
+ * in a new process, the FFT library's set-up for each new length.
+ * gsht_plan_get_info reports the sigma chosen.
+ */
+int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
+                           const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                           void *hip_stream);
 
 /*
  * New point set for an existing plan (same lmax, mmax, spin, epsilon, precision):
@@ -378,6 +405,9 @@ typedef struct {
     int adj_r, adj_b;   /* Legendre adjoint: slices per wave, degrees per reduction block */
     int row_mode;       /* phi transforms of the grid rows: 1 = in-LDS kernels split by
                            output parity (complex grids), 0 = library FFT */
+    double sigma;       /* nominal oversampling factor (2, 1.5 or 1.25); n1 and n2 are
+                           the FFT-friendly lengths at least about sigma (2 lmax + 1) and
+                           sigma (2 mmax + 1) */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */

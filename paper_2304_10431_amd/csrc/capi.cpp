@@ -96,10 +96,25 @@ long fft_size(double target, long floor_n)
     return best;
 }
 
-// Relative L2 error of the 2-D type-2 NUFFT with this kernel at oversampling 2,
-// beta = 2.3 w, measured for w = 4..16 on random Fourier series.
-const double kEsError[17] = {0, 0, 0, 0, 7.8e-4, 8.8e-5, 9.7e-6, 1.2e-6, 1.5e-7,
-                             1.7e-8, 2.0e-9, 2.0e-10, 2.0e-11, 2.1e-12, 2.0e-13, 2.4e-14, 3.0e-15};
+// Kernel settings by oversampling factor sigma (Sect. 3: sigma between about 1.2
+// and 2 trades grid size against kernel support).  err[w] is the relative L2 error
+// of the 2-D type-2 NUFFT with support w and beta = beta_per_w * w, measured for
+// w = 4..16 on random Fourier series (81 x 81 modes, 2000 random points, torus of
+// sigma * 81 cells); beta_per_w is the value that minimised the error for mid-range w
+// (for sigma = 2 it matches the 2.3 w of the exponential-of-semicircle literature).
+struct EsSetting {
+    double sigma, beta_per_w;
+    double err[17];
+};
+const EsSetting kEs[3] = {
+    {2.0, 2.3, {0, 0, 0, 0, 7.8e-4, 8.8e-5, 9.7e-6, 1.2e-6, 1.5e-7, 1.7e-8, 2.0e-9, 2.0e-10,
+                2.0e-11, 2.1e-12, 2.0e-13, 2.4e-14, 3.0e-15}},
+    {1.5, 2.05, {0, 0, 0, 0, 3.9e-3, 5.6e-4, 7.6e-5, 1.1e-5, 2.0e-6, 3.9e-7, 7.2e-8, 1.2e-8,
+                 1.8e-9, 2.5e-10, 3.8e-11, 7.4e-12, 1.5e-12}},
+    {1.25, 1.85, {0, 0, 0, 0, 1.3e-2, 2.9e-3, 5.9e-4, 1.1e-4, 2.5e-5, 7.5e-6, 2.3e-6, 6.4e-7,
+                  1.6e-7, 3.3e-8, 6.2e-9, 1.2e-9, 4.0e-10}},
+};
+constexpr int kNumEs = 3;
 
 // Interior-tap kernel weights of FP64 plans as polynomials.  Tap i of a point at
 // cell offset dx in (w/2 - 1, w/2] weighs psi((dx - i) 2 / w); with y = 2 dx - w + 1
@@ -160,12 +175,23 @@ bool es_poly_fit(int w, double beta, std::vector<double> &coef)
     return true;
 }
 
-int choose_w(double eps, int wmax)
+// Smallest support whose calibrated error is at most eps / 4.  If none up to wmax
+// is: wmax for the default sigma = 2 (the closest the plan gets), 0 (not reachable)
+// for the others.
+int choose_w(double eps, int wmax, int set)
 {
     for (int w = 4; w <= wmax; ++w)
-        if (kEsError[w] <= 0.25 * eps)
+        if (kEs[set].err[w] <= 0.25 * eps)
             return w;
-    return wmax;
+    return set == 0 ? wmax : 0;
+}
+
+int es_set_of(double sigma)
+{
+    for (int i = 0; i < kNumEs; ++i)
+        if (std::fabs(sigma - kEs[i].sigma) < 1e-9)
+            return i;
+    return -1;
 }
 
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
@@ -309,9 +335,11 @@ void choose_sizes(gsht_plan *p)
         ++nt;
     p->ntheta = (int)nt;
     p->nd = 2 * p->ntheta - 2;
-    p->w = choose_w(p->eps, p->prec == GSHT_F64 ? 16 : 8);
-    p->beta = 2.3 * p->w;
-    const double sigma = 2.0;
+    p->w = choose_w(p->eps, p->prec == GSHT_F64 ? 16 : 8, p->es_set);
+    if (p->w == 0)
+        return;  // not reachable at this sigma; the caller reports it
+    p->beta = kEs[p->es_set].beta_per_w * p->w;
+    const double sigma = kEs[p->es_set].sigma;
     p->n1 = (int)fft_size(sigma * (2 * p->lmax + 1), std::max(2 * p->w + 4, 2 * p->lmax + 2));
     p->n2 = (int)fft_size(sigma * (2 * p->mmax + 1), std::max(2 * p->w + 4, 2 * p->mmax + 2));
     p->a_min = -(p->w / 2);
@@ -575,9 +603,8 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     std::vector<int> rad;
     const int nh = p->n1 / 2;
     const bool fit_d = (size_t)lds_pad_n(p->nd, psh) * cs <= lim && col_radices(p->nd, rad);
-    const int novl = std::max(0, 2 * p->lmax - nh + 1);  // fold overlap kept in LDS
     const bool fit_2 = fit_d && p->n1 % 2 == 0 && nh > p->lmax &&
-                       (size_t)(lds_pad_n(std::max(p->nd, nh), psh) + novl) * cs <= lim &&
+                       (size_t)lds_pad_n(std::max(p->nd, nh), psh) * cs <= lim &&
                        std::max(p->nd, nh) <= column_half_maxn(p->prec) && col_radices(nh, rad);
     int mode = fit_2 ? 2 : fit_d ? 1 : 0;
     const char *e = getenv("GSHT_COLUMN_MODE");
@@ -652,11 +679,13 @@ struct PlanTrace {
 };
 
 int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double *theta,
-                     const double *phi, int64_t npts, double eps, int prec, hipStream_t s)
+                     const double *phi, int64_t npts, double eps, int prec, hipStream_t s,
+                     int es_set = 0)
 {
     PlanTrace tr(s);
     int rc;
     gsht_plan *p = new gsht_plan();
+    p->es_set = es_set;
     p->lmax = lmax;
     p->mmax = mmax;
     p->spin = spin;
@@ -665,6 +694,13 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     p->eps = eps;
     p->prec = prec;
     choose_sizes(p);
+    if (p->w == 0) {
+        const double sg = kEs[es_set].sigma;
+        delete p;
+        return fail(GSHT_EUNSUPPORTED,
+                    "epsilon %g is not reachable at oversampling %.2f with kernel supports up to %d",
+                    eps, sg, prec == GSHT_F64 ? 16 : 8);
+    }
     const size_t cs = csize(prec), rs = cs / 2;
     const size_t gcols = spin ? (size_t)p->n2 : (size_t)p->n2 / 2 + 1;
     // workspace estimate (before allocating anything large)
@@ -945,6 +981,25 @@ int gsht_plan_create(gsht_plan **p, int lmax, int mmax, int spin, const double *
                             (hipStream_t)hip_stream);
 }
 
+int gsht_plan_create_sigma(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
+                           const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                           double sigma, void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan output pointer is NULL");
+    *p = nullptr;
+    const int set = es_set_of(sigma);
+    if (set < 0)
+        return fail(GSHT_EINVAL, "sigma must be 2, 1.5 or 1.25, got %g", sigma);
+    int rc = check_common(lmax, mmax, spin, npts, epsilon, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (npts > 0 && (!theta || !phi))
+        return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
+    return plan_create_impl(p, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec,
+                            (hipStream_t)hip_stream, set);
+}
+
 int gsht_plan_set_points(gsht_plan *p, const double *theta, const double *phi, int64_t npts,
                          void *hip_stream)
 {
@@ -999,6 +1054,87 @@ int gsht_plan_adjoint(gsht_plan *p, const void *map, void *alm, void *hip_stream
     if (!alm || (!map && p->npts > 0))
         return fail(GSHT_EINVAL, "alm/map must not be NULL");
     return plan_adjoint_impl(p, map, alm, (hipStream_t)hip_stream);
+}
+
+int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
+                           const double *phi, int64_t npts, double epsilon, gsht_precision prec,
+                           void *hip_stream)
+{
+    if (!p)
+        return fail(GSHT_EINVAL, "plan output pointer is NULL");
+    *p = nullptr;
+    int rc = check_common(lmax, mmax, spin, npts, epsilon, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (npts > 0 && (!theta || !phi))
+        return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int ncomp = spin ? 2 : 1;
+    const size_t cs = csize((int)prec);
+    const size_t alm_bytes = cs * ncomp * (size_t)((int64_t)(mmax + 1) * (lmax + 1) -
+                                                   (int64_t)mmax * (mmax + 1) / 2);
+    const size_t map_bytes = cs / 2 * ncomp * (size_t)std::max<int64_t>(npts, 1);
+    void *alm = nullptr, *map = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    gsht_plan *best = nullptr;
+    float best_ms = -1.0f;
+    auto cleanup = [&]() {
+        if (alm) (void)hipFree(alm);
+        if (map) (void)hipFree(map);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&alm, alm_bytes) != hipSuccess || hipMalloc(&map, map_bytes) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(GSHT_ENOMEM, "tuning buffers could not be allocated");
+    }
+    if (launch_zero(alm, alm_bytes, s) != hipSuccess || launch_zero(map, map_bytes, s) != hipSuccess) {
+        cleanup();
+        return fail(GSHT_EHIP, "clearing the tuning buffers failed");
+    }
+    for (int set = 0; set < kNumEs; ++set) {
+        gsht_plan *c = nullptr;
+        rc = plan_create_impl(&c, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec, s, set);
+        if (rc != GSHT_OK) {
+            if (set == 0) {  // the default setting must build
+                cleanup();
+                return rc;
+            }
+            continue;  // not reachable at this sigma, or no room for a second plan
+        }
+        // one synthesis + adjoint to warm up, then the best of two
+        float t = -1.0f;
+        bool good = plan_synth_impl(c, alm, map, s) == GSHT_OK &&
+                    plan_adjoint_impl(c, map, alm, s) == GSHT_OK;
+        for (int rep = 0; good && rep < 2; ++rep) {
+            float ms = 0;
+            good = hipEventRecord(e0, s) == hipSuccess && plan_synth_impl(c, alm, map, s) == GSHT_OK &&
+                   plan_adjoint_impl(c, map, alm, s) == GSHT_OK &&
+                   hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                   hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (good)
+                t = (t < 0 || ms < t) ? ms : t;
+        }
+        if (!good) {
+            free_plan(c);
+            if (best)
+                free_plan(best);
+            cleanup();
+            return fail(GSHT_EHIP, "timing the candidate plan at sigma %.2f failed", kEs[set].sigma);
+        }
+        if (best_ms < 0 || t < best_ms) {
+            if (best)
+                free_plan(best);
+            best = c;
+            best_ms = t;
+        } else {
+            free_plan(c);
+        }
+    }
+    cleanup();
+    *p = best;
+    return ok();
 }
 
 int gsht_plan_autotune(gsht_plan *p, void *hip_stream)
@@ -1615,6 +1751,7 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->n2 = p->n2;
     info->w = p->w;
     info->beta = p->beta;
+    info->sigma = kEs[p->es_set].sigma;
     info->nrows = p->nrows;
     info->a_min = p->a_min;
     info->tile1 = p->t1;

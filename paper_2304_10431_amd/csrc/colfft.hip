@@ -290,14 +290,8 @@ __device__ inline C cmulc(C a, C b)  // a * conj(b)
     return o;
 }
 
-// LDS of mode 2: the column buffer, then the overlap differences (residues
-// nh - lmax .. lmax of the fold, present when nh <= 2 lmax).
+// LDS of mode 2: the column buffer (the transforms of lengths nd and nh = n1 / 2).
 __host__ __device__ inline int col_half_lds_n(int nd, int nh) { return nd > nh ? nd : nh; }
-__host__ __device__ inline int col_half_ovl(int lmax, int nh)
-{
-    const int n = 2 * lmax - nh + 1;
-    return n > 0 ? n : 0;
-}
 
 struct ColArgs {
     const double *kf1, *kf2;
@@ -338,9 +332,13 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
     // Fold: residue i < nh receives c_i (i <= lmax) and c_{i - nh} (i >= nh - lmax).
     // Only the even-row input ye = c_i + c_{i-nh} stays in registers: the odd-row
     // input is t^i (c_i - c_{i-nh}) (t^{-nh} = -1), i.e. t^i (+-ye) where only one
-    // term exists; the few residues with both keep c_i - c_{i-nh} in LDS (ovl).
+    // term exists.  The residues with both (2 lmax + 1 - nh of them: one at
+    // oversampling 2, a quarter of the column at 1.5) keep c_i - c_{i-nh} in this
+    // column of E, which holds nothing until its rows are written after the
+    // transforms; each thread reads back only what it wrote, so no barrier is needed
+    // for it, and the LDS stays at the column's own size.
     const int ov0 = nh - a.lmax;
-    C *ovl = X + lds_pad_n(col_half_lds_n(a.nd, nh), sh);
+    C *ovl = ec;
     C ye[MAXV];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
@@ -681,9 +679,8 @@ template <typename T>
 size_t col_lds(const gsht_plan &p)
 {
     const int sh = p.lds_psh;
-    const int n = p.colmode == 2
-                      ? lds_pad_n(col_half_lds_n(p.nd, p.n1 / 2), sh) + col_half_ovl(p.lmax, p.n1 / 2)
-                      : lds_pad_n(p.nd, sh);
+    const int n = p.colmode == 2 ? lds_pad_n(col_half_lds_n(p.nd, p.n1 / 2), sh)
+                                 : lds_pad_n(p.nd, sh);
     return sizeof(typename cx<T>::type) * (size_t)n;
 }
 

@@ -108,6 +108,7 @@ struct gsht_plan {
     // grids
     int ntheta = 0, nd = 0, n1 = 0, n2 = 0, w = 0;
     double beta = 0;
+    int es_set = 0;  // kernel setting (oversampling factor) index
     int nrows = 0, a_min = 0;
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
     int patch_pad = 0;     // extra cells per LDS patch row (bank spreading)

@@ -47,7 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("ntile2", ctypes.c_int), ("nchunks", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("column_mode", ctypes.c_int),
                 ("spread_colors", ctypes.c_int), ("syn_r", ctypes.c_int), ("adj_r", ctypes.c_int),
-                ("adj_b", ctypes.c_int), ("row_mode", ctypes.c_int)]
+                ("adj_b", ctypes.c_int), ("row_mode", ctypes.c_int), ("sigma", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -58,6 +58,8 @@ _SIGS = {
     "gsht_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
     "gsht_adjoint_synth_general": [_vp, _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp, _vp],
     "gsht_plan_create": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
+    "gsht_plan_create_sigma": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _d, _vp],
+    "gsht_plan_create_tuned": [ctypes.POINTER(_vp), _i, _i, _i, _vp, _vp, _i64, _d, _i, _vp],
     "gsht_plan_set_points": [_vp, _vp, _vp, _i64, _vp],
     "gsht_plan_synth": [_vp, _vp, _vp, _vp],
     "gsht_plan_adjoint": [_vp, _vp, _vp, _vp],
@@ -175,15 +177,23 @@ class Plan:
     """gsht_plan wrapper: geometry, FFT plans and workspace reused across calls."""
 
     def __init__(self, theta, phi, lmax: int, mmax: int, spin: int, epsilon: float,
-                 precision="f64"):
+                 precision="f64", sigma=None):
+        """sigma: None for the default oversampling (2), a number (2, 1.5 or 1.25) for
+        gsht_plan_create_sigma, or "tuned" for gsht_plan_create_tuned."""
         self.prec = _PREC[precision]
         self.lmax, self.mmax, self.spin = lmax, mmax, spin
         self.ncomp = 1 if spin == 0 else 2
         self.npts = _coords(theta, phi)
         self.device = theta.device
         h = ctypes.c_void_p(0)
-        _check(_lib.gsht_plan_create(ctypes.byref(h), lmax, mmax, spin, _ptr(theta), _ptr(phi),
-                                     self.npts, float(epsilon), self.prec, _stream()))
+        args = (ctypes.byref(h), lmax, mmax, spin, _ptr(theta), _ptr(phi), self.npts,
+                float(epsilon), self.prec)
+        if sigma is None:
+            _check(_lib.gsht_plan_create(*args, _stream()))
+        elif sigma == "tuned":
+            _check(_lib.gsht_plan_create_tuned(*args, _stream()))
+        else:
+            _check(_lib.gsht_plan_create_sigma(*args, float(sigma), _stream()))
         self._h = h
 
     def close(self):

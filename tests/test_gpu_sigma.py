@@ -1,0 +1,107 @@
+"""Oversampling factors other than 2 (gsht_plan_create_sigma) and the plan whose
+factor is picked by timing (gsht_plan_create_tuned): at sigma = 1.5 and 1.25 the
+kernel support and shape come from their own calibrated error tables, and synthesis
+and adjoint must still reach epsilon against the oracle, at both spins and both
+precisions; an epsilon the precision's kernels cannot reach at that sigma, and a
+sigma without a table, are refused."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2304_10431_amd import gsht
+    return gsht
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _case(spin, lmax, mmax, npts, seed):
+    rng = np.random.default_rng(seed)
+    th = np.arccos(rng.uniform(-1, 1, npts))
+    ph = rng.uniform(0, 2 * np.pi, npts)
+    th[:3] = [0.0, np.pi, 1e-7]
+    nc = oracle.ncomp(spin)
+    a = rng.standard_normal((nc, oracle.nalm(lmax, mmax))) + 1j * rng.standard_normal((nc, oracle.nalm(lmax, mmax)))
+    for blk in a:
+        for m in range(mmax + 1):
+            i0 = oracle.alm_index(m, m, lmax)
+            if m == 0:
+                blk[i0:i0 + lmax + 1] = blk[i0:i0 + lmax + 1].real
+            blk[i0:i0 + max(0, spin - m)] = 0
+    y = rng.standard_normal((nc, npts))
+    return th, ph, a, y
+
+
+def _check(G, plan, th, ph, a, y, lmax, mmax, spin, prec, eps):
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    m = plan.synth(dev(a).to(cdt)).double().cpu().numpy()
+    e_s = oracle.eps_eff(m, oracle.synth(a, lmax, mmax, spin, th, ph))
+    b = plan.adjoint(dev(y).to(rdt)).to(torch.complex128).cpu().numpy()
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    e_a = oracle.eps_eff(w * b, w * oracle.adjoint(y, lmax, mmax, spin, th, ph))
+    return e_s, e_a
+
+
+@pytest.mark.parametrize("sigma,prec,eps", [(1.5, "f64", 1e-10), (1.25, "f64", 1e-8),
+                                            (1.5, "f32", 1e-5), (1.25, "f64", 1e-5),
+                                            (2.0, "f64", 1e-10)])
+@pytest.mark.parametrize("spin,lmax,mmax", [(0, 250, 250), (2, 301, 180)])
+def test_sigma_reaches_epsilon(G, sigma, prec, eps, spin, lmax, mmax):
+    say("sigma", sigma, prec, eps, spin, lmax, mmax)
+    th, ph, a, y = _case(spin, lmax, mmax, 20000, 10 * spin + lmax)
+    plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec, sigma=sigma)
+    info = plan.info()
+    assert info["sigma"] == sigma
+    assert info["n1"] >= 0.999 * sigma * (2 * lmax + 1) and info["n1"] % 2 == 0
+    assert info["n2"] >= 0.999 * sigma * (2 * mmax + 1)
+    assert info["n1"] < 2.0 * sigma * (2 * lmax + 1)
+    assert math.isclose(info["beta"] / info["w"], {2.0: 2.3, 1.5: 2.05, 1.25: 1.85}[sigma])
+    e_s, e_a = _check(G, plan, th, ph, a, y, lmax, mmax, spin, prec, eps)
+    plan.close()
+    say("  n1 %d n2 %d w %d: synthesis %.2e adjoint %.2e" % (info["n1"], info["n2"], info["w"], e_s, e_a))
+    assert e_s <= eps
+    assert e_a <= eps
+
+
+def test_sigma_refusals(G):
+    say("sigma refusals")
+    th, ph, _, _ = _case(0, 40, 40, 500, 1)
+    # FP32 kernels stop at 8 cells; at sigma = 1.25 epsilon 1e-5 needs 10
+    with pytest.raises(G.GshtError, match="not reachable"):
+        G.Plan(dev(th), dev(ph), 40, 40, 0, 1e-5, "f32", sigma=1.25)
+    with pytest.raises(G.GshtError, match="sigma must be"):
+        G.Plan(dev(th), dev(ph), 40, 40, 0, 1e-5, "f64", sigma=1.7)
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-10)])
+def test_tuned_plan(G, prec, eps):
+    spin, lmax, mmax = 2, 301, 301
+    say("tuned", prec, eps)
+    th, ph, a, y = _case(spin, lmax, mmax, 30000, 7)
+    plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec, sigma="tuned")
+    info = plan.info()
+    assert info["sigma"] in (2.0, 1.5, 1.25)
+    e_s, e_a = _check(G, plan, th, ph, a, y, lmax, mmax, spin, prec, eps)
+    plan.close()
+    say("  chose sigma %.2f (n1 %d, w %d): synthesis %.2e adjoint %.2e"
+        % (info["sigma"], info["n1"], info["w"], e_s, e_a))
+    assert e_s <= eps
+    assert e_a <= eps
