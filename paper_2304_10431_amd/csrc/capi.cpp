@@ -102,6 +102,10 @@ long fft_size(double target, long floor_n)
 // w = 4..16 on random Fourier series (81 x 81 modes, 2000 random points, torus of
 // sigma * 81 cells); beta_per_w is the value that minimised the error for mid-range w
 // (for sigma = 2 it matches the 2.3 w of the exponential-of-semicircle literature).
+// The sigma = 2 row lists, at w = 4, 5 and 13..16, the error at the best beta near
+// 2.3 w; at 2.3 w itself it is up to 1.6 times larger there (w = 16: 1.9e-14, the
+// test's own floor), which the factor 4 margin of choose_w absorbs for every
+// epsilon a plan accepts.  es_calibration.py in the package reproduces the tables.
 struct EsSetting {
     double sigma, beta_per_w;
     double err[17];
