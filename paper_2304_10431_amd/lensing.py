@@ -22,10 +22,12 @@ from . import gsht
 class Lensing:
     """D_alpha for one geometry: points (theta, phi), lensing potential plm (and curl
     potential olm) with band limits (lmax_p, mmax_p), unlensed field band limits
-    (lmax, mmax), spin, accuracy epsilon and precision."""
+    (lmax, mmax), spin, accuracy epsilon and precision.  sigma is the oversampling
+    choice of both plans (None: 2; 2, 1.5 or 1.25; "tuned": the fastest by timing)."""
 
     def __init__(self, theta, phi, plm, lmax: int, mmax: int, spin: int, epsilon: float,
-                 precision="f64", olm=None, lmax_p: int | None = None, mmax_p: int | None = None):
+                 precision="f64", olm=None, lmax_p: int | None = None, mmax_p: int | None = None,
+                 sigma=None):
         self.spin = spin
         self.lmax_p = lmax if lmax_p is None else lmax_p
         self.mmax_p = self.lmax_p if mmax_p is None else mmax_p
@@ -33,7 +35,8 @@ class Lensing:
         cdt = gsht._CDT[prec]
         self.theta = theta
         self.phi = phi
-        self.dplan = gsht.Plan(theta, phi, self.lmax_p, self.mmax_p, 1, epsilon, precision)
+        self.dplan = gsht.Plan(theta, phi, self.lmax_p, self.mmax_p, 1, epsilon, precision,
+                               sigma=sigma)
         if olm is None:   # no curl potential: gradient-only spin-1 synthesis
             glm = gsht.alm_lscale(plm.to(cdt).reshape(1, -1).contiguous(), self.lmax_p, self.mmax_p)
             self.alpha = self.dplan.synth_grad(glm)
@@ -44,7 +47,8 @@ class Lensing:
         self._pot = (plm.to(cdt), None if olm is None else olm.to(cdt), epsilon, precision)
         self.theta_d, self.phi_d, chi = gsht.deflect(theta, phi, self.alpha, want_chi=spin > 0)
         self.chi = chi
-        self.plan = gsht.Plan(self.theta_d, self.phi_d, lmax, mmax, spin, epsilon, precision)
+        self.plan = gsht.Plan(self.theta_d, self.phi_d, lmax, mmax, spin, epsilon, precision,
+                              sigma=sigma)
 
     def close(self):
         self.plan.close()
