@@ -61,24 +61,29 @@ def sample_indices(th_h, n, seed):
 
 
 CASES = [
-    # workload, precision, eps, nsample
-    ("tlens_l2048", "f64", 1e-10, 300),
-    ("tlens_l2048", "f32", 1e-5, 300),
-    ("pollens_l4096", "f64", 1e-10, 150),
-    ("pollens_l4096", "f32", 1e-5, 150),
-    ("pollens_thin6144", "f32", 1e-5, 150),
+    # workload, precision, eps, nsample, oversampling (None: the default plan)
+    ("tlens_l2048", "f64", 1e-10, 300, None),
+    ("tlens_l2048", "f32", 1e-5, 300, None),
+    ("pollens_l4096", "f64", 1e-10, 150, None),
+    ("pollens_l4096", "f32", 1e-5, 150, None),
+    ("pollens_thin6144", "f32", 1e-5, 150, None),
+    # the benchmark's plans: chosen by timing (1.5 for these forms), and 1.25 in FP64
+    ("pollens_thin6144", "f32", 1e-5, 150, "tuned"),
+    ("pollens_thin6144", "f64", 1e-10, 100, "tuned"),
+    ("pollens_thin6144", "f64", 1e-5, 100, 1.25),
 ]
+ADJ_CASES = CASES[:4] + CASES[5:]
 
 
-@pytest.mark.parametrize("name,prec,eps,nsample", CASES)
-def test_fullsize_synthesis_sampled(G, name, prec, eps, nsample):
+@pytest.mark.parametrize("name,prec,eps,nsample,sigma", CASES)
+def test_fullsize_synthesis_sampled(G, name, prec, eps, nsample, sigma):
     spec = wl.WORKLOADS[name]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     th, ph = points(name)
-    say("fullsize synth", name, prec, eps, th.numel())
+    say("fullsize synth", name, prec, eps, sigma, th.numel())
     alm_h = wl.make_alm(spec)
     cdt = torch.complex128 if prec == "f64" else torch.complex64
-    plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec)
+    plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec, sigma=sigma)
     m = plan.synth(torch.from_numpy(alm_h).cuda().to(cdt))
     th_h, ph_h = th.cpu().numpy(), ph.cpu().numpy()
     idx = sample_indices(th_h, nsample, 3)
@@ -90,12 +95,12 @@ def test_fullsize_synthesis_sampled(G, name, prec, eps, nsample):
     assert err <= eps, err
 
 
-@pytest.mark.parametrize("name,prec,eps,nsample", CASES[:4])
-def test_fullsize_adjoint_sampled(G, name, prec, eps, nsample):
+@pytest.mark.parametrize("name,prec,eps,nsample,sigma", ADJ_CASES)
+def test_fullsize_adjoint_sampled(G, name, prec, eps, nsample, sigma):
     spec = wl.WORKLOADS[name]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     th, ph = points(name)
-    say("fullsize adjoint", name, prec, eps, th.numel())
+    say("fullsize adjoint", name, prec, eps, sigma, th.numel())
     th_h, ph_h = th.cpu().numpy(), ph.cpu().numpy()
     idx = sample_indices(th_h, nsample, 5)
     ncomp = 1 if spin == 0 else 2
@@ -103,7 +108,7 @@ def test_fullsize_adjoint_sampled(G, name, prec, eps, nsample):
     rdt = torch.float64 if prec == "f64" else torch.float32
     y = torch.zeros((ncomp, th.numel()), dtype=rdt, device="cuda")
     y[:, torch.from_numpy(idx).cuda()] = torch.from_numpy(y_s).cuda().to(rdt)
-    plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec)
+    plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec, sigma=sigma)
     got = plan.adjoint(y).cpu().numpy().astype(np.complex128)
     plan.close()
     ref = oracle.adjoint(y_s, lmax, mmax, spin, th_h[idx], ph_h[idx])
