@@ -83,3 +83,31 @@ def test_stage_names(lib):
     names = [lib.gsht_stage_name(i).decode() for i in range(n)]
     assert "legendre_synth" in names and "legendre_adj" in names and "spread" in names
     assert lib.gsht_stage_name(n).decode() == ""
+
+
+def test_sigma_and_point_moving_entries_reject_on_host(lib):
+    """The oversampling entries check sigma and the arguments before any device work;
+    moving points checks the plan pointer and the capacity."""
+    lib.gsht_last_error.restype = ctypes.c_char_p
+    P = ctypes.POINTER(ctypes.c_void_p)
+    lib.gsht_plan_create_sigma.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_void_p]
+    lib.gsht_plan_create_tuned.argtypes = lib.gsht_plan_create_sigma.argtypes[:9] + [ctypes.c_void_p]
+    h = ctypes.c_void_p(0)
+    for sigma in (1.7, 1.0, 3.0, float("nan")):
+        assert lib.gsht_plan_create_sigma(ctypes.byref(h), 10, 10, 0, None, None, 10, 1e-10, 0,
+                                          sigma, None) == -1
+        assert "sigma must be" in lib.gsht_last_error().decode()
+        assert h.value is None
+    # valid sigma, invalid arguments: the same checks as gsht_plan_create
+    assert lib.gsht_plan_create_sigma(ctypes.byref(h), 10, 11, 0, None, None, 10, 1e-10, 0,
+                                      1.5, None) == -1
+    assert lib.gsht_plan_create_tuned(ctypes.byref(h), 10, 10, 0, None, None, 10, 1e-14, 0,
+                                      None) == -1
+    assert lib.gsht_plan_create_tuned(None, 10, 10, 0, None, None, 10, 1e-10, 0, None) == -1
+    assert h.value is None
+    lib.gsht_plan_set_points.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p]
+    assert lib.gsht_plan_set_points(None, None, None, 0, None) == -1
