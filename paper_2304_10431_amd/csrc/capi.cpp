@@ -421,9 +421,14 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
 
 size_t csize(int prec) { return prec == GSHT_F64 ? 16 : 8; }
 
+int col_maxr(const gsht_plan *p) { return p->prec == GSHT_F32 ? 8 : 16; }
+
 // Radices of an in-LDS transform of length n (largest first), or false if n has a
 // prime factor above 7 or needs more than COL_MAXP passes.
-bool col_radices(int n, std::vector<int> &rad)
+// Radices of an in-LDS transform of length n, largest first.  maxr = 16 or 8: the
+// FP32 kernels are built without the radix-16 pass, whose 16 complex values plus
+// twiddles would make them spill at the register budget of two workgroups per CU.
+bool col_radices(int n, std::vector<int> &rad, int maxr)
 {
     rad.clear();
     int m = n;
@@ -432,20 +437,21 @@ bool col_radices(int n, std::vector<int> &rad)
             rad.push_back(f);
             m /= f;
         }
-    while (m % 16 == 0) {
-        rad.push_back(16);
-        m /= 16;
+    while (m % maxr == 0) {
+        rad.push_back(maxr);
+        m /= maxr;
     }
     for (int f : {8, 4, 2})
-        if (m % f == 0) {
+        if (f < maxr && m % f == 0) {
             rad.push_back(f);
             m /= f;
         }
-    // a lone radix-2 pass does little work per LDS round trip: 16 x 2 -> 8 x 4
+    // a lone radix-2 pass does little work per LDS round trip: 16 x 2 -> 8 x 4,
+    // 8 x 2 -> 4 x 4
     auto two = std::find(rad.begin(), rad.end(), 2);
-    auto sixteen = std::find(rad.begin(), rad.end(), 16);
-    if (two != rad.end() && sixteen != rad.end()) {
-        *sixteen = 8;
+    auto big = std::find(rad.begin(), rad.end(), maxr);
+    if (two != rad.end() && big != rad.end()) {
+        *big /= 2;
         *two = 4;
     }
     if (m != 1 || rad.empty() || (int)rad.size() > COL_MAXP)
@@ -461,7 +467,7 @@ bool col_radices(int n, std::vector<int> &rad)
 int setup_colfft(gsht_plan *p, ColFFT &f, int n, hipStream_t s)
 {
     std::vector<int> rad;
-    if (!col_radices(n, rad))
+    if (!col_radices(n, rad, col_maxr(p)))
         return fail(GSHT_EINVAL, "length %d cannot run as an in-LDS transform", n);
     f.n = n;
     f.npass = (int)rad.size();
@@ -559,7 +565,7 @@ int setup_rows(gsht_plan *p, hipStream_t s)
     std::vector<int> rad;
     const int nh = p->n2 / 2, cap = column_half_maxn(p->prec);
     const bool fit = p->spin > 0 && p->n2 % 2 == 0 && nh > p->mmax && nh <= cap &&
-                     2 * p->mmax + 1 <= cap && row_lds_bytes(*p) <= lim && col_radices(nh, rad);
+                     2 * p->mmax + 1 <= cap && row_lds_bytes(*p) <= lim && col_radices(nh, rad, col_maxr(p));
     // The library FFT is the default: the in-LDS row kernels measured slower at lmax
     // 4096 (FP32 1.04 vs 0.59 ms, FP64 2.2 vs 1.5 ms per direction).
     int mode = 0;
@@ -606,10 +612,10 @@ int setup_columns(gsht_plan *p, hipStream_t s)
     const int psh = p->lds_psh;
     std::vector<int> rad;
     const int nh = p->n1 / 2;
-    const bool fit_d = (size_t)lds_pad_n(p->nd, psh) * cs <= lim && col_radices(p->nd, rad);
+    const bool fit_d = (size_t)lds_pad_n(p->nd, psh) * cs <= lim && col_radices(p->nd, rad, col_maxr(p));
     const bool fit_2 = fit_d && p->n1 % 2 == 0 && nh > p->lmax &&
                        (size_t)lds_pad_n(std::max(p->nd, nh), psh) * cs <= lim &&
-                       std::max(p->nd, nh) <= column_half_maxn(p->prec) && col_radices(nh, rad);
+                       std::max(p->nd, nh) <= column_half_maxn(p->prec) && col_radices(nh, rad, col_maxr(p));
     int mode = fit_2 ? 2 : fit_d ? 1 : 0;
     const char *e = getenv("GSHT_COLUMN_MODE");
     if (e) {

@@ -14,7 +14,7 @@
 // deconvolution are fused here and the theta transform runs separately on E.
 //
 // The FFTs are in-place mixed-radix decimation-in-frequency passes over LDS (radices
-// 16, 8, 4, 2, 3, 5, 7): pass i splits sub-transforms of length L into radix r_i
+// 16 (FP64 only), 8, 4, 2, 3, 5, 7): pass i splits sub-transforms of length L into radix r_i
 // butterflies of stride s = L / r_i, each followed by the twiddles w_L^(q j).  The
 // result sits in digit-reversed order; a host-built table gives the LDS position of
 // every frequency.  Twiddles come from per-pass tables in the working precision,
@@ -241,7 +241,10 @@ __device__ void lds_fft(C *X, const ColFFT &f)
         const int s = L / r;
         const C *tw = reinterpret_cast<const C *>(f.tw) + f.twoff[p];
         switch (r) {
-        case 16: dif_pass<C, 16, DIR, NT>(X, tw, f.n, s, f.psh); break;
+        case 16:  // FP64 only: FP32 transforms get radices up to 8 (no spills)
+            if constexpr (sizeof(C) == 16)
+                dif_pass<C, 16, DIR, NT>(X, tw, f.n, s, f.psh);
+            break;
         case 8: dif_pass<C, 8, DIR, NT>(X, tw, f.n, s, f.psh); break;
         case 4: dif_pass<C, 4, DIR, NT>(X, tw, f.n, s, f.psh); break;
         case 2: dif_pass<C, 2, DIR, NT>(X, tw, f.n, s, f.psh); break;
