@@ -58,7 +58,7 @@ class Lensing:
         """New lensing potential (and curl potential) on the same points: the deflection
         is resynthesised and the lensed plan moved to the new deflected points
         (gsht_plan_set_points), without building new plans."""
-        plm_, olm_, eps, prec = self._pot
+        _, olm_, eps, prec = self._pot
         cdt = gsht._CDT[gsht._PREC[prec]]
         if (olm is None) != (olm_ is None):
             raise ValueError("update must keep the same potentials (curl given or not)")
