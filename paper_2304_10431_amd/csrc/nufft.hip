@@ -381,14 +381,14 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
         }
         e = hipStreamSynchronize(s);
     }
-out:
-    hipFree(k0);
-    hipFree(k1);
-    hipFree(v0);
-    hipFree(v1);
-    hipFree(cnt);
-    hipFree(tmp);
-    hipFree(inval);
+out:  // scratch of the sort; a failed free cannot change the result
+    (void)hipFree(k0);
+    (void)hipFree(k1);
+    (void)hipFree(v0);
+    (void)hipFree(v1);
+    (void)hipFree(cnt);
+    (void)hipFree(tmp);
+    (void)hipFree(inval);
     return e;
 }
 
