@@ -402,8 +402,13 @@ hipError_t build_tile_colors(gsht_plan &p, hipStream_t s)
 {
     p.ncolors = 0;
     const char *env = getenv("GSHT_SPREAD_COLORS");
+    // A patch spans its tile plus w - 1 cells to the right, modulo n2 in phi.  It must
+    // not wrap onto itself (t2 + w - 1 <= n2), and with an even number of tile
+    // columns the last (possibly narrower) column lies between two colour-0 columns
+    // across the wrap, so it must be at least w - 1 cells wide.
+    const int last = p.n2 - (p.nt2 - 1) * p.t2;
     if ((env && atoi(env) == 0) || p.nchunks == 0 || p.nt2 < 2 || p.t1 < p.w - 1 ||
-        p.t2 < p.w - 1)
+        p.t2 < p.w - 1 || p.t2 + p.w - 1 > p.n2 || (p.nt2 % 2 == 0 && last < p.w - 1))
         return hipSuccess;
     std::vector<int4> ck((size_t)p.nchunks);
     hipError_t e = hipMemcpyAsync(ck.data(), p.chunks, sizeof(int4) * ck.size(),

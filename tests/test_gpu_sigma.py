@@ -105,3 +105,31 @@ def test_tuned_plan(G, prec, eps):
         % (info["sigma"], info["n1"], info["w"], e_s, e_a))
     assert e_s <= eps
     assert e_a <= eps
+
+
+@pytest.mark.parametrize("sigma,prec,eps", [(1.5, "f32", 1e-5), (1.25, "f64", 1e-8),
+                                            (2.0, "f64", 1e-13)])
+@pytest.mark.parametrize("spin,lmax,mmax,npts", [(1, 64, 64, 3000), (3, 90, 20, 4000),
+                                                 (2, 2, 2, 500), (0, 7, 0, 300), (2, 40, 40, 1),
+                                                 (0, 30, 30, 0)])
+def test_sigma_edge_cases(G, sigma, prec, eps, spin, lmax, mmax, npts):
+    """Odd spins, mmax much below lmax, lmax = spin, mmax = 0, one point and no points
+    at the oversampling factors below 2, and at 2 with the widest kernel.  With
+    mmax = 2 and w >= 10 the torus is 40 cells around: a tile's spreading patch
+    (32 + w - 1 cells) would wrap onto itself, so the plan must flush with atomics
+    (the colour-ordered flush lost updates there)."""
+    say("sigma edge", sigma, prec, spin, lmax, mmax, npts)
+    th, ph, a, y = _case(spin, lmax, mmax, max(npts, 3), 100 + lmax + spin)
+    th, ph, y = th[:npts], ph[:npts], y[:, :npts]
+    plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec, sigma=sigma)
+    assert plan.info()["sigma"] == sigma
+    if npts == 0:
+        cdt = torch.complex128 if prec == "f64" else torch.complex64
+        assert plan.synth(dev(a).to(cdt)).shape == (oracle.ncomp(spin), 0)
+        plan.close()
+        return
+    e_s, e_a = _check(G, plan, th, ph, a, y, lmax, mmax, spin, prec, eps)
+    plan.close()
+    say("  synthesis %.2e adjoint %.2e" % (e_s, e_a))
+    assert e_s <= eps
+    assert e_a <= eps
