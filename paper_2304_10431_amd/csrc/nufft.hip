@@ -538,7 +538,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_kernel(
         const int pr = idx / PC, pc = idx - (idx / PC) * PC;
         const int r = row0 + pr;
         int c = col0 + pc;
-        if (c >= g.n2)
+        while (c >= g.n2)  // patches may span the torus more than once when n2 is small
             c -= g.n2;
         V v{};
         if (r < g.nrows)
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_deriv_kernel(
         const int pr = idx / PC, pc = idx - (idx / PC) * PC;
         const int r = row0 + pr;
         int c = col0 + pc;
-        if (c >= g.n2)
+        while (c >= g.n2)  // patches may span the torus more than once when n2 is small
             c -= g.n2;
         V v{};
         if (r < g.nrows)
@@ -795,7 +795,7 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
         if (r >= g.nrows)
             continue;
         int c = col0 + pc;
-        if (c >= g.n2)
+        while (c >= g.n2)  // patches may span the torus more than once when n2 is small
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
         const int pidx = pr * g.ps + pc;

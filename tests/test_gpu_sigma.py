@@ -133,3 +133,22 @@ def test_sigma_edge_cases(G, sigma, prec, eps, spin, lmax, mmax, npts):
     say("  synthesis %.2e adjoint %.2e" % (e_s, e_a))
     assert e_s <= eps
     assert e_a <= eps
+
+
+@pytest.mark.parametrize("sigma", [2.0, 1.5])
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-3), ("f32", 2e-2)])
+@pytest.mark.parametrize("spin,lmax,mmax", [(0, 5, 0), (2, 6, 1)])
+def test_smallest_torus(G, sigma, prec, eps, spin, lmax, mmax):
+    """Narrow kernels (w = 4, 5) on the smallest tori (12 to 16 cells around): a tile's
+    patch then spans the torus more than twice, and every patch cell must still wrap
+    to a cell of its own row."""
+    say("smallest torus", sigma, prec, eps, spin, lmax, mmax)
+    th, ph, a, y = _case(spin, lmax, mmax, 2000, 11 + spin)
+    plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec, sigma=sigma)
+    info = plan.info()
+    assert info["n2"] <= 20 and info["w"] <= 6
+    e_s, e_a = _check(G, plan, th, ph, a, y, lmax, mmax, spin, prec, eps)
+    plan.close()
+    say("  n2 %d w %d: synthesis %.2e adjoint %.2e" % (info["n2"], info["w"], e_s, e_a))
+    assert e_s <= eps
+    assert e_a <= eps
