@@ -350,6 +350,11 @@ void choose_sizes(gsht_plan *p)
     p->nrows = p->n1 / 2 + p->w + 2;
     p->t1 = 32;
     p->t2 = 32;
+    if (const char *e = getenv("GSHT_TILE")) {  // tile edge in cells (testing and tuning)
+        const int t = atoi(e);
+        if (t >= 16 && t <= 128 && t >= p->w - 1)
+            p->t1 = p->t2 = t;
+    }
     if (const char *e = getenv("GSHT_PATCH_PAD"))
         p->patch_pad = std::max(0, std::min(16, atoi(e)));
     p->spread_order = 1;
