@@ -164,8 +164,11 @@ int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const do
  * FFT plans do not depend on the points), so moving points costs a few milliseconds
  * instead of a plan creation: the lensing iterations of Sect. 4 deflect the same
  * pixels differently at every step.  Synchronises hip_stream first (transforms still
- * queued use the old points) and before returning.  GSHT_EINVAL for invalid points,
- * after which the plan must get valid points before its next transform.  Calls on one
+ * queued use the old points) and before returning.  GSHT_EINVAL for invalid points
+ * (GSHT_EHIP if the sort itself fails): the plan then holds no valid points, and every
+ * transform, several-map, derivative and batch call on it, and gsht_plan_get_sort,
+ * returns GSHT_EINVAL on the host, before any device work, until a later call of this
+ * function succeeds.  Calls on one
  * plan must not overlap with this one, and a graph captured earlier on this plan holds
  * the old sort's buffers: capture again after moving the points.
  */

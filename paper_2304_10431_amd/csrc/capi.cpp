@@ -105,7 +105,8 @@ long fft_size(double target, long floor_n)
 // The sigma = 2 row lists, at w = 4, 5 and 13..16, the error at the best beta near
 // 2.3 w; at 2.3 w itself it is up to 1.6 times larger there (w = 16: 1.9e-14, the
 // test's own floor), which the factor 4 margin of choose_w absorbs for every
-// epsilon a plan accepts.  es_calibration.py in the package reproduces the tables.
+// epsilon a plan accepts.  tests/test_es_table.py recomputes every entry with the
+// plain FP64 CPU NUFFT on the same draw.
 struct EsSetting {
     double sigma, beta_per_w;
     double err[17];
@@ -395,6 +396,9 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         p->syn_r = r1;
         p->adj_r = r2;
         p->adj_b = b;
+        const char *ap = getenv("GSHT_ADJ_PAIR");
+        if (ap)
+            p->adj_pair = atoi(ap) != 0;
     }
     p->syn_nchunk = (p->npairs + 64 * p->syn_r - 1) / (64 * p->syn_r);
     p->adj_nchunk = (p->npairs + 64 * p->adj_r - 1) / (64 * p->adj_r);
@@ -762,6 +766,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
             return fail(GSHT_EHIP, "tile colouring failed: %s", hipGetErrorString(e));
         }
         tr.mark("tile colours");
+        p->points_ok = true;
     }
     // per-column stage, then the rocFFT plans it leaves to rocFFT
     if (p->prec == GSHT_F64) {  // interior-tap weight polynomials (GSHT_ES_POLY=0: off)
@@ -860,6 +865,15 @@ int check_launch(hipError_t e, const char *what)
     return GSHT_OK;
 }
 
+// Transforms need a plan whose last bin sort and tile colouring completed.
+int need_points(const gsht_plan *p)
+{
+    if (!p->points_ok)
+        return fail(GSHT_EINVAL, "the plan has no valid points (its last gsht_plan_set_points "
+                                 "failed); give it valid points first");
+    return GSHT_OK;
+}
+
 #define RUN(stage, expr)                                                                       \
     do {                                                                                       \
         STAGE(stage);                                                                          \
@@ -911,7 +925,10 @@ int plan_synth_from_D(gsht_plan *p, hipStream_t s)
 int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s, double mscale = 1.0,
                     bool grad = false)
 {
-    int rc = plan_synth_grid(p, alm, mscale, s, grad);
+    int rc = need_points(p);
+    if (rc != GSHT_OK)
+        return rc;
+    rc = plan_synth_grid(p, alm, mscale, s, grad);
     if (rc != GSHT_OK)
         return rc;
     RUN(ST_INTERP, launch_interp(*p, map, s));
@@ -923,7 +940,10 @@ int plan_synth_impl(gsht_plan *p, const void *alm, void *map, hipStream_t s, dou
 int plan_deriv_impl(gsht_plan *p, const void *alm, void *map, void *dth, void *dph,
                     const void *gin, double *gth, double *gph, hipStream_t s)
 {
-    int rc = plan_synth_grid(p, alm, 1.0, s);
+    int rc = need_points(p);
+    if (rc != GSHT_OK)
+        return rc;
+    rc = plan_synth_grid(p, alm, 1.0, s);
     if (rc != GSHT_OK)
         return rc;
     RUN(ST_INTERP_DERIV, launch_interp_deriv(*p, map, dth, dph, gin, gth, gph, s));
@@ -933,6 +953,9 @@ int plan_deriv_impl(gsht_plan *p, const void *alm, void *map, void *dth, void *d
 // Adjoint from the map down to the doubled columns D (before the Legendre step).
 int plan_adjoint_to_D(gsht_plan *p, const void *map, hipStream_t s)
 {
+    const int rc = need_points(p);
+    if (rc != GSHT_OK)
+        return rc;
     const size_t cs = csize(p->prec);
     if (p->spin)
         RUN(ST_ZERO_GRID, launch_zero(p->G, (size_t)p->nrows * p->n2 * cs, s));
@@ -1027,7 +1050,11 @@ int gsht_plan_set_points(gsht_plan *p, const double *theta, const double *phi, i
         return fail(GSHT_EINVAL, "theta/phi must not be NULL when npts > 0");
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(hipStreamSynchronize(s));  // earlier transforms may still read the old sort
-    // the chunk list and tile items of the previous sort are rebuilt
+    // the chunk list, tile items and colours of the previous sort are rebuilt; until
+    // that has completed the plan refuses every transform
+    p->points_ok = false;
+    p->ncolors = 0;
+    p->nchunks = 0;
     for (void **q : {(void **)&p->chunks, (void **)&p->tile_items}) {
         if (!*q)
             continue;
@@ -1050,6 +1077,7 @@ int gsht_plan_set_points(gsht_plan *p, const double *theta, const double *phi, i
     e = build_tile_colors(*p, s);
     if (e != hipSuccess)
         return fail(GSHT_EHIP, "tile colouring failed: %s", hipGetErrorString(e));
+    p->points_ok = true;
     return ok();
 }
 
@@ -1318,6 +1346,8 @@ int gsht_plan_adjoint_many(gsht_plan *p, int nmaps, const void *map, void *alm, 
         return fail(GSHT_EINVAL, "nmaps must be >= 0, got %d", nmaps);
     if (nmaps > 0 && (!alm || (!map && p->npts > 0)))
         return fail(GSHT_EINVAL, "map/alm must not be NULL");
+    if (nmaps > 0 && need_points(p) != GSHT_OK)
+        return GSHT_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t cs = csize(p->prec);
     const size_t astride = (size_t)p->ncomp * p->nalm * cs;
@@ -1371,6 +1401,8 @@ int gsht_plan_synth_many(gsht_plan *p, int nmaps, const void *alm, void *map, vo
         return fail(GSHT_EINVAL, "nmaps must be >= 0, got %d", nmaps);
     if (nmaps > 0 && (!alm || (!map && p->npts > 0)))
         return fail(GSHT_EINVAL, "alm/map must not be NULL");
+    if (nmaps > 0 && need_points(p) != GSHT_OK)
+        return GSHT_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t cs = csize(p->prec);
     const size_t astride = (size_t)p->ncomp * p->nalm * cs;
@@ -1568,6 +1600,9 @@ static int batch_run(gsht_batch *b, int n, gsht_plan *const *plans, const void *
             if (plans[j] == plans[i])
                 return fail(GSHT_EINVAL, "plan %d appears twice in the batch (instances %d and %d "
                                          "would share its work buffers)", i, j, i);
+        if (need_points(plans[i]) != GSHT_OK)
+            return fail(GSHT_EINVAL, "plan %d has no valid points (its last gsht_plan_set_points "
+                                     "failed)", i);
     }
     hipStream_t s = (hipStream_t)hip_stream;
     const int ns = (int)b->streams.size();
@@ -1788,6 +1823,8 @@ int gsht_plan_get_sort(const gsht_plan *p, int32_t *perm, int32_t *tile_start, v
 {
     if (!p || !perm || !tile_start)
         return fail(GSHT_EINVAL, "plan/perm/tile_start must not be NULL");
+    if (need_points(p) != GSHT_OK)
+        return GSHT_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     if (p->npts > 0)
         HIP_TRY(hipMemcpyAsync(perm, p->perm, sizeof(int32_t) * (size_t)p->npts,

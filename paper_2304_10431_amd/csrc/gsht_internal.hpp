@@ -102,6 +102,10 @@ struct gsht_plan {
     int lmax = 0, mmax = 0, spin = 0, ncomp = 1;
     int64_t npts = 0;
     int64_t npts_cap = 0;  // points the sorted-coordinate buffers hold (set at creation)
+    // set only after a complete bin sort and tile colouring; cleared while the points
+    // are replaced and left clear when that fails, so no transform runs on a plan
+    // whose sort is incomplete
+    bool points_ok = false;
     double eps = 0;
     int prec = GSHT_F64;
     int64_t nalm = 0;
@@ -118,6 +122,8 @@ struct gsht_plan {
     int syn_r = 2;       // ring pairs per lane, Legendre synthesis (slices of 64)
     int adj_r = 3;       // ring pairs per lane, Legendre adjoint
     int adj_b = 8;       // degrees per reduction block of the adjoint
+    int adj_pair = 1;    // adjoint: one workgroup per column pair with LDS sums (1), or
+                         // one wave per (m, chunk) with global atomics (0)
     int syn_nchunk = 0;  // chunks of 64 * syn_r ring pairs
     int adj_nchunk = 0;  // chunks of 64 * adj_r ring pairs
     int64_t workspace_bytes = 0;

@@ -19,6 +19,23 @@ import torch
 from . import gsht
 
 
+def deflected_points(theta, phi, plm, lmax_p: int, mmax_p: int | None = None,
+                     epsilon: float = 1e-13):
+    """The points n' that the lensing potential plm (band limits lmax_p, mmax_p) maps
+    theta, phi to: the deflection is the FP64 gradient-only spin-1 synthesis of
+    sqrt(L (L+1)) phi_LM at the points (eq. deflect), then the great-circle step
+    (``gsht_deflect``).  Returns (theta', phi') as FP64 device tensors."""
+    mmax_p = lmax_p if mmax_p is None else mmax_p
+    plan = gsht.Plan(theta, phi, lmax_p, mmax_p, 1, epsilon, "f64")
+    try:
+        glm = gsht.alm_lscale(plm.to(torch.complex128).reshape(1, -1).contiguous(), lmax_p, mmax_p)
+        alpha = plan.synth_grad(glm)
+    finally:
+        plan.close()
+    th, ph, _ = gsht.deflect(theta, phi, alpha, want_chi=False)
+    return th, ph
+
+
 class Lensing:
     """D_alpha for one geometry: points (theta, phi), lensing potential plm (and curl
     potential olm) with band limits (lmax_p, mmax_p), unlensed field band limits
@@ -64,15 +81,16 @@ class Lensing:
             raise ValueError("update must keep the same potentials (curl given or not)")
         if olm is None:
             glm = gsht.alm_lscale(plm.to(cdt).reshape(1, -1).contiguous(), self.lmax_p, self.mmax_p)
-            self.alpha = self.dplan.synth_grad(glm)
+            alpha = self.dplan.synth_grad(glm)
         else:
             glm = gsht.alm_lscale(torch.stack([plm.to(cdt), olm.to(cdt)]).contiguous(),
                                   self.lmax_p, self.mmax_p)
-            self.alpha = self.dplan.synth(glm)
+            alpha = self.dplan.synth(glm)
+        theta_d, phi_d, chi = gsht.deflect(self.theta, self.phi, alpha, want_chi=self.spin > 0)
+        # the operator's state changes only once the plan has accepted the new points
+        self.plan.set_points(theta_d, phi_d)
+        self.alpha, self.theta_d, self.phi_d, self.chi = alpha, theta_d, phi_d, chi
         self._pot = (plm.to(cdt), None if olm is None else olm.to(cdt), eps, prec)
-        self.theta_d, self.phi_d, self.chi = gsht.deflect(self.theta, self.phi, self.alpha,
-                                                          want_chi=self.spin > 0)
-        self.plan.set_points(self.theta_d, self.phi_d)
 
     def forward(self, alm):
         """Lensed map [ncomp][npts]."""

@@ -110,6 +110,13 @@ def test_set_points_refusals(G):
     bad[17] = 4.0
     with pytest.raises(G.GshtError, match="theta outside"):
         plan.set_points(dev(bad), dev(ph))
+    # the refused sort left no valid points: every transform is refused on the host
+    y = dev(np.random.default_rng(3).standard_normal((2, 5000)))
+    for call in (lambda: plan.synth(a), lambda: plan.adjoint(y),
+                 lambda: plan.synth_many(a.unsqueeze(0)), lambda: plan.adjoint_many(y.unsqueeze(0)),
+                 lambda: plan.synth_deriv(a), lambda: plan.synth_vjp(a, y)):
+        with pytest.raises(G.GshtError, match="no valid points"):
+            call()
     plan.set_points(dev(th), dev(ph))             # valid points again: same results as before
     assert torch.equal(plan.synth(a).cpu(), before)
     plan.close()
