@@ -9,7 +9,8 @@ What it computes (Reinecke, Belkner & Carron 2023, Sect. 2):
 * ``synth``   -- eq. (forward) for spin 0, eq. (forwardpol) with chi = 0 for spin s > 0,
   evaluated as a direct sum over every (l, m), -l <= m <= l.
 * ``adjoint`` -- eq. (adjoint) for spin 0; for spin s the two-component adjoint
-  followed by the gradient/curl split given right after eq. (forwardpol).
+  followed by the gradient/curl split given right after eq. (forwardpol);
+  ``adjoint_cols`` gives the same sums for a chosen set of m only.
 * ``ring_synth`` / ``ring_adjoint`` -- the same sums restricted to the
   (theta, m) representation of iso-latitude rings (the "synthesis" step of
   Sect. 3 and its adjoint), used as stage references.
@@ -60,6 +61,8 @@ def _load():
         lib.gsht_oracle_slambda.argtypes = [i, i, i, ctypes.c_double, dp]
         lib.gsht_oracle_synth.argtypes = [dp, i, i, i, i64, dp, dp, dp, i]
         lib.gsht_oracle_adjoint.argtypes = [dp, i, i, i, i64, dp, dp, dp, i]
+        lib.gsht_oracle_adjoint_cols.argtypes = [dp, i, i, i, i64, dp, dp, dp, i, dp, i]
+        lib.gsht_oracle_adjoint_cols.restype = ctypes.c_int
         lib.gsht_oracle_ring_synth.argtypes = [dp, i, i, i, i, dp, dp, i]
         lib.gsht_oracle_ring_adjoint.argtypes = [dp, i, i, i, i, dp, dp, i]
         lib.gsht_oracle_synth_deriv.argtypes = [dp, i, i, i, i64, dp, dp, dp, dp, i]
@@ -128,6 +131,21 @@ def adjoint(maps, lmax: int, mmax: int, spin: int, theta, phi, nthreads: int = 0
     out = np.zeros((ncomp(spin), nalm(lmax, mmax)), dtype=np.complex128)
     _check(_load().gsht_oracle_adjoint(_p(y), lmax, mmax, spin, th.size, _p(th), _p(ph),
                                        _p(out.view(np.float64)), nthreads), "adjoint")
+    return out
+
+
+def adjoint_cols(maps, lmax: int, mmax: int, spin: int, theta, phi, ms,
+                 nthreads: int = 0) -> np.ndarray:
+    """The direct-sum adjoint restricted to the columns m in ``ms``: [ncomp][nalm]
+    complex128 with those columns as ``adjoint`` gives them and zeros elsewhere."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    y = np.ascontiguousarray(np.asarray(maps, dtype=np.float64)).reshape(ncomp(spin), th.size)
+    ml = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    out = np.zeros((ncomp(spin), nalm(lmax, mmax)), dtype=np.complex128)
+    _check(_load().gsht_oracle_adjoint_cols(_p(y), lmax, mmax, spin, th.size, _p(th), _p(ph),
+                                            _p(ml), ml.size, _p(out.view(np.float64)), nthreads),
+           "adjoint_cols")
     return out
 
 

@@ -379,6 +379,67 @@ int gsht_oracle_synth(const double *alm, int lmax, int mmax, int spin, int64_t n
 }
 
 /*
+ * Direct-sum adjoint for one m >= 0: the coefficients (l, m), l = m..lmax, of every
+ * component, written into alm ([ncomp][nalm] complex).  Returns ORACLE_ENOMEM on
+ * allocation failure.
+ */
+static int adjoint_one_m(const double *map, int lmax, int spin, int64_t npts, const double *theta,
+                         const double *phi, int64_t nalm, int m, double *alm)
+{
+    rec_table tp = {0}, tm = {0};
+    double *sp = (double *)calloc(2 * (size_t)(lmax + 1), sizeof(double));
+    double *sm = (double *)calloc(2 * (size_t)(lmax + 1), sizeof(double));
+    int ok = sp && sm && rec_table_init(&tp, lmax, m, spin) == ORACLE_OK;
+    if (ok && spin > 0)
+        ok = rec_table_init(&tm, lmax, m, -spin) == ORACLE_OK;
+    if (ok) {
+        for (int64_t i = 0; i < npts; ++i) {
+            double c = cos(m * phi[i]), s = sin(m * phi[i]);
+            /* +s part: (Q + iU) e^{-i m phi} sY_lm ; spin 0: T e^{-i m phi} Y_lm */
+            double q = map[i], u = (spin > 0) ? map[npts + i] : 0.0;
+            double pr = q * c + u * s, pi = u * c - q * s;
+            if (tp.l0 <= lmax) {
+                WALK_BEGIN(&tp, lmax, theta[i])
+                sp[2 * l] += pr * lam;
+                sp[2 * l + 1] += pi * lam;
+                WALK_END(lmax)
+            }
+            if (spin > 0 && tm.l0 <= lmax) {
+                /* -s part: (Q - iU) e^{-i m phi} (-s)Y_lm */
+                double nr = q * c - u * s, ni = -u * c - q * s;
+                WALK_BEGIN(&tm, lmax, theta[i])
+                sm[2 * l] += nr * lam;
+                sm[2 * l + 1] += ni * lam;
+                WALK_END(lmax)
+            }
+        }
+        for (int l = m; l <= lmax; ++l) {
+            double *g = alm + 2 * alm_idx(lmax, l, m);
+            if (l < spin)
+                continue;
+            if (spin == 0) {
+                g[0] = sp[2 * l];
+                g[1] = (m == 0) ? 0.0 : sp[2 * l + 1];
+            } else {
+                double sg = (spin & 1) ? -1.0 : 1.0;
+                double ar = sp[2 * l] + sg * sm[2 * l], ai = sp[2 * l + 1] + sg * sm[2 * l + 1];
+                double br = sp[2 * l] - sg * sm[2 * l], bi = sp[2 * l + 1] - sg * sm[2 * l + 1];
+                double *cc = g + 2 * nalm;
+                g[0] = -0.5 * ar;                  /* G = -(S+ + (-1)^s S-)/2   */
+                g[1] = (m == 0) ? 0.0 : -0.5 * ai;
+                cc[0] = -0.5 * bi;                 /* C = -(S+ - (-1)^s S-)/(2i) */
+                cc[1] = (m == 0) ? 0.0 : 0.5 * br;
+            }
+        }
+    }
+    rec_table_free(&tp);
+    rec_table_free(&tm);
+    free(sp);
+    free(sm);
+    return ok ? ORACLE_OK : ORACLE_ENOMEM;
+}
+
+/*
  * Direct-sum adjoint.  map: [ncomp][npts] real; alm out: [ncomp][nalm] complex.
  * Parallel over m >= 0; each m is owned by one thread.
  */
@@ -394,59 +455,43 @@ int gsht_oracle_adjoint(const double *map, int lmax, int mmax, int spin, int64_t
     memset(alm, 0, sizeof(double) * 2 * (size_t)nalm * (spin > 0 ? 2 : 1));
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
     for (int m = 0; m <= mmax; ++m) {
-        rec_table tp = {0}, tm = {0};
-        double *sp = (double *)calloc(2 * (size_t)(lmax + 1), sizeof(double));
-        double *sm = (double *)calloc(2 * (size_t)(lmax + 1), sizeof(double));
-        int ok = sp && sm && rec_table_init(&tp, lmax, m, spin) == ORACLE_OK;
-        if (ok && spin > 0)
-            ok = rec_table_init(&tm, lmax, m, -spin) == ORACLE_OK;
-        if (!ok) {
+        if (adjoint_one_m(map, lmax, spin, npts, theta, phi, nalm, m, alm) != ORACLE_OK) {
 #pragma omp atomic write
             status = ORACLE_ENOMEM;
-        } else {
-            for (int64_t i = 0; i < npts; ++i) {
-                double c = cos(m * phi[i]), s = sin(m * phi[i]);
-                /* +s part: (Q + iU) e^{-i m phi} sY_lm ; spin 0: T e^{-i m phi} Y_lm */
-                double q = map[i], u = (spin > 0) ? map[npts + i] : 0.0;
-                double pr = q * c + u * s, pi = u * c - q * s;
-                if (tp.l0 <= lmax) {
-                    WALK_BEGIN(&tp, lmax, theta[i])
-                    sp[2 * l] += pr * lam;
-                    sp[2 * l + 1] += pi * lam;
-                    WALK_END(lmax)
-                }
-                if (spin > 0 && tm.l0 <= lmax) {
-                    /* -s part: (Q - iU) e^{-i m phi} (-s)Y_lm */
-                    double nr = q * c - u * s, ni = -u * c - q * s;
-                    WALK_BEGIN(&tm, lmax, theta[i])
-                    sm[2 * l] += nr * lam;
-                    sm[2 * l + 1] += ni * lam;
-                    WALK_END(lmax)
-                }
-            }
-            for (int l = m; l <= lmax; ++l) {
-                double *g = alm + 2 * alm_idx(lmax, l, m);
-                if (l < spin)
-                    continue;
-                if (spin == 0) {
-                    g[0] = sp[2 * l];
-                    g[1] = (m == 0) ? 0.0 : sp[2 * l + 1];
-                } else {
-                    double sg = (spin & 1) ? -1.0 : 1.0;
-                    double ar = sp[2 * l] + sg * sm[2 * l], ai = sp[2 * l + 1] + sg * sm[2 * l + 1];
-                    double br = sp[2 * l] - sg * sm[2 * l], bi = sp[2 * l + 1] - sg * sm[2 * l + 1];
-                    double *cc = g + 2 * nalm;
-                    g[0] = -0.5 * ar;                  /* G = -(S+ + (-1)^s S-)/2   */
-                    g[1] = (m == 0) ? 0.0 : -0.5 * ai;
-                    cc[0] = -0.5 * bi;                 /* C = -(S+ - (-1)^s S-)/(2i) */
-                    cc[1] = (m == 0) ? 0.0 : 0.5 * br;
-                }
-            }
         }
-        rec_table_free(&tp);
-        rec_table_free(&tm);
-        free(sp);
-        free(sm);
+    }
+    return status;
+}
+
+/*
+ * The same adjoint for the listed m values only (each in [0, mmax], no repeats):
+ * their coefficients as gsht_oracle_adjoint gives them, every other entry of alm
+ * zero.  Lets a test check sampled outputs of a large adjoint one column at a time.
+ */
+int gsht_oracle_adjoint_cols(const double *map, int lmax, int mmax, int spin, int64_t npts,
+                             const double *theta, const double *phi, const int32_t *mlist,
+                             int nm, double *alm, int nthreads)
+{
+    int nt = nthreads_or_default(nthreads);
+    int64_t nalm;
+    int status = ORACLE_OK;
+    if (lmax < 0 || mmax < 0 || mmax > lmax || spin < 0 || spin > lmax || npts < 0 || nm < 0)
+        return ORACLE_EINVAL;
+    for (int k = 0; k < nm; ++k) {
+        if (mlist[k] < 0 || mlist[k] > mmax)
+            return ORACLE_EINVAL;
+        for (int j = 0; j < k; ++j)
+            if (mlist[j] == mlist[k])
+                return ORACLE_EINVAL;
+    }
+    nalm = alm_count(lmax, mmax);
+    memset(alm, 0, sizeof(double) * 2 * (size_t)nalm * (spin > 0 ? 2 : 1));
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int k = 0; k < nm; ++k) {
+        if (adjoint_one_m(map, lmax, spin, npts, theta, phi, nalm, mlist[k], alm) != ORACLE_OK) {
+#pragma omp atomic write
+            status = ORACLE_ENOMEM;
+        }
     }
     return status;
 }

@@ -1,9 +1,11 @@
 """Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
 
-This module holds no spherical-harmonic or NUFFT arithmetic: it only draws
-random coefficients, builds point sets (uniform, Gauss-Legendre, thinned
-Gauss-Legendre) and displaces them along great circles.  Both the GPU path and
-the oracle receive exactly the arrays produced here.
+This module holds no spherical-harmonic, NUFFT or lensing arithmetic: it only
+draws random coefficients (signal a_lm and lensing potentials) and builds the
+undeflected point sets (uniform, Gauss-Legendre, thinned Gauss-Legendre).  The
+GPU path and the oracle receive exactly the arrays produced here; each side
+deflects the points with its own code (the library's lensing calls, or the
+oracle's direct sums).
 
 Workloads (shapes of the paper's lensing benchmarks, Sect. 4):
 
@@ -13,12 +15,13 @@ Workloads (shapes of the paper's lensing benchmarks, Sect. 4):
 * ``pollens_thin6144`` -- spin 2, lmax 4096, longitude-thinned Gauss-Legendre grid with
   6144 rings (about 4.8e7 points, the "~5e7 pixel" intermediate grid of Sect. 4), deflected.
 
-Deflection model (a stand-in for a lensing potential; the paper's inputs are
-simulated CMB fields, not a public dataset): a curl-free tangent field
-alpha = grad_perp Phi with Phi(n) = sum_q A_q cos(k_q . n + c_q), 48 plane waves
-in 3-D restricted to the unit sphere, |k_q| log-uniform in [2, 600],
-A_q proportional to |k_q|^-3, rescaled to an rms |alpha| of 2.5 arcmin.  Points are
-moved along the great circle generated by alpha (the geodesic step of Sect. 2).
+Deflection model (a stand-in for the paper's simulated lensing potential): a
+Gaussian potential phi_LM with C_L proportional to L^-4 above L = 60, flat at
+C_60 for 2 <= L <= 60 and zero for L < 2, band-limited at the workload's lmax, and
+scaled so that the sphere average of |alpha|^2 with alpha the gradient of the
+potential is (2.5 arcmin)^2.  The deflection field is the spin-1 synthesis of
+sqrt(L (L + 1)) phi_LM on the undeflected points (eq. deflect) and the points move
+along great circles (end of Sect. 3).
 """
 from __future__ import annotations
 
@@ -108,73 +111,30 @@ def thinned_gl_grid(nring: int):
     return theta, phi
 
 
-def deflect(theta, phi, seed: int, rms_arcmin: float = 2.5, nmodes: int = 48,
-            chunk: int = 1 << 22, device=None):
-    """Displace points along great circles by a smooth random curl-free field.
-
-    theta/phi: numpy arrays or torch tensors.  The arithmetic runs in torch FP64 on
-    ``device`` (default: the tensors' device, or the CPU for numpy input); the
-    result has the input's type.  Returns (theta', phi') in [0, pi] x [0, 2 pi).
-    """
-    import torch
-    rng = np.random.default_rng(seed)
-    kmag = np.exp(rng.uniform(math.log(2.0), math.log(600.0), nmodes))
-    kdir = rng.standard_normal((nmodes, 3))
-    kdir /= np.linalg.norm(kdir, axis=1)[:, None]
-    kvec = kdir * kmag[:, None]
-    amp = kmag ** -3.0
-    ph0 = rng.uniform(0.0, 2.0 * math.pi, nmodes)
-    as_numpy = not isinstance(theta, torch.Tensor)
-    if as_numpy:
-        dev = torch.device(device or "cpu")
-        th_all = torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float64)).to(dev)
-        ph_all = torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float64)).to(dev)
-    else:
-        dev = torch.device(device) if device is not None else theta.device
-        th_all = theta.to(dev, torch.float64)
-        ph_all = phi.to(dev, torch.float64)
-    n = th_all.numel()
-    ath = torch.empty(n, dtype=torch.float64, device=dev)
-    aph = torch.empty(n, dtype=torch.float64, device=dev)
-    kv = kvec.tolist()
-    for s in range(0, n, chunk):
-        th = th_all[s:s + chunk]
-        ph = ph_all[s:s + chunk]
-        st, ct, sp, cp = torch.sin(th), torch.cos(th), torch.sin(ph), torch.cos(ph)
-        nx, ny, nz = st * cp, st * sp, ct
-        gx = torch.zeros_like(th)
-        gy = torch.zeros_like(th)
-        gz = torch.zeros_like(th)
-        for q in range(nmodes):
-            f = -amp[q] * torch.sin(kv[q][0] * nx + kv[q][1] * ny + kv[q][2] * nz + ph0[q])
-            gx += f * kv[q][0]
-            gy += f * kv[q][1]
-            gz += f * kv[q][2]
-        ath[s:s + chunk] = gx * ct * cp + gy * ct * sp - gz * st
-        aph[s:s + chunk] = -gx * sp + gy * cp
-    scale = rms_arcmin * ARCMIN / math.sqrt(float(torch.mean(ath * ath + aph * aph)))
-    ath *= scale
-    aph *= scale
-    tp, pp = geodesic_step(th_all, ph_all, ath, aph)
-    if as_numpy:
-        return tp.cpu().numpy(), pp.cpu().numpy()
-    return tp, pp
+POTENTIAL_RMS_ARCMIN = 2.5
 
 
-def geodesic_step(theta, phi, ath, aph):
-    """n' = cos|a| n + sin|a|/|a| (a_th e_th + a_ph e_ph)  (Sect. 2); torch FP64."""
-    import torch
-    a = torch.sqrt(ath * ath + aph * aph)
-    safe = torch.where(a > 0, a, torch.ones_like(a))
-    sinc = torch.where(a > 0, torch.sin(a) / safe, torch.ones_like(a))
-    ca = torch.cos(a)
-    st, ct = torch.sin(theta), torch.cos(theta)
-    zp = ca * ct - sinc * ath * st
-    rho_x = ca * st + sinc * ath * ct      # along the local horizontal radial axis
-    rho_y = sinc * aph                     # along e_phi
-    thp = torch.atan2(torch.sqrt(rho_x * rho_x + rho_y * rho_y), zp)
-    php = torch.remainder(phi + torch.atan2(rho_y, rho_x), 2.0 * math.pi)
-    return thp, php
+def potential_cl(lmax: int) -> np.ndarray:
+    """Shape of the lensing potential's spectrum: L^-4 above L = 60, flat at its
+    L = 60 value for 2 <= L <= 60, zero for L < 2 (the overall scale is set by the
+    deflection rms)."""
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    cl = np.where(ell > 60, (np.maximum(ell, 1.0) / 60.0) ** -4.0, 1.0)
+    cl[:2] = 0.0
+    return cl
+
+
+def lensing_potential(lmax: int, seed: int, rms_arcmin: float = POTENTIAL_RMS_ARCMIN) -> np.ndarray:
+    """Seeded Gaussian lensing potential phi_LM [nalm] complex128 (mmax = lmax), scaled
+    so that the realisation's deflection has the requested rms over the sphere:
+    mean |alpha|^2 = (1/4 pi) sum_LM L (L + 1) |phi_LM|^2 over all M (stored M > 0
+    counted twice, by the reality of the field)."""
+    plm = gaussian_alm(lmax, lmax, 0, np.random.default_rng(seed), cl=potential_cl(lmax))[0]
+    ls = np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)]).astype(np.float64)
+    ms = np.concatenate([np.full(lmax + 1 - m, m) for m in range(lmax + 1)])
+    wm = np.where(ms == 0, 1.0, 2.0)
+    ms2 = float(np.sum(wm * ls * (ls + 1.0) * np.abs(plm) ** 2)) / (4.0 * math.pi)
+    return plm * (rms_arcmin * ARCMIN / math.sqrt(ms2))
 
 
 WORKLOADS = {
@@ -185,24 +145,103 @@ WORKLOADS = {
 }
 
 
-def make_points(spec: dict, replica: int = 0, deflected: bool = True, device=None):
-    """Point set of a workload (theta, phi) as FP64 numpy arrays (the deflection
-    arithmetic runs in torch on ``device``, default CPU)."""
-    seed = seed_for(spec["id"], replica)
+def base_points(spec: dict, replica: int = 0):
+    """Undeflected point set of a workload (theta, phi) as FP64 numpy arrays
+    (uniform workloads are not deflected)."""
     kind = spec["points"]
     if kind == "uniform":
-        return uniform_sphere(spec["npts"], np.random.default_rng(seed))
+        return uniform_sphere(spec["npts"], np.random.default_rng(seed_for(spec["id"], replica)))
     if kind == "gl":
         th, ph, _ = gl_grid(spec["nring"], spec["nphi"])
     elif kind == "thin":
         th, ph = thinned_gl_grid(spec["nring"])
     else:
         raise ValueError(kind)
-    if deflected:
-        th, ph = deflect(th, ph, seed + 500, device=device)
     return th, ph
+
+
+def make_potential(spec: dict, replica: int = 0) -> np.ndarray:
+    """The workload's lensing potential (band limit = the workload's lmax)."""
+    return lensing_potential(spec["lmax"], seed_for(spec["id"], replica) + 500)
+
+
+# Sampled accuracy check of the full-size workloads: points near the equator (where
+# Sect. 4 evaluates the effective accuracy), within 5 degrees of the poles, and
+# uniformly random, drawn without repeats from the undeflected point set.
+SAMPLE_SPLIT = (5000, 2500, 2500)
+SAMPLE_EQ_BAND = 0.01                   # |theta - pi/2| below this, in radians
+SAMPLE_POLE_CAP = 5.0 * math.pi / 180.0
+
+
+def sample_indices(theta, seed: int, split=SAMPLE_SPLIT) -> np.ndarray:
+    """Point indices of the sampled check: the equator group, the polar group and the
+    random group, concatenated in that order."""
+    th = np.asarray(theta)
+    rng = np.random.default_rng(seed)
+    eq = np.flatnonzero(np.abs(th - math.pi / 2) < SAMPLE_EQ_BAND)
+    pole = np.flatnonzero((th < SAMPLE_POLE_CAP) | (th > math.pi - SAMPLE_POLE_CAP))
+    g_eq = rng.choice(eq, split[0], replace=False)
+    g_pole = rng.choice(pole, split[1], replace=False)
+    taken = np.zeros(th.size, bool)
+    taken[g_eq] = True
+    taken[g_pole] = True
+    g_rand = rng.choice(np.flatnonzero(~taken), split[2], replace=False)
+    return np.concatenate([g_eq, g_pole, g_rand]).astype(np.int64)
+
+
+def adjoint_support(split=SAMPLE_SPLIT) -> np.ndarray:
+    """Positions (into the sample) where the adjoint check's input is non-zero: the
+    first half of each group."""
+    o = np.cumsum((0,) + tuple(split))
+    return np.concatenate([np.arange(o[k], o[k] + split[k] // 2) for k in range(3)])
+
+
+def adjoint_check_input(ncomp: int, n: int, seed: int) -> np.ndarray:
+    """Values of the adjoint check's input on its support: N(0, 1), [ncomp][n]."""
+    return np.random.default_rng(seed).standard_normal((ncomp, n))
 
 
 def make_alm(spec: dict, replica: int = 0) -> np.ndarray:
     return gaussian_alm(spec["lmax"], spec["mmax"], spec["spin"],
                         np.random.default_rng(seed_for(spec["id"], replica) + 77))
+
+
+# Batched uneven workload: independent instances with lmax uniform in [512, 3000],
+# spin 0 or 2, 1e6 to 6e6 uniformly random points each, FP32 at epsilon 1e-5; and
+# the other reading of "16 maps sharing a geometry": 4 geometries of 16 maps each.
+BATCH_ID = 4
+
+
+def batched_instances(n: int = 64, seed: int = 1000 * BATCH_ID):
+    """Specs of the uneven batch: dicts with lmax (= mmax), spin, npts and the seeds of
+    the instance's points and coefficients."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        lmax = int(rng.integers(512, 3001))
+        out.append(dict(lmax=lmax, mmax=lmax, spin=int(rng.choice([0, 2])),
+                        npts=int(rng.integers(1_000_000, 6_000_001)),
+                        point_seed=seed + 10 * i + 1, alm_seed=seed + 10 * i + 2))
+    return out
+
+
+def batched_groups(ngroups: int = 4, maps: int = 16, seed: int = 1000 * BATCH_ID + 900):
+    """Specs of the geometry groups: dicts with lmax, spin, npts, the point seed and one
+    coefficient seed per map."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(ngroups):
+        lmax = int(rng.integers(512, 3001))
+        out.append(dict(lmax=lmax, mmax=lmax, spin=int(rng.choice([0, 2])),
+                        npts=int(rng.integers(1_000_000, 6_000_001)),
+                        point_seed=seed + 100 * g + 1,
+                        alm_seeds=[seed + 100 * g + 10 + k for k in range(maps)]))
+    return out
+
+
+def instance_points(spec: dict):
+    return uniform_sphere(spec["npts"], np.random.default_rng(spec["point_seed"]))
+
+
+def instance_alm(spec: dict, seed: int) -> np.ndarray:
+    return gaussian_alm(spec["lmax"], spec["mmax"], spec["spin"], np.random.default_rng(seed))

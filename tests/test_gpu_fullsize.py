@@ -1,15 +1,21 @@
-"""Full-size GPU parity at the benchmark workloads, on sampled outputs.
+"""Full-size GPU parity at the benchmark workloads, on 10^4 sampled outputs.
 
 The transforms run on every point (8.4M, 33.6M and 48M deflected points) in the
-same plan configuration the benchmark times; the FP64 oracle evaluates sampled
-outputs one by one: points near the equator (as in the paper's accuracy check),
-within a few degrees of the poles (where the paper reports a uniform error map)
-and uniformly random ones.  The adjoint is checked with the input supported on
-the sampled points only (zero elsewhere), which the oracle can sum exactly.
-A Gauss-Legendre round trip (exact quadrature) pins both directions at full
-band limit without the oracle.
+plan configurations the benchmark times.  The points are the workload's grid
+deflected by the library (FP64 spin-1 synthesis of the potential's gradient and the
+great-circle step); the FP64 oracle values at 10^4 sampled points (5000 near the
+equator, where Sect. 4 measures the effective accuracy, 2500 within 5 degrees of the
+poles, 2500 random) were written by ``tests/golden/make_fullsize_samples.py``, which
+deflects the sampled points itself with the oracle's direct sums.  The test first
+checks that both deflections agree, then gives the GPU the oracle's coordinates at
+the sampled points, so that both sides evaluate the same points.  The adjoint is
+checked with its input supported on 5000 of the sampled points (zero elsewhere) on
+25 columns m of the result, which the oracle sums exactly.  Gauss-Legendre round
+trips (exact quadrature) pin both directions over all coefficients at full band
+limit without the oracle.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -20,6 +26,8 @@ import oracle
 from paper_2304_10431_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -34,98 +42,179 @@ def G():
     return gsht
 
 
+def fixture(name):
+    with np.load(os.path.join(GOLDEN, "%s_samples.npz" % name)) as f:
+        return {k: f[k] for k in ("idx", "theta", "phi", "synth")}
+
+
+def unit(th, ph):
+    return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+
+
 _POINTS = {}
 
 
 def points(name):
+    """(theta, phi) on the GPU: the library-deflected workload with the sampled points
+    set to the oracle's coordinates; also the largest distance between the two
+    deflections at the sampled points."""
     if name not in _POINTS:
+        from paper_2304_10431_amd.lensing import deflected_points
         spec = wl.WORKLOADS[name]
-        if spec["points"] == "thin":
-            th, ph = wl.thinned_gl_grid(spec["nring"])
-        else:
-            th, ph, _ = wl.gl_grid(spec["nring"], spec["nphi"])
-        th, ph = wl.deflect(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(),
-                            wl.seed_for(spec["id"]) + 500)
-        _POINTS[name] = (th, ph)
+        th0, ph0 = wl.base_points(spec)
+        plm = torch.from_numpy(wl.make_potential(spec)).cuda()
+        th, ph = deflected_points(torch.from_numpy(th0).cuda(), torch.from_numpy(ph0).cuda(),
+                                  plm, spec["lmax"])
+        del th0, ph0
+        fx = fixture(name)
+        idx = torch.from_numpy(fx["idx"]).cuda()
+        got = unit(th[idx].cpu().numpy(), ph[idx].cpu().numpy())
+        d = np.linalg.norm(got - unit(fx["theta"], fx["phi"]), axis=0)
+        polar = np.zeros(d.size, bool)
+        polar[wl.SAMPLE_SPLIT[0]:wl.SAMPLE_SPLIT[0] + wl.SAMPLE_SPLIT[1]] = True
+        dist = (float(np.max(d[~polar])), float(np.max(d[polar])))
+        th[idx] = torch.from_numpy(fx["theta"]).cuda()
+        ph[idx] = torch.from_numpy(fx["phi"]).cuda()
+        _POINTS.clear()  # one workload's points at a time
+        _POINTS[name] = (th, ph, fx, dist)
     return _POINTS[name]
 
 
-def sample_indices(th_h, n, seed):
+NAMES = ["tlens_l2048", "pollens_l4096", "pollens_thin6144"]
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_fullsize_deflection_matches_oracle(G, name):
+    """The library's deflection of the workload equals the oracle's at the sampled
+    points: distance on the unit sphere at most 1e-14, and 5e-14 within 5 degrees of
+    the poles, where the oracle's FP64 recurrence itself loses digits at high degree
+    (its direct sum and the plain CPU NUFFT-based SHT at epsilon 1e-13 differ by
+    1.5e-14 there at lmax 2048, and by 2e-16 at the median)."""
+    th, ph, fx, dist = points(name)
+    say("deflection", name, th.numel(), "max distance %.2e (polar %.2e)" % dist)
+    assert dist[0] <= 1e-14, dist
+    assert dist[1] <= 5e-14, dist
+
+
+def adjoint_columns(mmax, seed=17):
     rng = np.random.default_rng(seed)
-    eq = np.flatnonzero(np.abs(th_h - math.pi / 2) < 0.02)
-    pole = np.flatnonzero((th_h < 0.05) | (th_h > math.pi - 0.05))
-    k = n // 3
-    idx = np.concatenate([rng.choice(eq, k, replace=False), rng.choice(pole, k, replace=False),
-                          rng.choice(th_h.size, n - 2 * k, replace=False)])
-    return np.unique(idx)
+    mid = rng.choice(np.arange(4, mmax), 20, replace=False)
+    return np.concatenate([[0, 1, 2, 3], np.sort(mid), [mmax]]).astype(np.int32)
+
+
+def col_mask(lmax, ms):
+    sel = np.zeros(oracle.nalm(lmax, lmax), bool)
+    for m in ms:
+        i0 = oracle.alm_index(m, m, lmax)
+        sel[i0:i0 + lmax + 1 - m] = True
+    return sel
 
 
 CASES = [
-    # workload, precision, eps, nsample, oversampling (None: the default plan)
-    ("tlens_l2048", "f64", 1e-10, 300, None),
-    ("tlens_l2048", "f32", 1e-5, 300, None),
-    ("pollens_l4096", "f64", 1e-10, 150, None),
-    ("pollens_l4096", "f32", 1e-5, 150, None),
-    ("pollens_thin6144", "f32", 1e-5, 150, None),
-    # the benchmark's plans: chosen by timing (1.5 for these forms), and 1.25 in FP64
-    ("pollens_thin6144", "f32", 1e-5, 150, "tuned"),
-    ("pollens_thin6144", "f64", 1e-10, 100, "tuned"),
-    ("pollens_thin6144", "f64", 1e-5, 100, 1.25),
+    # workload, precision, eps, oversampling (None: the default plan)
+    ("tlens_l2048", "f64", 1e-10, None),
+    ("tlens_l2048", "f32", 1e-5, None),
+    ("pollens_l4096", "f64", 1e-10, None),
+    ("pollens_l4096", "f32", 1e-5, None),
+    ("pollens_thin6144", "f32", 1e-5, None),
+    # the benchmark's plans: chosen by timing, and 1.25 in FP64 at 1e-5
+    ("pollens_thin6144", "f32", 1e-5, "tuned"),
+    ("pollens_thin6144", "f64", 1e-10, "tuned"),
+    ("pollens_thin6144", "f64", 1e-5, "tuned"),
+    ("pollens_thin6144", "f64", 1e-5, 1.25),
 ]
-ADJ_CASES = CASES[:4] + CASES[5:]
 
 
-@pytest.mark.parametrize("name,prec,eps,nsample,sigma", CASES)
-def test_fullsize_synthesis_sampled(G, name, prec, eps, nsample, sigma):
+@pytest.mark.parametrize("name,prec,eps,sigma", CASES)
+def test_fullsize_sampled(G, name, prec, eps, sigma):
     spec = wl.WORKLOADS[name]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
-    th, ph = points(name)
-    say("fullsize synth", name, prec, eps, sigma, th.numel())
-    alm_h = wl.make_alm(spec)
-    cdt = torch.complex128 if prec == "f64" else torch.complex64
-    plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec, sigma=sigma)
-    m = plan.synth(torch.from_numpy(alm_h).cuda().to(cdt))
-    th_h, ph_h = th.cpu().numpy(), ph.cpu().numpy()
-    idx = sample_indices(th_h, nsample, 3)
-    got = m[:, torch.from_numpy(idx).cuda()].double().cpu().numpy()
-    plan.close()
-    ref = oracle.synth(alm_h, lmax, mmax, spin, th_h[idx], ph_h[idx])
-    err = oracle.eps_eff(got, ref)
-    say("  eps_eff", err)
-    assert err <= eps, err
-
-
-@pytest.mark.parametrize("name,prec,eps,nsample,sigma", ADJ_CASES)
-def test_fullsize_adjoint_sampled(G, name, prec, eps, nsample, sigma):
-    spec = wl.WORKLOADS[name]
-    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
-    th, ph = points(name)
-    say("fullsize adjoint", name, prec, eps, sigma, th.numel())
-    th_h, ph_h = th.cpu().numpy(), ph.cpu().numpy()
-    idx = sample_indices(th_h, nsample, 5)
     ncomp = 1 if spin == 0 else 2
-    y_s = np.random.default_rng(9).standard_normal((ncomp, idx.size))
+    th, ph, fx, _ = points(name)
+    say("fullsize", name, prec, eps, sigma, th.numel())
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
     rdt = torch.float64 if prec == "f64" else torch.float32
-    y = torch.zeros((ncomp, th.numel()), dtype=rdt, device="cuda")
-    y[:, torch.from_numpy(idx).cuda()] = torch.from_numpy(y_s).cuda().to(rdt)
+    idx = torch.from_numpy(fx["idx"]).cuda()
     plan = G.Plan(th, ph, lmax, mmax, spin, eps, prec, sigma=sigma)
-    got = plan.adjoint(y).cpu().numpy().astype(np.complex128)
+    m = plan.synth(torch.from_numpy(wl.make_alm(spec)).cuda().to(cdt))
+    got = m[:, idx].double().cpu().numpy()
+    del m
+    # adjoint: input on half of each sample group
+    sup = wl.adjoint_support()
+    y_s = wl.adjoint_check_input(ncomp, sup.size, 9)
+    y = torch.zeros((ncomp, th.numel()), dtype=rdt, device="cuda")
+    y[:, idx[torch.from_numpy(sup).cuda()]] = torch.from_numpy(y_s).cuda().to(rdt)
+    b = plan.adjoint(y).cpu().numpy().astype(np.complex128)
     plan.close()
-    ref = oracle.adjoint(y_s, lmax, mmax, spin, th_h[idx], ph_h[idx])
-    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
-    err = oracle.eps_eff(got * w, ref * w)
-    say("  eps_eff", err)
-    assert err <= eps, err
+    del y
+    e_syn = oracle.eps_eff(got, fx["synth"])
+    ms = adjoint_columns(mmax)
+    ref = oracle.adjoint_cols(y_s, lmax, mmax, spin, fx["theta"][sup], fx["phi"][sup], ms)
+    sel = col_mask(lmax, ms)
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[sel][None, :]
+    e_adj = oracle.eps_eff(b[:, sel] * w, ref[:, sel] * w)
+    say("  eps_eff synthesis %.3e (10^4 points), adjoint %.3e (%d columns)"
+        % (e_syn, e_adj, ms.size))
+    assert e_syn <= eps, e_syn
+    assert e_adj <= eps, e_adj
 
 
-@pytest.mark.parametrize("lmax,spin,prec,eps,tol", [
-    (2048, 0, "f64", 1e-10, 1e-9),
-    (4096, 2, "f32", 1e-5, 1e-4),
+def test_fullsize_many_maps_matrix_core(G):
+    """Sixteen maps on the benchmark's FP32 plan through the matrix-core Legendre step
+    (synthesis and adjoint), every map against the oracle on the sample.  The maps are
+    copies of the workload's coefficients scaled over six decades, so each map's oracle
+    values are the scaled sample values."""
+    name = "pollens_thin6144"
+    spec = wl.WORKLOADS[name]
+    lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    th, ph, fx, _ = points(name)
+    say("fullsize matrix-core 16 maps", th.numel())
+    nm = 16
+    scale = np.logspace(-3, 3, nm)
+    idx = torch.from_numpy(fx["idx"]).cuda()
+    plan = G.Plan(th, ph, lmax, mmax, spin, 1e-5, "f32", sigma="tuned")
+    a = torch.from_numpy(wl.make_alm(spec)).cuda().to(torch.complex64)
+    am = (a.unsqueeze(0) * torch.from_numpy(scale).cuda().to(torch.complex64)[:, None, None])
+    mm = plan.synth_many(am.contiguous())
+    del am
+    worst = 0.0
+    for k in range(nm):
+        got = mm[k][:, idx].double().cpu().numpy() / scale[k]
+        worst = max(worst, oracle.eps_eff(got, fx["synth"]))
+    del mm
+    sup = wl.adjoint_support()
+    y_s = wl.adjoint_check_input(2, sup.size, 9)
+    ym = torch.zeros((nm, 2, th.numel()), dtype=torch.float32, device="cuda")
+    ysd = torch.from_numpy(y_s).cuda().float()
+    for k in range(nm):
+        ym[k][:, idx[torch.from_numpy(sup).cuda()]] = ysd * float(scale[k])
+    bm = plan.adjoint_many(ym)
+    del ym
+    plan.close()
+    ms = adjoint_columns(mmax)
+    ref = oracle.adjoint_cols(y_s, lmax, mmax, spin, fx["theta"][sup], fx["phi"][sup], ms)
+    sel = col_mask(lmax, ms)
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[sel][None, :]
+    worst_a = 0.0
+    for k in range(nm):
+        got = bm[k].cpu().numpy().astype(np.complex128)[:, sel] / scale[k]
+        worst_a = max(worst_a, oracle.eps_eff(got * w, ref[:, sel] * w))
+    say("  worst eps_eff over 16 maps: synthesis %.3e, adjoint %.3e" % (worst, worst_a))
+    assert worst <= 1e-5, worst
+    assert worst_a <= 1e-5, worst_a
+
+
+@pytest.mark.parametrize("lmax,spin,prec,eps", [
+    (2048, 0, "f64", 1e-10),
+    (4096, 2, "f32", 1e-5),
+    (4096, 2, "f64", 1e-10),
 ])
-def test_fullsize_gl_round_trip(G, lmax, spin, prec, eps, tol):
+def test_fullsize_gl_round_trip(G, lmax, spin, prec, eps):
     """adjoint(W * synth(a)) = a on the undeflected GL grid with lmax + 1 rings and
     2 lmax + 1 longitudes (exact quadrature); the GPU treats the grid as general
-    points, so both NUFFT directions and both Legendre steps are exercised."""
+    points, so both NUFFT directions and both Legendre steps are exercised.  The bar
+    is epsilon itself, although two epsilon-accurate steps are composed: each step's
+    error is far below its bound (about 1e-12 in FP64 at 1e-10, 1e-6 in FP32 at 1e-5)."""
     say("gl round trip", lmax, spin, prec)
     th_h, ph_h, wt_h = wl.gl_grid(lmax + 1, 2 * lmax + 1)
     a_h = wl.gaussian_alm(lmax, lmax, spin, np.random.default_rng(77))
@@ -141,5 +230,5 @@ def test_fullsize_gl_round_trip(G, lmax, spin, prec, eps, tol):
     w = torch.from_numpy(np.sqrt(oracle.alm_weights(lmax, lmax))).cuda()[None, :]
     err = float(torch.linalg.norm((b.to(torch.complex128) - a.to(torch.complex128)) * w) /
                 torch.linalg.norm(a.to(torch.complex128) * w))
-    say("  round-trip rel err", err)
-    assert err <= tol, err
+    say("  round-trip rel err %.3e" % err)
+    assert err <= eps, err

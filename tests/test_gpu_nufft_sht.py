@@ -27,6 +27,7 @@ import pytest
 import torch
 
 import oracle
+from lensed_points import deflect_large
 from oracle import nufft_sht as o8
 
 pytestmark = pytest.mark.gpu
@@ -149,10 +150,9 @@ def test_gpu_equals_cpu_nufft_sht_fullsize(G, prec, eps):
     spec = wl.WORKLOADS["tlens_l2048"]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
     say("nufft-sht full-size parity", prec, eps, "lmax", lmax)
-    th0, ph0, _ = wl.gl_grid(spec["nring"], spec["nphi"])
-    th_d, ph_d = wl.deflect(torch.from_numpy(th0).cuda(), torch.from_numpy(ph0).cuda(),
-                            wl.seed_for(spec["id"]) + 500)
-    th, ph = th_d.cpu().numpy(), ph_d.cpu().numpy()
+    th0, ph0 = wl.base_points(spec)
+    th, ph = deflect_large(th0, ph0, wl.make_potential(spec), lmax)
+    th_d, ph_d = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
     a = wl.make_alm(spec)
     p = expected_plan(lmax, mmax, eps)
     plan = G.Plan(th_d, ph_d, lmax, mmax, spin, eps, prec)

@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import oracle
+from lensed_points import deflect_small
 from paper_2304_10431_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -117,18 +118,24 @@ def test_legendre_adjoint_stage_matches_oracle(G, lmax, mmax, spin, ntheta):
     assert np.all(got[:, :lmax + 1].imag == 0)
 
 
+@pytest.mark.parametrize("pair", [1, 0])
 @pytest.mark.parametrize("syn_r,adj_r,adj_b", [(1, 1, 8), (2, 2, 8), (4, 2, 4), (1, 4, 4),
                                                (2, 3, 8), (4, 4, 8), (2, 3, 4)])
 @pytest.mark.parametrize("lmax,mmax,spin,ntheta", [(300, 300, 2, 302), (200, 200, 0, 203),
-                                                   (130, 100, 2, 520)])
-def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta):
+                                                   (130, 100, 2, 520), (161, 161, 1, 1100)])
+def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta,
+                                pair):
     """Every supported launch shape (ring pairs per lane, degrees per adjoint block)
-    of both Legendre kernels against the oracle; ntheta = 520 spans several chunks
-    and a ragged last one for every shape."""
-    say("legendre shapes", syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta)
+    of both Legendre kernels against the oracle, with the adjoint as column-pair
+    workgroups summing in LDS (pair 1) and as one wave per chunk with global atomics
+    (pair 0); ntheta = 520 spans several chunks and a ragged last one for every
+    shape, ntheta = 1100 more chunks than a pair workgroup has waves, and the odd
+    mmax = 161 pairs every column with another."""
+    say("legendre shapes", syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta, pair)
     monkeypatch.setenv("GSHT_SYN_R", str(syn_r))
     monkeypatch.setenv("GSHT_ADJ_R", str(adj_r))
     monkeypatch.setenv("GSHT_ADJ_B", str(adj_b))
+    monkeypatch.setenv("GSHT_ADJ_PAIR", str(pair))
     rng = np.random.default_rng(lmax + 13 * spin)
     a = wl.gaussian_alm(lmax, mmax, spin, rng, cl=np.ones(lmax + 1))
     ref = doubled_reference(a, lmax, mmax, spin, ntheta)
@@ -169,7 +176,7 @@ def make_case(kind, n, seed):
     if kind == "gl":
         nr = max(4, int(math.sqrt(n / 2)))
         th, ph, _ = wl.gl_grid(nr, 2 * nr + 1)
-        return wl.deflect(th, ph, seed)
+        return deflect_small(th, ph, 48, seed)
     raise ValueError(kind)
 
 
