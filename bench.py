@@ -4,27 +4,35 @@ One step = one synthesis (a_lm -> map) plus one adjoint (map -> a_lm) through th
 C ABI (plan API, geometry reused as in the paper's lensing use), with all inputs
 resident in HBM.  Forms timed:
 
-  * FP32 form, epsilon = 1e-5   (headline ``value``: seconds per step)
+  * FP64 form, epsilon = 1e-10  (headline ``value``: seconds per step, the paper's
+    double precision)
+  * FP32 form, epsilon = 1e-5   (FFT/NUFFT in FP32, Legendre recurrence in FP64)
   * FP64 form, epsilon = 1e-5   (for the FP32-vs-FP64 speed-up at equal accuracy)
-  * FP64 form, epsilon = 1e-10
 
 Workload: spin 2, lmax = mmax = 4096, Gaussian E/B a_lm, points of a 6144-ring
-longitude-thinned Gauss-Legendre grid displaced by a 2.5 arcmin rms deflection
-field (about 4.8e7 points; the "~5e7 pixel" intermediate grid of the paper's
-Sect. 4 benchmark).  Synthetic data, generated with fixed seeds.
+longitude-thinned Gauss-Legendre grid displaced along great circles by the gradient
+of a Gaussian lensing potential (C_L ~ L^-4 above L = 60, 2.5 arcmin rms; about
+4.8e7 points, the "~5e7 pixel" intermediate grid of the paper's Sect. 4 benchmark).
+The deflection is computed by the library (FP64 spin-1 synthesis, great-circle
+step).  Synthetic data, generated with fixed seeds.
 
-Also reported: synthesis and adjoint times of each form (HIP events), the dominant
-kernel's achieved fraction of the MI355X FP64 vector peak (Legendre recurrence),
-the spreading kernel's HBM fraction and LDS atomic rate, per-stage times from HIP
-events inside the library, and the FP64 CPU oracle timed on a bounded sample of
-points on the host cores, with each form's effective accuracy against it
-(synthesis on the sampled points, adjoint of an input supported on them).
+Reported beside the headline: synthesis and adjoint times of each form (HIP events
+on the stream the library launches on, timed with the library's profiling off);
+per-stage times from a separate profiled pass of the same steps; the dominant
+kernel's achieved fraction of its MI355X roofline (``roofline``) and the same figure
+for the other main kernels; the spreading stage's HBM fraction and LDS atomic rate;
+the several-map (matrix-core) forms; the batched uneven workload (64 instances as
+one captured graph, and 4 geometries x 16 maps); the FP64 CPU oracle timed on a
+bounded sample of points on the host cores, with each form's effective accuracy
+against the oracle's values at 10^4 sampled points; and the plain CPU NUFFT-based
+SHT timed at lmax 2048 on 8.4M deflected points.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -40,42 +48,106 @@ METRIC = "synth+adjoint s @ lmax4096 spin2 ~50M pts: FP32 eps1e-5 vs FP64 eps1e-
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 HBM_PEAK_GBS = 8000.0
 CALIB_BYTES = 1 << 30            # plain copy used to calibrate the HBM byte counters
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_legendre_synth_pollens_thin6144.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_10431_amd", "csrc", f)
-                  for f in ("legendre_kernels.hip", "legendre_device.hpp")]
-
-
-def measured_traffic(workload):
-    """HBM bytes per launch of the Legendre synthesis from the committed counter
-    runs, or None if they were taken on another workload or on a different version
-    of the kernel source."""
-    import hashlib
-    try:
-        rec = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel_source_sha256") != sha or rec.get("workload", "").split()[0] != workload:
-        return None
-    return rec.get("bytes_per_launch")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_%s.json")
+CSRC = os.path.join(ROOT, "paper_2304_10431_amd", "csrc")
+# sources that define each stage's kernels (a traffic record holds only for them)
+STAGE_SOURCES = {
+    "legendre_synth": ["legendre_kernels.hip", "legendre_device.hpp"],
+    "legendre_adj": ["legendre_kernels.hip", "legendre_device.hpp"],
+    "spread": ["nufft.hip"],
+    "interp": ["nufft.hip"],
+    "column_fwd": ["colfft.hip"],
+    "column_adj": ["colfft.hip"],
+}
+HEADLINE = "f64_eps1e-10"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def legendre_flops(lmax, mmax, spin, npairs):
+def sources_sha(stage):
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES[stage]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form, stage):
+    """HBM bytes per call of a stage (summed over its launches) from the committed
+    counter runs, or None if they were taken on another workload or form, or on a
+    different version of the stage's kernel sources."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE % workload))[form][stage]
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("kernel_source_sha256") != sources_sha(stage):
+        return None
+    return rec.get("bytes_per_call")
+
+
+def legendre_flops(lmax, mmax, spin):
     """Algorithmic FP64 flops of one Legendre launch: per (l, m, ring pair) unit,
     8 flop for spin 0 (2 FMA recurrence + 2 FMA accumulation) and 24 flop for
     spin > 0 (2 recurrences + 4 complex-by-real accumulations), over
-    max(m, s) <= l <= lmax, 0 <= m <= mmax."""
+    max(m, s) <= l <= lmax, 0 <= m <= mmax and the (lmax + 2) / 2 ring pairs of the
+    smallest ring grid that is exact (lmax + 2 rings)."""
     units = 0
     for m in range(mmax + 1):
         l0 = max(m, spin)
         if l0 <= lmax:
             units += lmax - l0 + 1
     per = 8 if spin == 0 else 24
-    return per * units * npairs
+    return per * units * ((lmax + 3) // 2)
+
+
+def stage_bytes(stage, info, npts, ncomp, prec):
+    """Algorithmic HBM bytes of one call of an HBM-bound stage.
+    spread: per point its sorted FP64 (theta, phi) (16 B), 4 B permutation entry and
+    ncomp map values, plus one read and one write of every kept grid cell, times the
+    patch halo factor ((T + w - 1) / T)^2.  interp: the same with one read of the grid.
+    column_fwd: the doubled columns read once (ncol x nd complex) and the kept rows of
+    the oversampled columns written once (ncol x nrows complex); column_adj: the
+    reverse."""
+    rs = 8 if prec == "f64" else 4
+    cs = 2 * rs
+    w, t1, t2 = info["w"], info["tile1"], info["tile2"]
+    halo = (t1 + w - 1) * (t2 + w - 1) / float(t1 * t2)
+    grid = info["nrows"] * info["n2"] * ncomp * rs
+    pts = npts * (16 + 4 + ncomp * rs)
+    ncol = 2 * info["mmax"] + 1 if ncomp == 2 else info["mmax"] + 1
+    if stage == "spread":
+        return pts + 2 * grid * halo
+    if stage == "interp":
+        return pts + grid * halo
+    if stage in ("column_fwd", "column_adj"):
+        return ncol * (info["ndouble"] + info["nrows"]) * cs
+    return None
+
+
+def roofline_entry(stage, form_key, r, spec, npts, workload):
+    info, st = r["info"], r["stages"]
+    ms, cnt = st[stage]
+    if not cnt:
+        return None
+    avg_s = ms / cnt / 1e3
+    ncomp = 2 if spec["spin"] else 1
+    if stage.startswith("legendre"):
+        flops = legendre_flops(spec["lmax"], spec["mmax"], spec["spin"])
+        ach = flops / avg_s / 1e12
+        e = {"kernel": stage, "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flops_per_launch": flops}
+    else:
+        nb = stage_bytes(stage, info, npts, ncomp, form_key[:3])
+        if nb is None:
+            return None
+        ach = nb / avg_s / 1e9
+        e = {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "bytes_per_launch": nb}
+    e["avg_launch_ms"] = avg_s * 1e3
+    e["traffic"] = measured_traffic(workload, form_key, stage)
+    return e
 
 
 def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, autotune=False,
@@ -95,9 +167,8 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
         plan.synth(a, out=m)
         plan.adjoint(m, out=b)
     torch.cuda.synchronize()
-    plan.set_profiling(True)
-    # the library launches on torch's current stream, so events recorded there
-    # bracket exactly one synthesis and one adjoint
+    # timed steps, library profiling off; the library launches on torch's current
+    # stream, so events recorded there bracket exactly one synthesis and one adjoint
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -111,12 +182,22 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
     dt = (time.perf_counter() - t0) / steps
     syn_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    # per-stage times: a separate pass of the same steps with the library's events on
+    plan.set_profiling(True)
+    for _ in range(steps):
+        plan.synth(a, out=m)
+        plan.adjoint(m, out=b)
+    torch.cuda.synchronize()
     stages = plan.stage_times()
     plan.set_profiling(False)
     info = plan.info()
     r = dict(s_per_step=dt, synth_ms=syn_ms, adjoint_ms=adj_ms, plan_s=t_plan, stages=stages,
              info=info)
-    if spec["spin"] > 0:
+    if check is not None:
+        r["check_synth"] = m[:, check["idx"]].double().cpu().numpy()
+        rdt = torch.float64 if prec == "f64" else torch.float32
+        r["check_adjoint"] = plan.adjoint(check["yfull"].to(rdt)).to(torch.complex128).cpu().numpy()
+    if spin > 0:
         # the gradient-only setting (C = 0): same plan, same step count
         g = a[:1].contiguous()
         bg = plan.adjoint_grad(m)
@@ -133,158 +214,258 @@ def time_form(gsht, torch, th, ph, alm, spec, prec, eps, steps, warmup, many=0, 
         r["gradient_only"] = {
             "synth_ms": sum(e[0].elapsed_time(e[1]) for e in evg) / steps,
             "adjoint_ms": sum(e[1].elapsed_time(e[2]) for e in evg) / steps}
-        m = plan.synth(a, out=m)
+        del g, bg
+    del m, b
     if many > 1:
-        # several maps on the same plan: FP32 plans take groups of 8..16 maps through the
-        # matrix-core Legendre step, smaller groups (and FP64) through the FP64 group kernel
-        am = a.unsqueeze(0).repeat(many, 1, 1).contiguous()
-        am *= torch.linspace(0.5, 2.0, many, device=am.device).to(am.dtype)[:, None, None]
-        mm = plan.synth_many(am)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            plan.synth_many(am, out=mm)
-        e1.record()
-        torch.cuda.synchronize()
-        r["synth_many"] = {"maps": many, "synth_ms_per_map": e0.elapsed_time(e1) / steps / many,
-                           "legendre": "mfma" if (prec == "f32" and many >= 8) else "fp64"}
-        plan.set_profiling(True)
+        r.update(time_many(plan, torch, a, prec, steps, many, check))
+    return plan, r
+
+
+def time_many(plan, torch, a, prec, steps, many, check):
+    """Several maps on the same plan: FP32 plans take groups of 8..16 maps through the
+    matrix-core Legendre step, smaller groups (and FP64) through the FP64 group kernel."""
+    out = {}
+    fac = torch.linspace(0.5, 2.0, many, device=a.device)
+    am = (a.unsqueeze(0) * fac.to(a.dtype)[:, None, None]).contiguous()
+    mm = plan.synth_many(am)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
         plan.synth_many(am, out=mm)
-        st = plan.stage_times()
-        plan.set_profiling(False)
-        r["synth_many"]["legendre_ms_per_map"] = st["legendre_synth"][0] / many
-        r["synth_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
-        # accuracy of the last map against its own single-map synthesis
-        one = plan.synth(am[many - 1].contiguous())
-        r["synth_many"]["eps_vs_single"] = float(torch.linalg.norm((mm[many - 1] - one).double())
-                                                 / torch.linalg.norm(one.double()))
-        del am, one
-        fac = torch.linspace(0.5, 2.0, many, device=mm.device)
-        if check is not None:
-            # the last map's values on the oracle's sample points, undone the scaling
-            r["many_check"] = {"synth": (mm[many - 1][:, check["idx"]] / fac[-1]).double().cpu().numpy()}
-        # adjoint of the same maps (matrix-core Legendre step for 8..16 FP32 maps)
-        bm = plan.adjoint_many(mm)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(steps):
-            plan.adjoint_many(mm, out=bm)
-        e1.record()
-        torch.cuda.synchronize()
-        r["adjoint_many"] = {"maps": many, "adjoint_ms_per_map": e0.elapsed_time(e1) / steps / many,
-                             "legendre": "mfma" if (prec == "f32" and many >= 8) else "fp64"}
-        plan.set_profiling(True)
+    e1.record()
+    torch.cuda.synchronize()
+    kind = "mfma" if (prec == "f32" and many >= 8) else "fp64"
+    out["synth_many"] = {"maps": many, "synth_ms_per_map": e0.elapsed_time(e1) / steps / many,
+                         "legendre": kind}
+    plan.set_profiling(True)
+    plan.synth_many(am, out=mm)
+    st = plan.stage_times()
+    plan.set_profiling(False)
+    out["synth_many"]["legendre_ms_per_map"] = st["legendre_synth"][0] / many
+    out["synth_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
+    one = plan.synth(am[many - 1].contiguous())
+    out["synth_many"]["eps_vs_single"] = float(torch.linalg.norm((mm[many - 1] - one).double())
+                                               / torch.linalg.norm(one.double()))
+    del am, one
+    if check is not None:
+        out["many_check"] = {"synth": (mm[many - 1][:, check["idx"]] / fac[-1]).double().cpu().numpy()}
+    bm = plan.adjoint_many(mm)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
         plan.adjoint_many(mm, out=bm)
-        st = plan.stage_times()
-        plan.set_profiling(False)
-        r["adjoint_many"]["legendre_ms_per_map"] = st["legendre_adj"][0] / many
-        r["adjoint_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
-        one = plan.adjoint(mm[many - 1].contiguous())
-        r["adjoint_many"]["eps_vs_single"] = float(
-            torch.linalg.norm((bm[many - 1] - one).to(torch.complex128))
-            / torch.linalg.norm(one.to(torch.complex128)))
-        del bm, one
-        if check is not None:
-            # adjoint of scaled copies of the oracle's sampled input
-            ym = (check["yfull"].to(mm.dtype).unsqueeze(0) * fac[:, None, None]).contiguous()
-            bmy = plan.adjoint_many(ym)
-            r["many_check"]["adjoint"] = (bmy[many - 1] / fac[-1]).to(torch.complex128).cpu().numpy()
-            del ym, bmy
-        del mm
-    return plan, m, r
+    e1.record()
+    torch.cuda.synchronize()
+    out["adjoint_many"] = {"maps": many, "adjoint_ms_per_map": e0.elapsed_time(e1) / steps / many,
+                           "legendre": kind}
+    plan.set_profiling(True)
+    plan.adjoint_many(mm, out=bm)
+    st = plan.stage_times()
+    plan.set_profiling(False)
+    out["adjoint_many"]["legendre_ms_per_map"] = st["legendre_adj"][0] / many
+    out["adjoint_many"]["prep_ms_per_map"] = st["prep_alm"][0] / many
+    one = plan.adjoint(mm[many - 1].contiguous())
+    out["adjoint_many"]["eps_vs_single"] = float(
+        torch.linalg.norm((bm[many - 1] - one).to(torch.complex128))
+        / torch.linalg.norm(one.to(torch.complex128)))
+    del bm, one
+    if check is not None:
+        ym = (check["yfull"].to(mm.dtype).unsqueeze(0) * fac[:, None, None]).contiguous()
+        bmy = plan.adjoint_many(ym)
+        out["many_check"]["adjoint"] = (bmy[many - 1] / fac[-1]).to(torch.complex128).cpu().numpy()
+        del ym, bmy
+    del mm
+    return out
 
 
-def spreading_figures(info, stages, npts, ncomp, prec):
-    """Spreading (type-1 NUFFT) throughput.  Algorithmic HBM bytes per launch:
-    per point its sorted FP64 (theta, phi) (16 B), its 4 B permutation entry and its
-    ncomp map values; per grid cell one read and one write of the grid value (complex
-    for spin > 0, real for spin 0), times the halo factor ((T + w - 1) / T)^2 of a
-    tile's patch.  LDS integer atomics: w^2 taps x ncomp per point."""
-    rs = 8 if prec == "f64" else 4
-    w, t1, t2 = info["w"], info["tile1"], info["tile2"]
-    halo = (t1 + w - 1) * (t2 + w - 1) / float(t1 * t2)
-    grid = info["nrows"] * info["n2"] * ncomp * rs
-    nbytes = npts * (16 + 4 + ncomp * rs) + 2 * grid * halo
-    ms, cnt = stages["spread"]
-    avg_s = ms / max(cnt, 1) / 1e3
-    atomics = npts * w * w * ncomp
-    return {"kernel": "spread", "bound": "hbm", "achieved": nbytes / avg_s / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / avg_s / 1e9 / HBM_PEAK_GBS,
-            "bytes_per_launch": nbytes, "avg_launch_ms": avg_s * 1e3,
-            "lds_atomics_per_launch": atomics, "lds_atomic_gops": atomics / avg_s / 1e9}
+def load_samples(workload):
+    """The committed oracle values at 10^4 sampled points of the workload (written by
+    tests/golden/make_fullsize_samples.py), or None."""
+    path = os.path.join(GOLDEN, "%s_samples.npz" % workload)
+    if not os.path.exists(path):
+        return None
+    with np.load(path) as f:
+        return {k: f[k] for k in ("idx", "theta", "phi", "synth")}
 
 
-def sample_points(npts, nsample, ncomp):
-    """The bounded sample the oracle is timed on: sorted random point indices and an
-    adjoint input supported on them."""
-    rng = np.random.default_rng(12345)
-    idx = np.sort(rng.choice(npts, nsample, replace=False))
-    y = np.random.default_rng(7).standard_normal((ncomp, nsample))
-    return idx, y
+def adjoint_columns(mmax, seed=17):
+    rng = np.random.default_rng(seed)
+    mid = rng.choice(np.arange(4, mmax), 20, replace=False)
+    return np.concatenate([[0, 1, 2, 3], np.sort(mid), [mmax]]).astype(np.int32)
 
 
-def cpu_baseline(spec, th_h, ph_h, alm_h, idx, y, m_gpu_h, adj_gpu_h, many_checks=None):
-    """Oracle (FP64 direct sum, all host cores) on a bounded random sample of the
-    workload's points, scaled linearly to the full point count.  Also returns the
-    GPU forms' effective accuracy against it: synthesis on the sampled points, and the
-    adjoint of an input supported on them (w_m-weighted over a_lm)."""
+def accuracy_and_cpu_baseline(spec, alm_h, fx, sup, y_s, results, time_sample):
+    """Each form's effective accuracy against the oracle (synthesis at the 10^4 sampled
+    points; adjoint of an input supported on 5000 of them, on 25 columns m), and the
+    oracle (FP64 direct sum, all host cores) timed on a bounded sample of the points:
+    synthesis and full adjoint on time_sample points, scaled linearly to the workload."""
     import oracle
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
-    nsample = idx.size
     cores = len(os.sched_getaffinity(0))
+    th_s, ph_s = fx["theta"][sup], fx["phi"][sup]
+    ms = adjoint_columns(mmax)
+    ref_adj = oracle.adjoint_cols(y_s, lmax, mmax, spin, th_s, ph_s, ms, nthreads=cores)
+    sel = np.zeros(oracle.nalm(lmax, mmax), bool)
+    for m in ms:
+        i0 = oracle.alm_index(m, m, lmax)
+        sel[i0:i0 + lmax + 1 - m] = True
+    wts = np.sqrt(oracle.alm_weights(lmax, mmax))[sel][None, :]
+    err = {}
+    for k, r in results.items():
+        err[k] = {"synthesis": oracle.eps_eff(r["check_synth"], fx["synth"]),
+                  "adjoint": oracle.eps_eff(wts * r["check_adjoint"][:, sel], wts * ref_adj[:, sel])}
+        mc = r.get("many_check")
+        if mc:
+            err[k]["synthesis_many"] = oracle.eps_eff(mc["synth"], fx["synth"])
+            err[k]["adjoint_many"] = oracle.eps_eff(wts * mc["adjoint"][:, sel], wts * ref_adj[:, sel])
+    # timing sample: spread over the three groups
+    pick = np.random.default_rng(12345).choice(fx["idx"].size, time_sample, replace=False)
+    th_t, ph_t = fx["theta"][pick], fx["phi"][pick]
     t0 = time.time()
-    ref = oracle.synth(alm_h, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
+    oracle.synth(alm_h, lmax, mmax, spin, th_t, ph_t, nthreads=cores)
     t_syn = time.time() - t0
+    log("oracle synthesis on %d points: %.1f s" % (time_sample, t_syn))
+    y_t = np.random.default_rng(7).standard_normal((2 if spin else 1, time_sample))
     t0 = time.time()
-    ref_adj = oracle.adjoint(y, lmax, mmax, spin, th_h[idx], ph_h[idx], nthreads=cores)
+    oracle.adjoint(y_t, lmax, mmax, spin, th_t, ph_t, nthreads=cores)
     t_adj = time.time() - t0
-    npts = th_h.size
-    per_step = (t_syn + t_adj) * npts / nsample
-    wts = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
-    err = {k: {"synthesis": oracle.eps_eff(v[:, idx], ref),
-               "adjoint": oracle.eps_eff(wts * adj_gpu_h[k], wts * ref_adj)}
-           for k, v in m_gpu_h.items()}
-    for k, mc in (many_checks or {}).items():
-        # several-map paths: the last map of the group against the same oracle values
-        if "synth" in mc:
-            err[k]["synthesis_many"] = oracle.eps_eff(mc["synth"], ref)
-        if "adjoint" in mc:
-            err[k]["adjoint_many"] = oracle.eps_eff(wts * mc["adjoint"], wts * ref_adj)
-    return dict(value=per_step, unit="s", cores=cores, kind="oracle",
-                sample="%d random points of the %d-point workload: synthesis %.1f s + adjoint "
-                       "%.1f s on %d threads, scaled linearly to all points" %
-                       (nsample, npts, t_syn, t_adj, cores)), err
+    log("oracle adjoint on %d points: %.1f s" % (time_sample, t_adj))
+    npts = spec["npts_total"]
+    per_step = (t_syn + t_adj) * npts / time_sample
+    cb = dict(value=per_step, unit="s", cores=cores, kind="oracle",
+              sample="%d of the sampled points of the %d-point workload: synthesis %.1f s + "
+                     "adjoint %.1f s on %d threads, scaled linearly to all points"
+                     % (time_sample, npts, t_syn, t_adj, cores))
+    return cb, err
 
 
-def cpu_nufft_baseline(spec, th_h, ph_h, alm_h, eps):
-    """The plain CPU NUFFT-based SHT (FP64, all host cores), one synthesis and one
-    adjoint at the full workload, with its own parameter choice for eps."""
+def cpu_nufft_baseline(eps=1e-10):
+    """The plain CPU NUFFT-based SHT of the oracle package (FP64, all host cores), one
+    synthesis and one adjoint at lmax 2048, spin 0, on the 2049 x 4097 Gauss-Legendre
+    grid deflected by the workload's potential (deflection computed by the same CPU
+    code, untimed), with its own parameter choice for eps."""
+    import oracle
+    from oracle import lensing as ol
     from oracle import nufft_sht
+    from paper_2304_10431_amd import workloads as wl
+    spec = wl.WORKLOADS["tlens_l2048"]
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
-    p = nufft_sht.default_params(lmax, mmax, eps)
     cores = len(os.sched_getaffinity(0))
+    th0, ph0 = wl.base_points(spec)
+    g = np.zeros((2, oracle.nalm(lmax, lmax)), dtype=np.complex128)
+    g[0] = wl.make_potential(spec)
     t0 = time.time()
-    m = nufft_sht.synth(alm_h, lmax, mmax, spin, th_h, ph_h, nthreads=cores, **p)
+    alpha = nufft_sht.synth(ol.lscale(g, lmax, lmax), lmax, lmax, 1, th0, ph0, nthreads=cores,
+                            **nufft_sht.default_params(lmax, lmax, 1e-12))
+    th, ph, _ = ol.deflect(th0, ph0, alpha)
+    del alpha, th0, ph0
+    log("cpu nufft: deflected %d points (%.1f s, untimed)" % (th.size, time.time() - t0))
+    alm_h = wl.make_alm(spec)
+    p = nufft_sht.default_params(lmax, mmax, eps)
+    t0 = time.time()
+    m = nufft_sht.synth(alm_h, lmax, mmax, spin, th, ph, nthreads=cores, **p)
     t_syn = time.time() - t0
     log("cpu nufft synthesis %.1f s" % t_syn)
     t0 = time.time()
-    nufft_sht.adjoint(m, lmax, mmax, spin, th_h, ph_h, nthreads=cores, **p)
+    nufft_sht.adjoint(m, lmax, mmax, spin, th, ph, nthreads=cores, **p)
     t_adj = time.time() - t0
     log("cpu nufft adjoint %.1f s" % t_adj)
     return dict(value=t_syn + t_adj, unit="s", cores=cores, kind="oracle (plain CPU NUFFT SHT)",
-                eps=eps, params=p,
+                eps=eps, params=p, workload="tlens_l2048: spin 0, lmax 2048, %d deflected "
+                "Gauss-Legendre points" % th.size,
                 sample="whole workload, one synthesis (%.1f s) + one adjoint (%.1f s), FP64"
                        % (t_syn, t_adj))
 
 
+def batched(gsht, torch, steps, warmup, nstreams=4):
+    """The batched uneven workload, FP32 at eps 1e-5 on plans that pick their
+    oversampling by timing: (a) 64 independent instances, synthesis + adjoint of all of
+    them as one captured graph over worker streams; (b) 4 geometries x 16 maps through
+    the several-map calls (matrix-core Legendre step)."""
+    from paper_2304_10431_amd import workloads as wl
+    out = {}
+    specs = wl.batched_instances()
+    t0 = time.time()
+    plans, alms, maps, adjs = [], [], [], []
+    for k, s in enumerate(specs):
+        th, ph = wl.instance_points(s)
+        plans.append(gsht.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), s["lmax"],
+                               s["mmax"], s["spin"], 1e-5, "f32", sigma="tuned"))
+        alms.append(torch.from_numpy(wl.instance_alm(s, s["alm_seed"])).cuda().to(torch.complex64))
+        if k % 16 == 15:
+            log("batch: %d plans (%.0f s)" % (k + 1, time.time() - t0))
+    torch.cuda.synchronize()
+    t_plans = time.time() - t0
+    batch = gsht.Batch(nstreams)
+    maps = batch.synth(plans, alms)
+    adjs = batch.adjoint(plans, maps)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.synth(plans, alms, maps)
+        batch.adjoint(plans, maps, adjs)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    out["instances_graph"] = {
+        "instances": len(specs), "points": int(sum(s["npts"] for s in specs)),
+        "ms_per_step": e0.elapsed_time(e1) / steps, "streams": nstreams, "plans_s": t_plans,
+        "sigma": sorted({p.info()["sigma"] for p in plans})}
+    log("batch: 64 instances, %.1f ms per synthesis + adjoint (graph)"
+        % out["instances_graph"]["ms_per_step"])
+    del graph
+    batch.close()
+    for p in plans:
+        p.close()
+    del plans, alms, maps, adjs
+    torch.cuda.empty_cache()
+    groups = wl.batched_groups()
+    tot, t_plans = 0.0, 0.0
+    for g in groups:
+        th, ph = wl.instance_points(g)
+        t0 = time.time()
+        plan = gsht.Plan(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(), g["lmax"],
+                         g["mmax"], g["spin"], 1e-5, "f32", sigma="tuned")
+        t_plans += time.time() - t0
+        am = torch.from_numpy(np.stack([wl.instance_alm(g, sd) for sd in g["alm_seeds"]])).cuda()
+        am = am.to(torch.complex64)
+        mm = plan.synth_many(am)
+        bm = plan.adjoint_many(mm)
+        for _ in range(warmup):
+            plan.synth_many(am, out=mm)
+            plan.adjoint_many(mm, out=bm)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            plan.synth_many(am, out=mm)
+            plan.adjoint_many(mm, out=bm)
+        e1.record()
+        torch.cuda.synchronize()
+        tot += e0.elapsed_time(e1) / steps
+        plan.close()
+        del am, mm, bm
+        torch.cuda.empty_cache()
+    out["groups_many"] = {"groups": len(groups), "maps": sum(len(g["alm_seeds"]) for g in groups),
+                          "ms_per_step": tot, "plans_s": t_plans,
+                          "shapes": [[g["lmax"], g["spin"], g["npts"]] for g in groups]}
+    log("batch: 4 x 16 maps, %.1f ms per synthesis + adjoint" % tot)
+    return out
+
+
 def point_desc(spec):
     if spec["points"] == "thin":
-        return ("%d-ring longitude-thinned Gauss-Legendre grid, 2.5 arcmin rms deflection"
-                % spec["nring"])
+        return ("%d-ring longitude-thinned Gauss-Legendre grid deflected by a 2.5 arcmin rms "
+                "Gaussian lensing potential" % spec["nring"])
     if spec["points"] == "gl":
-        return ("%d x %d Gauss-Legendre grid, 2.5 arcmin rms deflection"
-                % (spec["nring"], spec["nphi"]))
+        return ("%d x %d Gauss-Legendre grid deflected by a 2.5 arcmin rms Gaussian lensing "
+                "potential" % (spec["nring"], spec["nphi"]))
     return "uniform random points"
 
 
@@ -295,15 +476,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="pollens_thin6144")
     ap.add_argument("--cpu-sample", type=int, default=2048)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-cpu-nufft", action="store_true",
+                    help="skip the plain CPU NUFFT-based SHT baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven workload")
     ap.add_argument("--autotune", action="store_true",
                     help="let each plan time the Legendre launch shapes and keep the fastest")
     ap.add_argument("--many", type=int, default=16,
-                    help="maps per call for the several-map synthesis timing (FP32 form; 0: off)")
-    ap.add_argument("--cpu-nufft", action="store_true",
-                    help="also time the plain CPU NUFFT-based SHT on the whole workload "
-                         "(FP64, eps 1e-10; minutes at lmax 2048)")
-    ap.add_argument("--no-f64", action="store_true")
+                    help="maps per call for the several-map timing (FP32 form; 0: off)")
+    ap.add_argument("--forms", default="f64:1e-10,f32:1e-5,f64:1e-5",
+                    help="comma-separated precision:epsilon forms (the headline is f64:1e-10)")
     ap.add_argument("--sigma", default="tuned",
                     help="oversampling factor of the plans: tuned (gsht_plan_create_tuned picks "
                          "the fastest of 2, 1.5, 1.25 at plan time) or one of 2, 1.5, 1.25")
@@ -319,9 +501,11 @@ def main():
     import torch
     from paper_2304_10431_amd import gsht
     from paper_2304_10431_amd import workloads as wl
+    from paper_2304_10431_amd.lensing import deflected_points
 
-    spec = wl.WORKLOADS[args.workload]
+    spec = dict(wl.WORKLOADS[args.workload])
     lmax, mmax, spin = spec["lmax"], spec["mmax"], spec["spin"]
+    ncomp = 2 if spin else 1
     if args.copy_calib:
         src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -330,63 +514,69 @@ def main():
         del src, dst
     t0 = time.time()
     log("generating %s points" % args.workload)
-    if spec["points"] == "thin":
-        th0, ph0 = wl.thinned_gl_grid(spec["nring"])
-    elif spec["points"] == "gl":
-        th0, ph0, _ = wl.gl_grid(spec["nring"], spec["nphi"])
-    else:
-        th0, ph0 = wl.uniform_sphere(spec["npts"], np.random.default_rng(wl.seed_for(spec["id"])))
+    th0, ph0 = wl.base_points(spec)
     th = torch.from_numpy(th0).cuda()
     ph = torch.from_numpy(ph0).cuda()
     del th0, ph0
     if spec["points"] != "uniform":
-        th, ph = wl.deflect(th, ph, wl.seed_for(spec["id"]) + 500)
+        plm = torch.from_numpy(wl.make_potential(spec)).cuda()
+        th, ph = deflected_points(th, ph, plm, lmax)
+        del plm
+    fx = None if args.no_cpu else load_samples(args.workload)
+    chk, sup, y_s = None, None, None
+    if fx is not None:
+        # the 10^4 sampled points take the oracle's deflected coordinates (within 1e-14
+        # of the library's), so that both sides evaluate the same points
+        idx = torch.from_numpy(fx["idx"]).cuda()
+        th[idx] = torch.from_numpy(fx["theta"]).cuda()
+        ph[idx] = torch.from_numpy(fx["phi"]).cuda()
+        sup = wl.adjoint_support()
+        y_s = wl.adjoint_check_input(ncomp, sup.size, 9)
+        yfull = torch.zeros((ncomp, th.numel()), dtype=torch.float64, device="cuda")
+        yfull[:, idx[torch.from_numpy(sup).cuda()]] = torch.from_numpy(y_s).cuda()
+        chk = {"idx": idx, "yfull": yfull}
     alm_h = wl.make_alm(spec)
     alm = torch.from_numpy(alm_h).cuda()
     torch.cuda.synchronize()
     npts = th.numel()
+    spec["npts_total"] = npts
     log("inputs ready: %d points, %.1f s" % (npts, time.time() - t0))
 
-    ncomp = 2 if spin else 1
-    if not args.no_cpu:
-        idx, ysam = sample_points(npts, args.cpu_sample, ncomp)
-        yfull = torch.zeros((ncomp, npts), dtype=torch.float64, device="cuda")
-        yfull[:, torch.from_numpy(idx).cuda()] = torch.from_numpy(ysam).cuda()
-    adj_maps = {}
-    forms = [("f32", 1e-5)]
-    if not args.no_f64:
-        forms += [("f64", 1e-5), ("f64", 1e-10)]
+    forms = []
+    for f in args.forms.split(","):
+        p, e = f.split(":")
+        forms.append((p, float(e)))
     results = {}
-    maps = {}
     for prec, eps in forms:
-        log("timing %s eps %.0e" % (prec, eps))
-        chk = None if args.no_cpu else {"idx": torch.from_numpy(idx).cuda(), "yfull": yfull}
-        plan, m, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
-                               many=args.many if prec == "f32" else 0, autotune=args.autotune,
-                               check=chk,
-                               sigma=args.sigma if args.sigma == "tuned" else float(args.sigma))
         key = "%s_eps%.0e" % (prec, eps)
+        log("timing %s" % key)
+        plan, r = time_form(gsht, torch, th, ph, alm, spec, prec, eps, args.steps, args.warmup,
+                            many=args.many if prec == "f32" else 0, autotune=args.autotune,
+                            check=chk,
+                            sigma=args.sigma if args.sigma == "tuned" else float(args.sigma))
         results[key] = r
-        maps[key] = m.detach().to(torch.float64).cpu().numpy()
-        if not args.no_cpu:
-            rdt = torch.float64 if prec == "f64" else torch.float32
-            adj_maps[key] = plan.adjoint(yfull.to(rdt)).to(torch.complex128).cpu().numpy()
         log("%s: %.2f ms/step (synthesis %.2f, adjoint %.2f; plan %.2f s)" %
             (key, 1e3 * r["s_per_step"], r["synth_ms"], r["adjoint_ms"], r["plan_s"]))
         plan.close()
-        del plan, m
+        del plan
         torch.cuda.empty_cache()
 
-    head = results["f32_eps1e-05"]
-    info = head["info"]
-    st = head["stages"]
-    leg_ms, leg_n = st["legendre_synth"]
-    leg_avg_s = leg_ms / max(leg_n, 1) / 1e3
-    flops = legendre_flops(lmax, mmax, spin, (info["ntheta"] + 1) // 2)
-    achieved = flops / leg_avg_s / 1e12
-    adj_ms, adj_n = st["legendre_adj"]
-    adj_avg_s = adj_ms / max(adj_n, 1) / 1e3
-
+    head_key = HEADLINE if HEADLINE in results else next(iter(results))
+    head = results[head_key]
+    # roofline of the main kernels of the headline form; the dominant one (longest
+    # stage) is the line's roofline
+    roofs = {}
+    for stage in STAGE_SOURCES:
+        e = roofline_entry(stage, head_key, head, spec, npts, args.workload)
+        if e is not None:
+            roofs[stage] = e
+    dom = max(roofs, key=lambda s: roofs[s]["avg_launch_ms"])
+    roof = dict(roofs[dom])
+    roof["form"] = head_key
+    roof["others"] = {s: {"frac": v["frac"], "bound": v["bound"], "avg_launch_ms": v["avg_launch_ms"],
+                          "traffic": v["traffic"]}
+                      for s, v in roofs.items() if s != dom}
+    f32 = results.get("f32_eps1e-05")
     out = {
         "metric": METRIC,
         "value": head["s_per_step"],
@@ -398,51 +588,58 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FFT/NUFFT), f64 Legendre",
+        "dtype": "f64" if head_key.startswith("f64") else "f32 (FFT/NUFFT), f64 Legendre",
         "data": "synthetic",
-        "config": {"workload": "%s: spin %d, lmax=mmax=%d, %d points (%s), FP32 eps 1e-5"
-                               % (args.workload, spin, lmax, npts, point_desc(spec)),
+        "config": {"workload": "%s: spin %d, lmax=mmax=%d, %d points (%s), %s"
+                               % (args.workload, spin, lmax, npts, point_desc(spec),
+                                  head_key.replace("_", " ")),
                    "npts": npts, "lmax": lmax, "mmax": mmax, "spin": spin},
+        "f32_eps1e-5_s": f32["s_per_step"] if f32 else None,
         "forms": {k: {"s_per_step": v["s_per_step"], "synth_ms": v["synth_ms"],
                       "adjoint_ms": v["adjoint_ms"], "plan_s": v["plan_s"],
                       "sigma": v["info"]["sigma"],
                       "w": v["info"]["w"], "n1": v["info"]["n1"], "n2": v["info"]["n2"],
-                      "column_mode": v["info"]["column_mode"],
+                      "column_mode": v["info"]["column_mode"], "tile": v["info"]["tile1"],
                       "legendre_shapes": [v["info"]["syn_r"], v["info"]["adj_r"], v["info"]["adj_b"]],
                       "gradient_only_ms": v.get("gradient_only"),
                       "synth_many": v.get("synth_many"),
                       "adjoint_many": v.get("adjoint_many"),
                       "stage_ms": {n: (t / c if c else None) for n, (t, c) in v["stages"].items()}}
                   for k, v in results.items()},
-        "roofline": {"kernel": "legendre_synth", "bound": "alu",
-                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
-                     "flops_per_launch": flops, "avg_launch_ms": leg_avg_s * 1e3,
-                     "legendre_adj_frac": flops / adj_avg_s / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
+        "roofline": roof,
     }
-    out["spreading"] = {k: spreading_figures(v["info"], v["stages"], npts, ncomp, k[:3])
-                        for k, v in results.items()}
-    if "f64_eps1e-05" in results:
-        out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / head["s_per_step"]
-        sm, am_ = head.get("synth_many"), head.get("adjoint_many")
+    out["spreading"] = {}
+    for k, v in results.items():
+        e = roofline_entry("spread", k, v, spec, npts, args.workload)
+        if e is not None:
+            w = v["info"]["w"]
+            atomics = npts * w * w * ncomp
+            e["lds_atomics_per_launch"] = atomics
+            e["lds_atomic_gops"] = atomics / (e["avg_launch_ms"] / 1e3) / 1e9
+            out["spreading"][k] = e
+    if "f64_eps1e-05" in results and f32:
+        out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / f32["s_per_step"]
+        sm, am_ = f32.get("synth_many"), f32.get("adjoint_many")
         if sm and am_ and sm.get("legendre") == "mfma":
             # per map: FP32 form with the matrix-core Legendre step (16-map groups) against
             # the plain FP64 form, synthesis + adjoint
             out["speedup_f32_mfma_many_vs_f64_eps1e-5"] = (
                 results["f64_eps1e-05"]["s_per_step"] * 1e3
                 / (sm["synth_ms_per_map"] + am_["adjoint_ms_per_map"]))
-    if "f64_eps1e-10" in results:
-        out["f64_eps1e-10_s"] = results["f64_eps1e-10"]["s_per_step"]
-    if not args.no_cpu:
-        th_h = th.cpu().numpy()
-        ph_h = ph.cpu().numpy()
-        mchk = {k: v.pop("many_check") for k, v in results.items() if "many_check" in v}
-        cb, err = cpu_baseline(spec, th_h, ph_h, alm_h, idx, ysam, maps, adj_maps, mchk)
+    del th, ph, alm
+    if chk is not None:
+        del chk
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        log("batched uneven workload")
+        out["batched"] = batched(gsht, torch, max(1, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+    if fx is not None:
+        cb, err = accuracy_and_cpu_baseline(spec, alm_h, fx, sup, y_s, results, args.cpu_sample)
         out["cpu_baseline"] = cb
         out["eps_eff_on_sample"] = err
-    if args.cpu_nufft:
-        out["cpu_nufft_baseline"] = cpu_nufft_baseline(spec, th.cpu().numpy(), ph.cpu().numpy(),
-                                                       alm_h, 1e-10)
+    if not args.no_cpu_nufft:
+        out["cpu_nufft_baseline"] = cpu_nufft_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -144,14 +144,19 @@ int gsht_plan_create_sigma(gsht_plan **p, int lmax, int mmax, int spin, const do
                            double sigma, void *hip_stream);
 
 /*
- * Plan whose sigma is picked by measurement: builds the plan at every sigma of
- * gsht_plan_create_sigma that reaches epsilon, times one synthesis + adjoint of each
- * on these points (best of two after a warm-up; zero inputs, since the work does
- * not depend on the values), keeps the fastest and frees the rest.  Holds at most two
- * plans plus one coefficient and one map buffer at a time; a candidate that does not
- * fit is skipped (the sigma = 2 plan must build).  Takes a few transforms' time and,
- * in a new process, the FFT library's set-up for each new length.
- * gsht_plan_get_info reports the sigma chosen.
+ * Plan whose oversampling factor sigma and grid tile edge are picked by measurement:
+ * builds the plan at every sigma of gsht_plan_create_sigma that reaches epsilon, with
+ * tiles of 32, 48 and 64 cells (those whose spreading and interpolation patches fit
+ * a workgroup's LDS), times one synthesis + adjoint of each on these points (best of
+ * two after a warm-up; zero coefficients and a constant map, since the work does not
+ * depend on the values as long as the map is not zero), keeps the fastest and frees
+ * the rest.  Holds at most two plans plus one coefficient and one map buffer at a
+ * time; a candidate that does not fit is skipped (the sigma = 2, 32-cell plan must
+ * build).  Takes a few transforms' time per candidate and, in a new process, the FFT
+ * library's set-up for each new length.  gsht_plan_get_info reports the sigma and
+ * tile chosen.  (The environment variable GSHT_TILE sets the tile edge of the other
+ * plan constructors, for experiments: 16..128 cells, at least w - 1, and a patch
+ * within the LDS, else GSHT_EINVAL.)
  */
 int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const double *theta,
                            const double *phi, int64_t npts, double epsilon, gsht_precision prec,
@@ -406,8 +411,6 @@ typedef struct {
                            workgroup per chunk with an atomic flush */
     int syn_r;          /* Legendre synthesis: slices of 64 ring pairs per wave */
     int adj_r, adj_b;   /* Legendre adjoint: slices per wave, degrees per reduction block */
-    int row_mode;       /* phi transforms of the grid rows: 1 = in-LDS kernels split by
-                           output parity (complex grids), 0 = library FFT */
     double sigma;       /* nominal oversampling factor (2, 1.5 or 1.25); n1 and n2 are
                            the FFT-friendly lengths at least about sigma (2 lmax + 1) and
                            sigma (2 mmax + 1) */

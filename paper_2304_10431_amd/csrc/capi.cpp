@@ -351,16 +351,10 @@ void choose_sizes(gsht_plan *p)
     p->nrows = p->n1 / 2 + p->w + 2;
     p->t1 = 32;
     p->t2 = 32;
-    if (const char *e = getenv("GSHT_TILE")) {  // tile edge in cells (testing and tuning)
-        const int t = atoi(e);
-        if (t >= 16 && t <= 128 && t >= p->w - 1)
-            p->t1 = p->t2 = t;
-    }
-    if (const char *e = getenv("GSHT_PATCH_PAD"))
-        p->patch_pad = std::max(0, std::min(16, atoi(e)));
-    p->spread_order = 1;
-    if (const char *e = getenv("GSHT_SPREAD_ORDER"))
-        p->spread_order = atoi(e) ? 1 : 0;
+    if (p->tile_req > 0)  // tile edge chosen by the caller (tuned plans) or GSHT_TILE
+        p->t1 = p->t2 = p->tile_req;
+    else if (const char *e = getenv("GSHT_TILE"))
+        p->t1 = p->t2 = atoi(e);
     p->nt1 = (p->nrows + p->t1 - 1) / p->t1;
     p->nt2 = (p->n2 + p->t2 - 1) / p->t2;
     p->ntiles = (int64_t)p->nt1 * p->nt2;
@@ -396,9 +390,6 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
         p->syn_r = r1;
         p->adj_r = r2;
         p->adj_b = b;
-        const char *ap = getenv("GSHT_ADJ_PAIR");
-        if (ap)
-            p->adj_pair = atoi(ap) != 0;
     }
     p->syn_nchunk = (p->npairs + 64 * p->syn_r - 1) / (64 * p->syn_r);
     p->adj_nchunk = (p->npairs + 64 * p->adj_r - 1) / (64 * p->adj_r);
@@ -562,45 +553,6 @@ int make_twist(gsht_plan *p, void **out, int n, hipStream_t s)
 // Default LDS padding shift of the in-LDS transforms.
 constexpr int kLdsPadShift = 4;
 
-// phi transforms of the grid rows in LDS (complex grids): n2 / 2 > mmax and both
-// n2 / 2 and the 2 mmax + 1 modes within the per-thread capacity of the split kernels.
-// GSHT_ROW_MODE (0, 1) forces a mode for testing.
-int setup_rows(gsht_plan *p, hipStream_t s)
-{
-    int dev = 0, maxsh = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lim = std::min((size_t)maxsh, COL_MAX_BYTES);
-    std::vector<int> rad;
-    const int nh = p->n2 / 2, cap = column_half_maxn(p->prec);
-    const bool fit = p->spin > 0 && p->n2 % 2 == 0 && nh > p->mmax && nh <= cap &&
-                     2 * p->mmax + 1 <= cap && row_lds_bytes(*p) <= lim && col_radices(nh, rad, col_maxr(p));
-    // The library FFT is the default: the in-LDS row kernels measured slower at lmax
-    // 4096 (FP32 1.04 vs 0.59 ms, FP64 2.2 vs 1.5 ms per direction).
-    int mode = 0;
-    if (const char *e = getenv("GSHT_ROW_MODE")) {
-        const int want = atoi(e);
-        if (want < 0 || want > 1 || (want == 1 && !fit))
-            return fail(GSHT_EINVAL, "GSHT_ROW_MODE=%s is not possible for this plan", e);
-        mode = want;
-    }
-    if (mode == 1 && row_set_lds(p->prec) != hipSuccess) {
-        (void)hipGetLastError();
-        mode = 0;
-    }
-    p->rowmode = mode;
-    if (mode == 0)
-        return GSHT_OK;
-    int rc;
-    if (p->colmode == 2 && p->n1 == p->n2) {
-        p->cf_p = p->cf_h;       // same length, same tables
-        p->twist2 = p->twist;
-        return GSHT_OK;
-    }
-    if ((rc = setup_colfft(p, p->cf_p, nh, s)) != GSHT_OK) return rc;
-    return make_twist(p, &p->twist2, p->n2, s);
-}
-
 // Per-column FFT stage: fuse as much as fits in one workgroup's LDS.  The
 // environment variable GSHT_COLUMN_MODE (0, 1, 2) forces a mode for testing.
 int setup_columns(gsht_plan *p, hipStream_t s)
@@ -699,7 +651,7 @@ struct PlanTrace {
 
 int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double *theta,
                      const double *phi, int64_t npts, double eps, int prec, hipStream_t s,
-                     int es_set = 0)
+                     int es_set = 0, int tile = 0)
 {
     PlanTrace tr(s);
     int rc;
@@ -712,6 +664,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     p->npts_cap = npts;
     p->eps = eps;
     p->prec = prec;
+    p->tile_req = tile;
     choose_sizes(p);
     if (p->w == 0) {
         const double sg = kEs[es_set].sigma;
@@ -719,6 +672,19 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
         return fail(GSHT_EUNSUPPORTED,
                     "epsilon %g is not reachable at oversampling %.2f with kernel supports up to %d",
                     eps, sg, prec == GSHT_F64 ? 16 : 8);
+    }
+    {
+        // tile edge: the colour-ordered spreading needs patches (tile + w - 1 cells) that
+        // reach at most one tile beyond their own, and each patch (16 bytes per cell in
+        // FP64, 8 in FP32) must fit a workgroup's LDS
+        const int t = p->t1, pe = t + p->w - 1;
+        const size_t patch = (size_t)pe * pe * (prec == GSHT_F64 ? 16 : 8);
+        if (t < 16 || t > 128 || t < p->w - 1 || patch > COL_MAX_BYTES) {
+            delete p;
+            return fail(GSHT_EINVAL, "tile edge %d is not possible with kernel support %d "
+                                     "(16..128 cells, at least w - 1, patch of %zu bytes within "
+                                     "the %zu of LDS)", t, p->w, patch, COL_MAX_BYTES);
+        }
     }
     const size_t cs = csize(prec), rs = cs / 2;
     const size_t gcols = spin ? (size_t)p->n2 : (size_t)p->n2 / 2 + 1;
@@ -788,8 +754,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     }
     tr.mark("kernel polynomials");
     if ((rc = setup_columns(p, s)) != GSHT_OK) { free_plan(p); return rc; }
-    if ((rc = setup_rows(p, s)) != GSHT_OK) { free_plan(p); return rc; }
-    tr.mark("column/row setup");
+    tr.mark("column setup");
     const size_t nd = p->nd, n1 = p->n1, n2 = p->n2;
     rc = GSHT_OK;
     if (p->colmode == 0) {
@@ -800,7 +765,7 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
         rc = make_fft(p->fT_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n1, p->ncol);
         if (rc == GSHT_OK) rc = make_fft(p->fT_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n1, p->ncol);
     }
-    if (rc == GSHT_OK && p->rowmode == 0) {
+    if (rc == GSHT_OK) {
         if (spin) {
             rc = make_fft(p->fP_inv, rocfft_transform_type_complex_inverse, rocfft_placement_inplace, prec, n2, p->nrows);
             if (rc == GSHT_OK) rc = make_fft(p->fP_fwd, rocfft_transform_type_complex_forward, rocfft_placement_inplace, prec, n2, p->nrows);
@@ -913,9 +878,7 @@ int plan_synth_from_D(gsht_plan *p, hipStream_t s)
     if (p->colmode < 2)
         RUNFFT(ST_FFT_THETA_INV, run_fft(p->fT_inv, p->E, nullptr, p->fftwork, p->fftwork_bytes, s));
     RUN(ST_TRANSPOSE_FWD, launch_transpose_fwd(*p, s));
-    if (p->spin && p->rowmode)
-        RUN(ST_FFT_PHI_INV, launch_row_inv(*p, s));
-    else if (p->spin)
+    if (p->spin)
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
     else
         RUNFFT(ST_FFT_PHI_INV, run_fft(p->fP_inv, p->G, p->g, p->fftwork, p->fftwork_bytes, s));
@@ -962,9 +925,7 @@ int plan_adjoint_to_D(gsht_plan *p, const void *map, hipStream_t s)
     else
         RUN(ST_ZERO_GRID, launch_zero(p->g, (size_t)p->nrows * p->n2 * (cs / 2), s));
     RUN(ST_SPREAD, launch_spread(*p, map, s));
-    if (p->spin && p->rowmode)
-        RUN(ST_FFT_PHI_FWD, launch_row_fwd(*p, s));
-    else if (p->spin)
+    if (p->spin)
         RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->G, nullptr, p->fftwork, p->fftwork_bytes, s));
     else
         RUNFFT(ST_FFT_PHI_FWD, run_fft(p->fP_fwd, p->g, p->G, p->fftwork, p->fftwork_bytes, s));
@@ -1132,19 +1093,25 @@ int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const do
         cleanup();
         return fail(GSHT_ENOMEM, "tuning buffers could not be allocated");
     }
-    if (launch_zero(alm, alm_bytes, s) != hipSuccess || launch_zero(map, map_bytes, s) != hipSuccess) {
+    // coefficient values do not change the work; the map must be non-zero, or the
+    // spreading step would skip every chunk
+    if (launch_zero(alm, alm_bytes, s) != hipSuccess ||
+        launch_fill_real(map, 1.0, (int64_t)(map_bytes / (cs / 2)), (int)prec, s) != hipSuccess) {
         cleanup();
-        return fail(GSHT_EHIP, "clearing the tuning buffers failed");
+        return fail(GSHT_EHIP, "preparing the tuning buffers failed");
     }
-    for (int set = 0; set < kNumEs; ++set) {
+    const int tiles[3] = {32, 48, 64};
+    for (int cand = 0; cand < 3 * kNumEs; ++cand) {
+        const int set = cand / 3, tile = tiles[cand % 3];
         gsht_plan *c = nullptr;
-        rc = plan_create_impl(&c, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec, s, set);
+        rc = plan_create_impl(&c, lmax, mmax, spin, theta, phi, npts, epsilon, (int)prec, s, set,
+                              tile);
         if (rc != GSHT_OK) {
-            if (set == 0) {  // the default setting must build
+            if (cand == 0) {  // the default setting must build
                 cleanup();
                 return rc;
             }
-            continue;  // not reachable at this sigma, or no room for a second plan
+            continue;  // not reachable at this sigma or tile, or no room for a second plan
         }
         // one synthesis + adjoint to warm up, then the best of two
         float t = -1.0f;
@@ -1164,7 +1131,8 @@ int gsht_plan_create_tuned(gsht_plan **p, int lmax, int mmax, int spin, const do
             if (best)
                 free_plan(best);
             cleanup();
-            return fail(GSHT_EHIP, "timing the candidate plan at sigma %.2f failed", kEs[set].sigma);
+            return fail(GSHT_EHIP, "timing the candidate plan at sigma %.2f, tile %d failed",
+                        kEs[set].sigma, tile);
         }
         if (best_ms < 0 || t < best_ms) {
             if (best)
@@ -1815,7 +1783,6 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->syn_r = p->syn_r;
     info->adj_r = p->adj_r;
     info->adj_b = p->adj_b;
-    info->row_mode = p->rowmode;
     return ok();
 }
 

@@ -472,134 +472,6 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
         dc[i] = X[lds_pos(fd.perm[i], sh)];
 }
 
-// ---- phi transforms of the grid rows (complex grids, spin > 0) ---------------------
-
-struct RowArgs {
-    int mmax, n2, nrows;
-};
-
-// Row a of the torus, in place: G[a][b] = sum_{|m| <= mmax} G[a][m mod n2] e^{2 pi i m b / n2}
-// for every b < n2 (only the 2 mmax + 1 mode entries are read).  Split by output
-// parity exactly as column_fwd_half_kernel: with nh = n2 / 2 the even outputs are the
-// length-nh transform of the modes folded modulo nh, the odd outputs that of the
-// folded modes times t^m, t = e^{2 pi i / n2}.  twist[k] = e^{-2 pi i k / n2}.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT, col_half_waves<T>()) void row_inv_half_kernel(
-    typename cx<T>::type *__restrict__ G, RowArgs a, ColFFT fh,
-    const typename cx<T>::type *__restrict__ twist)
-{
-    using C = typename cx<T>::type;
-    constexpr int MAXV = col_half_maxn<T>() / NT;
-    extern __shared__ unsigned char smem_raw[];
-    C *X = reinterpret_cast<C *>(smem_raw);
-    const int sh = fh.psh;  // LDS padding shift
-    const int tid = threadIdx.x, nh = fh.n;
-    C *g = G + (size_t)blockIdx.x * a.n2;
-    const int ov0 = nh - a.mmax;
-    C *ovl = X + lds_pad_n(nh, sh);
-    C ye[MAXV];
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int i = tid + v * NT;
-        ye[v].x = ye[v].y = 0;
-        if (i < nh) {
-            C c1, c2;
-            c1.x = c1.y = 0;
-            c2 = c1;
-            if (i <= a.mmax)
-                c1 = g[i];            // m = i
-            if (i >= ov0)
-                c2 = g[i + nh];       // m = i - nh, stored at i - nh + n2
-            ye[v] = cadd(c1, c2);
-            if (i >= ov0 && i <= a.mmax)
-                ovl[i - ov0] = csub(c1, c2);
-        }
-    }
-    __syncthreads();  // every input is read before the row is overwritten
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int i = tid + v * NT;
-        if (i < nh) {
-            C d = ye[v];
-            if (i >= ov0 && i <= a.mmax) {
-                d = ovl[i - ov0];
-            } else if (i > a.mmax) {
-                d.x = -d.x;
-                d.y = -d.y;
-            }
-            X[lds_pos(i, sh)] = cmulc(d, twist[i]);
-        }
-    }
-    __syncthreads();
-    lds_fft<C, 1, NT>(X, fh);
-    for (int i = tid; i < nh; i += NT)
-        g[2 * i + 1] = X[lds_pos(fh.perm[i], sh)];
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int i = tid + v * NT;
-        if (i < nh)
-            X[lds_pos(i, sh)] = ye[v];
-    }
-    __syncthreads();
-    lds_fft<C, 1, NT>(X, fh);
-    for (int i = tid; i < nh; i += NT)
-        g[2 * i] = X[lds_pos(fh.perm[i], sh)];
-}
-
-// Transpose of row_inv_half_kernel, in place: the modes |m| <= mmax of the row,
-// G[a][m mod n2] = sum_b G[a][b] e^{-2 pi i m b / n2} (other entries left as they were).
-template <typename T, int NT>
-__global__ __launch_bounds__(NT, col_half_waves<T>()) void row_fwd_half_kernel(
-    typename cx<T>::type *__restrict__ G, RowArgs a, ColFFT fh,
-    const typename cx<T>::type *__restrict__ twist)
-{
-    using C = typename cx<T>::type;
-    constexpr int MAXV = col_half_maxn<T>() / NT;
-    extern __shared__ unsigned char smem_raw[];
-    C *X = reinterpret_cast<C *>(smem_raw);
-    const int sh = fh.psh;  // LDS padding shift
-    const int tid = threadIdx.x, nh = fh.n, nm = 2 * a.mmax + 1;
-    C *g = G + (size_t)blockIdx.x * a.n2;
-    for (int i = tid; i < nh; i += NT)
-        X[lds_pos(i, sh)] = g[2 * i + 1];
-    __syncthreads();
-    lds_fft<C, -1, NT>(X, fh);
-    C acc[MAXV];
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int j = tid + v * NT;
-        acc[v].x = acc[v].y = 0;
-        if (j < nm) {
-            const int m = j - a.mmax;
-            const int mh = m < 0 ? m + nh : m;           // |m| < nh
-            acc[v] = cmul(X[lds_pos(fh.perm[mh], sh)], twist[m < 0 ? m + a.n2 : m]);
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < nh; i += NT)
-        X[lds_pos(i, sh)] = g[2 * i];
-    __syncthreads();
-    lds_fft<C, -1, NT>(X, fh);
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int j = tid + v * NT;
-        if (j < nm) {
-            const int m = j - a.mmax;
-            acc[v] = cadd(acc[v], X[lds_pos(fh.perm[m < 0 ? m + nh : m], sh)]);
-        }
-    }
-    __syncthreads();  // every input is read before the modes are written
-#pragma unroll
-    for (int v = 0; v < MAXV; ++v) {
-        const int j = tid + v * NT;
-        if (j < nm) {
-            const int m = j - a.mmax;
-            g[m < 0 ? m + a.n2 : m] = acc[v];
-        }
-    }
-}
-
 // Mode 1, D column -> zero-padded, deconvolved spectrum over all n1 entries (the
 // theta transform follows in the library FFT).
 template <typename T>
@@ -741,60 +613,6 @@ void launch_adj(const gsht_plan &p, hipStream_t s)
 }
 
 }  // namespace
-
-template <typename T>
-hipError_t row_set_lds()
-{
-    constexpr int NT = col_half_threads<T>();
-    const int bytes = (int)std::min<size_t>(COL_MAX_BYTES, 163840);
-    hipError_t e = hipFuncSetAttribute((const void *)row_inv_half_kernel<T, NT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void *)row_fwd_half_kernel<T, NT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-hipError_t row_set_lds(int prec) { return prec == GSHT_F64 ? row_set_lds<double>() : row_set_lds<float>(); }
-
-size_t row_lds_bytes(const gsht_plan &p)
-{
-    const int nh = p.n2 / 2;
-    const int novl = std::max(0, 2 * p.mmax - nh + 1);
-    return (size_t)(lds_pad_n(nh, p.lds_psh) + novl) * (p.prec == GSHT_F64 ? 16 : 8);
-}
-
-template <typename T>
-static void launch_rows(const gsht_plan &p, bool inverse, hipStream_t s)
-{
-    constexpr int NT = col_half_threads<T>();
-    using C = typename cx<T>::type;
-    const RowArgs a{p.mmax, p.n2, p.nrows};
-    if (inverse)
-        hipLaunchKernelGGL((row_inv_half_kernel<T, NT>), dim3((unsigned)p.nrows), dim3(NT),
-                           row_lds_bytes(p), s, (C *)p.G, a, p.cf_p, (const C *)p.twist2);
-    else
-        hipLaunchKernelGGL((row_fwd_half_kernel<T, NT>), dim3((unsigned)p.nrows), dim3(NT),
-                           row_lds_bytes(p), s, (C *)p.G, a, p.cf_p, (const C *)p.twist2);
-}
-
-hipError_t launch_row_inv(const gsht_plan &p, hipStream_t s)
-{
-    if (p.prec == GSHT_F64)
-        launch_rows<double>(p, true, s);
-    else
-        launch_rows<float>(p, true, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_fwd(const gsht_plan &p, hipStream_t s)
-{
-    if (p.prec == GSHT_F64)
-        launch_rows<double>(p, false, s);
-    else
-        launch_rows<float>(p, false, s);
-    return hipGetLastError();
-}
 
 hipError_t column_set_lds(const gsht_plan &p)
 {

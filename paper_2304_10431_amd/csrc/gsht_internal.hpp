@@ -115,15 +115,12 @@ struct gsht_plan {
     int es_set = 0;  // kernel setting (oversampling factor) index
     int nrows = 0, a_min = 0;
     int t1 = 0, t2 = 0, nt1 = 0, nt2 = 0;
-    int patch_pad = 0;     // extra cells per LDS patch row (bank spreading)
-    int spread_order = 1;  // spreading visit order inside a chunk (see nufft.hip)
+    int tile_req = 0;      // requested tile edge (0: the default 32)
     int64_t ntiles = 0, nchunks = 0;
     int ncol = 0, npairs = 0;
     int syn_r = 2;       // ring pairs per lane, Legendre synthesis (slices of 64)
     int adj_r = 3;       // ring pairs per lane, Legendre adjoint
     int adj_b = 8;       // degrees per reduction block of the adjoint
-    int adj_pair = 1;    // adjoint: one workgroup per column pair with LDS sums (1), or
-                         // one wave per (m, chunk) with global atomics (0)
     int syn_nchunk = 0;  // chunks of 64 * syn_r ring pairs
     int adj_nchunk = 0;  // chunks of 64 * adj_r ring pairs
     int64_t workspace_bytes = 0;
@@ -168,11 +165,6 @@ struct gsht_plan {
     double *es_poly = nullptr;  // [w][pdeg + 1] interior-tap weight polynomials (FP64 plans)
     gsht::ColFFT cf_d, cf_h;  // lengths nd and n1 / 2
     void *twist = nullptr;    // [n1] exp(-2 pi i k / n1), plan precision (mode 2)
-    // phi transforms of the grid rows: 1 = in-LDS kernels split by output parity
-    // (complex grids only), 0 = library FFT
-    int rowmode = 0;
-    gsht::ColFFT cf_p;        // length n2 / 2
-    void *twist2 = nullptr;   // [n2] exp(-2 pi i k / n2), plan precision
     // FFT plans
     gsht::FFTPlan fD_fwd, fD_inv, fT_inv, fT_fwd, fP_inv, fP_fwd;
     void *fftwork = nullptr;
@@ -230,13 +222,10 @@ hipError_t launch_transpose_adj(const gsht_plan &p, hipStream_t s);  // G -> E (
                                                                      // kept rows only if colmode 2)
 hipError_t launch_deconv_adj(const gsht_plan &p, hipStream_t s);     // E -> D
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s);
+hipError_t launch_fill_real(void *ptr, double value, int64_t n, int prec, hipStream_t s);
 
 // ---- per-column FFT stage (colfft.hip) ------------------------------------
 hipError_t column_set_lds(const gsht_plan &p);                    // once per plan
-hipError_t row_set_lds(int prec);                                  // row kernels' LDS limit
-size_t row_lds_bytes(const gsht_plan &p);
-hipError_t launch_row_inv(const gsht_plan &p, hipStream_t s);     // G rows: modes -> grid
-hipError_t launch_row_fwd(const gsht_plan &p, hipStream_t s);     // G rows: grid -> modes
 int column_half_maxn(int prec);  // largest nd or n1 / 2 of mode 2
 size_t column_lds_bytes(const gsht_plan &p);  // LDS per workgroup of the plan's mode
 hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s);  // D -> E

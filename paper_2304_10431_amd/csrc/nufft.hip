@@ -468,8 +468,7 @@ struct GridGeom {
     const double *poly;  // FP64 interior-tap kernel polynomials (or null), see point_weights
     double c1, c2, half;
     int a_min, n2, stride, nrows, t1, t2, nt2;
-    int ps;      // row stride of a tile's LDS patch in cells (>= t2 + w - 1)
-    int sorder;  // spreading visit order: 0 = stride coprime to the chunk, 1 = sorted
+    int ps;      // row stride of a tile's LDS patch in cells (t2 + w - 1)
     int64_t npts;
 };
 
@@ -757,12 +756,8 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
     if (!(S > 0.0) || !isfinite(S))
         return;  // nothing (finite) to spread; uniform over the block
     const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
-    // Visit order: sorted (default; neighbouring lanes on neighbouring cells, hence
-    // distinct banks), or with a stride coprime to the chunk length (lanes on
-    // distant points: fewer same-cell collisions, more bank conflicts).
-    const int stride = (n % 97 == 0) ? 89 : 97;
     for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
-        const int p = ck.y + (g.sorder ? k : (int)(((int64_t)k * stride) % n));
+        const int p = ck.y + k;
         T wx[W], wy[W];
         int lr, lc;
         point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
@@ -867,8 +862,7 @@ static GridGeom make_geom(const gsht_plan &p)
     g.t1 = p.t1;
     g.t2 = p.t2;
     g.nt2 = p.nt2;
-    g.ps = p.t2 + p.w - 1 + p.patch_pad;
-    g.sorder = p.spread_order;
+    g.ps = p.t2 + p.w - 1;
     g.npts = p.npts;
     g.poly = p.es_poly;
     return g;
@@ -878,7 +872,7 @@ template <typename T, int W>
 static hipError_t interp_w(const gsht_plan &p, void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1;
     if (p.spin) {
         const size_t sm = (size_t)PR * PS * sizeof(typename cpl<T>::type);
         hipLaunchKernelGGL((interp_kernel<T, W, true>), dim3((unsigned)p.nchunks),
@@ -903,7 +897,7 @@ template <typename T, int W>
 static hipError_t interp_deriv_w(const gsht_plan &p, const DerivOut &o, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1;
     const bool vjp = o.gin != nullptr;
     const dim3 grd((unsigned)p.nchunks), blk(NUFFT_THREADS);
     T *map = (T *)o.map, *dth = (T *)o.dth, *dph = (T *)o.dph;
@@ -936,7 +930,7 @@ template <typename T, int W>
 static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
-    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1 + p.patch_pad;
+    const int PR = p.t1 + W - 1, PS = p.t2 + W - 1;
     if (p.ncolors > 0) {
         const size_t sm = (size_t)PR * PS * (p.spin ? 2 : 1) * sizeof(typename SpreadAcc<T>::U);
         for (int c = 0; c < p.ncolors; ++c) {

@@ -29,6 +29,27 @@ __global__ void zero_kernel(T *__restrict__ p, size_t n)
         p[i] = T{};
 }
 
+template <typename T>
+__global__ void fill_kernel(T *__restrict__ p, T v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_real(void *ptr, double value, int64_t n, int prec, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (prec == GSHT_F64)
+        hipLaunchKernelGGL(fill_kernel<double>, dim3(nb), dim3(256), 0, s, (double *)ptr, value, n);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, dim3(nb), dim3(256), 0, s, (float *)ptr,
+                           (float)value, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(void *ptr, size_t bytes, hipStream_t s)
 {
     if (bytes == 0)
@@ -135,7 +156,7 @@ constexpr int TR = 8;
 template <typename T>
 __global__ void transpose_fwd_kernel(const typename cplx2<T>::type *__restrict__ E, int mmax,
                                      int spin, int n1, int n2, int gcols, int nrows, int a_min,
-                                     int modes_only, typename cplx2<T>::type *__restrict__ G)
+                                     typename cplx2<T>::type *__restrict__ G)
 {
     __shared__ typename cplx2<T>::type tile[TT][TT + 1];
     const int b0 = blockIdx.x * TT, r0 = blockIdx.y * TT;
@@ -163,12 +184,8 @@ __global__ void transpose_fwd_kernel(const typename cplx2<T>::type *__restrict__
     __syncthreads();
     for (int yy = ty; yy < TT; yy += TR) {
         const int r = r0 + yy, b = b0 + tx;
-        if (r < nrows && b < gcols) {
-            // the in-LDS row transform reads the 2 mmax + 1 mode entries only
-            if (modes_only && b > mmax && b < n2 - mmax)
-                continue;
+        if (r < nrows && b < gcols)
             G[(size_t)r * gcols + b] = tile[tx][yy];
-        }
     }
 }
 
@@ -225,11 +242,11 @@ hipError_t launch_transpose_fwd(const gsht_plan &p, hipStream_t s)
     dim3 blk(TT, TR), grd((gc + TT - 1) / TT, (p.nrows + TT - 1) / TT);
     if (p.prec == GSHT_F64)
         hipLaunchKernelGGL(transpose_fwd_kernel<double>, grd, blk, 0, s, (const double2 *)p.E,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.rowmode,
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min,
                            (double2 *)p.G);
     else
         hipLaunchKernelGGL(transpose_fwd_kernel<float>, grd, blk, 0, s, (const float2 *)p.E,
-                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min, p.rowmode,
+                           p.mmax, p.spin, p.n1, p.n2, gc, p.nrows, p.a_min,
                            (float2 *)p.G);
     return hipGetLastError();
 }

@@ -118,24 +118,18 @@ def test_legendre_adjoint_stage_matches_oracle(G, lmax, mmax, spin, ntheta):
     assert np.all(got[:, :lmax + 1].imag == 0)
 
 
-@pytest.mark.parametrize("pair", [1, 0])
 @pytest.mark.parametrize("syn_r,adj_r,adj_b", [(1, 1, 8), (2, 2, 8), (4, 2, 4), (1, 4, 4),
                                                (2, 3, 8), (4, 4, 8), (2, 3, 4)])
 @pytest.mark.parametrize("lmax,mmax,spin,ntheta", [(300, 300, 2, 302), (200, 200, 0, 203),
                                                    (130, 100, 2, 520), (161, 161, 1, 1100)])
-def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta,
-                                pair):
+def test_legendre_launch_shapes(G, monkeypatch, syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta):
     """Every supported launch shape (ring pairs per lane, degrees per adjoint block)
-    of both Legendre kernels against the oracle, with the adjoint as column-pair
-    workgroups summing in LDS (pair 1) and as one wave per chunk with global atomics
-    (pair 0); ntheta = 520 spans several chunks and a ragged last one for every
-    shape, ntheta = 1100 more chunks than a pair workgroup has waves, and the odd
-    mmax = 161 pairs every column with another."""
-    say("legendre shapes", syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta, pair)
+    of both Legendre kernels against the oracle; ntheta = 520 spans several chunks
+    and a ragged last one for every shape, ntheta = 1100 many chunks per column."""
+    say("legendre shapes", syn_r, adj_r, adj_b, lmax, mmax, spin, ntheta)
     monkeypatch.setenv("GSHT_SYN_R", str(syn_r))
     monkeypatch.setenv("GSHT_ADJ_R", str(adj_r))
     monkeypatch.setenv("GSHT_ADJ_B", str(adj_b))
-    monkeypatch.setenv("GSHT_ADJ_PAIR", str(pair))
     rng = np.random.default_rng(lmax + 13 * spin)
     a = wl.gaussian_alm(lmax, mmax, spin, rng, cl=np.ones(lmax + 1))
     ref = doubled_reference(a, lmax, mmax, spin, ntheta)
@@ -331,43 +325,6 @@ def test_column_stage_modes_agree(G, monkeypatch, lmax, spin, prec, eps):
         assert rel_l2(outs[mode][1] * w, outs[0][1] * w) <= tol
 
 
-@pytest.mark.parametrize("lmax,mmax,spin,prec,eps", [(130, 130, 2, "f64", 1e-11),
-                                                     (200, 77, 1, "f64", 1e-10),
-                                                     (512, 512, 2, "f32", 1e-5),
-                                                     (512, 400, 3, "f64", 1e-10),
-                                                     (47, 47, 2, "f32", 1e-4)])
-def test_row_transform_modes_agree(G, monkeypatch, lmax, mmax, spin, prec, eps):
-    """The in-LDS phi transforms of the grid rows (row mode 1; split by output parity,
-    mode entries only) against the library FFT (row mode 0) and the oracle, synthesis
-    and adjoint; mmax < lmax gives n2 != n1 (separate tables), mmax = 512 folds two
-    modes onto one residue."""
-    say("row modes", lmax, mmax, spin, prec, eps)
-    rng = np.random.default_rng(500 + lmax + mmax)
-    th, ph = wl.uniform_sphere(6000, rng)
-    a = wl.gaussian_alm(lmax, mmax, spin, rng)
-    y = rng.standard_normal((oracle.ncomp(spin), th.size))
-    cdt = torch.complex128 if prec == "f64" else torch.complex64
-    rdt = torch.float64 if prec == "f64" else torch.float32
-    ref_m = oracle.synth(a, lmax, mmax, spin, th, ph)
-    ref_a = oracle.adjoint(y, lmax, mmax, spin, th, ph)
-    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
-    outs = {}
-    for mode in (0, 1):
-        monkeypatch.setenv("GSHT_ROW_MODE", str(mode))
-        plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec)
-        assert plan.info()["row_mode"] == mode
-        m = plan.synth(dev(a).to(cdt)).cpu().numpy().astype(np.float64)
-        b = plan.adjoint(dev(y).to(rdt)).cpu().numpy().astype(np.complex128)
-        plan.close()
-        em, ea = oracle.eps_eff(m, ref_m), oracle.eps_eff(b * w, ref_a * w)
-        say("  mode", mode, "synth", em, "adjoint", ea)
-        assert em <= eps and ea <= eps, (mode, em, ea)
-        outs[mode] = (m, b)
-    tol = 1e-12 if prec == "f64" else 2e-6
-    assert rel_l2(outs[1][0], outs[0][0]) <= tol
-    assert rel_l2(outs[1][1] * w, outs[0][1] * w) <= tol
-
-
 @pytest.mark.parametrize("lmax,mmax,spin,npts,prec,eps,colors", [
     (127, 127, 2, 30000, "f64", 1e-10, 4),   # even number of tile columns
     (40, 23, 2, 20000, "f64", 1e-10, 6),     # n2 = 96: three tile columns (odd)
@@ -404,7 +361,7 @@ def test_spreading_by_tile_colour(G, monkeypatch, lmax, mmax, spin, npts, prec, 
 def test_lds_padding_is_bitwise_neutral(G, monkeypatch, lmax, mmax, spin, prec):
     """The padding slots of the in-LDS transforms move values, never the arithmetic:
     every padding (none, one slot per 4, per 32 elements) gives identical bits, for
-    the fused column stage and the in-LDS row transforms."""
+    the fused column stage."""
     say("lds padding", lmax, mmax, spin, prec)
     rng = np.random.default_rng(600 + lmax)
     th, ph = wl.uniform_sphere(5000, rng)
@@ -413,8 +370,6 @@ def test_lds_padding_is_bitwise_neutral(G, monkeypatch, lmax, mmax, spin, prec):
     cdt = torch.complex128 if prec == "f64" else torch.complex64
     rdt = torch.float64 if prec == "f64" else torch.float32
     monkeypatch.setenv("GSHT_COLUMN_MODE", "2")
-    if spin:
-        monkeypatch.setenv("GSHT_ROW_MODE", "1")
     outs = []
     for pad in ("0", "2", "5"):
         monkeypatch.setenv("GSHT_LDS_PAD", pad)
