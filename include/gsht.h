@@ -467,6 +467,23 @@ int gsht_legendre_rings(const void *alm, int lmax, int mmax, int spin, int nthet
 int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int ntheta,
                                 gsht_precision prec, void *alm, void *hip_stream);
 
+/*
+ * Allocation-free form of gsht_legendre_rings_adjoint, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, layouts and results; it calls
+ * no hipMalloc, hipFree or other allocating routine and does not synchronise.  The
+ * Legendre tables, start data and accumulators live in one fixed 64 MiB scratch
+ * array per device, held by the library until the process ends; sizes whose tables
+ * need more (about 56 nalm bytes for spin > 0, 40 nalm for spin 0) are refused with
+ * GSHT_EINVAL before any device work.  Each call rewrites every part of the scratch
+ * it reads (start data copied from the host, tables and live-chunk table recomputed,
+ * accumulators cleared by a fill kernel).  All calls on one device share its
+ * scratch: calls that overlap on one device (other host threads, or other streams
+ * still running an earlier call) race and must be serialised by the caller.
+ */
+int gsht_legendre_rings_adjoint_noalloc(const void *F, int lmax, int mmax, int spin, int ntheta,
+                                        gsht_precision prec, void *alm, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

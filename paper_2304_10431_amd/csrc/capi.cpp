@@ -60,6 +60,39 @@ int ok()
 
 std::once_flag g_fft_once;
 
+// ---- device scratch of the allocation-free entry point ------------------------
+// One fixed array per device, in the code object's global memory: the Legendre
+// tables, the start data and the adjoint's accumulators of one
+// gsht_legendre_rings_adjoint_noalloc call live here instead of in allocations.  Host
+// code must not pass the array's name to a kernel (it is a host-side stand-in, not a
+// device address): its address on each device comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+// host copies of the start data most recently sent to each device's scratch (kept
+// until the next call on that device)
+std::vector<StartInfo> g_scratch_start[kMaxDevices];
+
+int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(GSHT_EUNSUPPORTED, "device %d is beyond the %d devices the scratch table covers",
+                    dev, kMaxDevices);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GSHT_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GSHT_OK;
+}
+
 bool smooth7(long n)
 {
     if (n < 1)
@@ -2017,6 +2050,72 @@ int gsht_legendre_rings_adjoint(const void *F, int lmax, int mmax, int spin, int
         rc2 = check_launch(hipStreamSynchronize(s), "synchronize");
     free_plan(p);
     return rc2 == GSHT_OK ? ok() : rc2;
+}
+
+int gsht_legendre_rings_adjoint_noalloc(const void *F, int lmax, int mmax, int spin, int ntheta,
+                                        gsht_precision prec, void *alm, void *hip_stream)
+{
+    int rc = check_common(lmax, mmax, spin, 0, prec == GSHT_F64 ? 1e-10 : 1e-5, (int)prec);
+    if (rc != GSHT_OK)
+        return rc;
+    if (ntheta < 2 || ntheta > 1 << 20)
+        return fail(GSHT_EINVAL, "ntheta must be in [2, 2^20], got %d", ntheta);
+    if (!alm || !F)
+        return fail(GSHT_EINVAL, "alm/F must not be NULL");
+    // the call's plan lives on the stack and points into the device scratch
+    gsht_plan p;
+    p.lmax = lmax;
+    p.mmax = mmax;
+    p.spin = spin;
+    p.prec = (int)prec;
+    p.ncomp = spin ? 2 : 1;
+    p.nalm = (int64_t)(mmax + 1) * (lmax + 1) - (int64_t)mmax * (mmax + 1) / 2;
+    p.ntheta = ntheta;
+    p.nd = 2 * ntheta - 2;
+    p.ncol = spin ? 2 * mmax + 1 : mmax + 1;
+    p.npairs = (ntheta + 1) / 2;
+    p.adj_nchunk = (p.npairs + 64 * p.adj_r - 1) / (64 * p.adj_r);
+    p.syn_nchunk = (p.npairs + 64 * p.syn_r - 1) / (64 * p.syn_r);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_ab = up(sizeof(double2) * (size_t)p.nalm);
+    const size_t b_norm = up(sizeof(double) * (size_t)p.nalm);
+    const size_t b_acc = up(sizeof(double) * 2 * p.ncomp * (size_t)p.nalm);
+    const size_t b_start = up(sizeof(StartInfo) * (size_t)(mmax + 1));
+    const size_t b_live = up(sizeof(int32_t) * (size_t)(mmax + 1) * p.adj_nchunk);
+    const size_t need = b_ab + b_norm + b_acc + b_start + b_live;
+    if (need > kScratchBytes)
+        return fail(GSHT_EINVAL, "lmax %d, mmax %d, spin %d, ntheta %d need %zu bytes of device "
+                                 "scratch; the allocation-free entry point holds %zu",
+                    lmax, mmax, spin, ntheta, need, kScratchBytes);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    void *base = nullptr;
+    if ((rc = scratch_address(dev, &base)) != GSHT_OK)
+        return rc;
+    char *q = (char *)base;
+    p.leg.ab = (double2 *)q;
+    q += b_ab;
+    p.leg.norm = (double *)q;
+    q += b_norm;
+    p.acc = (double *)q;
+    q += b_acc;
+    p.leg.start = (StartInfo *)q;
+    q += b_start;
+    p.leg.lfirst_adj = (int32_t *)q;
+    // start data: computed on the host, sent from a host copy kept until the next call
+    g_scratch_start[dev] = make_start_info(lmax, mmax, spin);
+    HIP_TRY(hipMemcpyAsync(p.leg.start, g_scratch_start[dev].data(),
+                           sizeof(StartInfo) * (size_t)(mmax + 1), hipMemcpyHostToDevice, s));
+    rc = check_launch(launch_leg_tables(p, s), "legendre tables");
+    if (rc == GSHT_OK)
+        rc = check_launch(launch_leg_live_adj(p, s), "live-chunk table");
+    if (rc == GSHT_OK)
+        rc = check_launch(launch_leg_adjoint(p, F, false, s), "legendre_adjoint");
+    if (rc == GSHT_OK)
+        rc = check_launch(launch_leg_finalize(p, alm, 1.0, false, s), "finalize");
+    return rc == GSHT_OK ? ok() : rc;
 }
 
 }  // extern "C"

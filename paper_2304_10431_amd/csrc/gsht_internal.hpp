@@ -183,6 +183,7 @@ namespace gsht {
 // ---- Legendre step (legendre.hip) ------------------------------------------
 hipError_t launch_leg_tables(const gsht_plan &p, hipStream_t s);
 hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s);
+hipError_t launch_leg_live_adj(const gsht_plan &p, hipStream_t s);  // adjoint's table only
 // mscale multiplies the coefficients (prep) or results (finalize) of every m > 0:
 // 1 for the transforms, 1/2 or 2 for the weights w_m of their derivatives.
 // grad: gradient-only spin s (C = 0 on input; only G on output).

@@ -115,6 +115,12 @@ hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_leg_live_adj(const gsht_plan &p, hipStream_t s)
+{
+    live_launch(p, p.adj_r, p.adj_nchunk, p.leg.lfirst_adj, s);
+    return hipGetLastError();
+}
+
 // Accumulators of one ring pair: spin s -> N+ (0,1), S+ (2,3), N- (4,5), S- (6,7);
 // spin 0 -> N (0,1), S (2,3).  SG = (-1)^(l - l0).
 template <bool SPIN, int SG>

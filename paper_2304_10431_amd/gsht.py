@@ -77,6 +77,7 @@ _SIGS = {
     "gsht_plan_get_stage_times": [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64), _i],
     "gsht_legendre_rings": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
     "gsht_legendre_rings_adjoint": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
+    "gsht_legendre_rings_adjoint_noalloc": [_vp, _i, _i, _i, _i, _i, _vp, _vp],
     "gsht_deflect": [_vp, _vp, _vp, _i, _i64, _vp, _vp, _vp, _vp],
     "gsht_deflect_vjp": [_vp, _vp, _i, _i64, _vp, _vp, _vp, _vp, _vp],
     "gsht_spin_phase": [_vp, _vp, _i, _i, _i, _i64, _vp],
@@ -411,6 +412,22 @@ def legendre_rings_adjoint(F, lmax: int, mmax: int, spin: int, ntheta: int, prec
     _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
     _check(_lib.gsht_legendre_rings_adjoint(_ptr(F), lmax, mmax, spin, ntheta, prec, _ptr(out),
                                             _stream()))
+    return out
+
+
+def legendre_rings_adjoint_noalloc(F, lmax: int, mmax: int, spin: int, ntheta: int, out,
+                                   precision="f64"):
+    """Allocation-free stage entry point gsht_legendre_rings_adjoint_noalloc: the same
+    result as legendre_rings_adjoint, written into the caller's ``out``
+    [ncomp][nalm]; the library allocates nothing (its tables live in a fixed device
+    scratch array shared by all calls on the device)."""
+    prec = _PREC[precision]
+    ncomp = 1 if spin == 0 else 2
+    ncol = mmax + 1 if spin == 0 else 2 * mmax + 1
+    _need(F, _CDT[prec], (ncol, 2 * ntheta - 2), "F")
+    _need(out, _CDT[prec], (ncomp, nalm(lmax, mmax)), "alm")
+    _check(_lib.gsht_legendre_rings_adjoint_noalloc(_ptr(F), lmax, mmax, spin, ntheta, prec,
+                                                    _ptr(out), _stream()))
     return out
 
 

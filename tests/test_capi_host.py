@@ -111,3 +111,17 @@ def test_sigma_and_point_moving_entries_reject_on_host(lib):
     lib.gsht_plan_set_points.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int64, ctypes.c_void_p]
     assert lib.gsht_plan_set_points(None, None, None, 0, None) == -1
+
+
+def test_noalloc_refuses_sizes_beyond_its_scratch(lib):
+    """The allocation-free entry point refuses, before any device work, a size whose
+    tables exceed its fixed scratch (lmax 4096, spin 2 needs about 470 MB)."""
+    f = lib.gsht_legendre_rings_adjoint_noalloc
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.gsht_last_error.restype = ctypes.c_char_p
+    rc = f(ctypes.c_void_p(16), 4096, 4096, 2, 4117, 0, ctypes.c_void_p(16), None)
+    assert rc == -1
+    assert b"scratch" in lib.gsht_last_error()
+    rc = f(None, 64, 64, 2, 70, 0, ctypes.c_void_p(16), None)   # NULL input
+    assert rc == -1
