@@ -32,13 +32,16 @@ namespace gsht {
 // ---- live-chunk table -------------------------------------------------------------
 
 // For each (m, chunk): the first degree at which the chunk's most equatorial ring
-// reaches 2^-900 in either channel (lmax + 1 if never).  The other rings of the
-// chunk are smaller there, so a chunk whose entry exceeds lmax has nothing above
-// the accumulation threshold and is skipped.
+// reaches 2^THR in either channel (lmax + 1 if never).  The other rings of the
+// chunk are smaller there, so a chunk whose entry exceeds lmax has nothing at or
+// above 2^THR and is skipped.  THR is the kernel's in-range threshold: the synthesis
+// takes 2^-900 and the adjoint 2^-256, below which it adds nothing (a channel
+// contributes only once its value has reached that threshold), so skipping such a
+// chunk leaves the results unchanged.
 template <bool SPIN>
 __global__ void leg_live_kernel(const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
                                 int lmax, int mmax, int ntheta, int npairs, int chunk_pairs,
-                                int nchunk, int32_t *__restrict__ lfirst)
+                                int nchunk, int thr, int32_t *__restrict__ lfirst)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (int64_t)(mmax + 1) * nchunk)
@@ -63,8 +66,8 @@ __global__ void leg_live_kernel(const double2 *__restrict__ ab, const StartInfo 
     int res = lmax + 1;
     for (int l = l0; l <= lmax; ++l) {
         int k;
-        const bool ha = a1 != 0.0 && (frexp(a1, &k), k + ea >= -900);
-        const bool hb = SPIN && b1 != 0.0 && (frexp(b1, &k), k + eb >= -900);
+        const bool ha = a1 != 0.0 && (frexp(a1, &k), k + ea >= thr);
+        const bool hb = SPIN && b1 != 0.0 && (frexp(b1, &k), k + eb >= thr);
         if (ha || hb) {
             res = l;
             break;
@@ -96,28 +99,29 @@ __global__ void leg_live_kernel(const double2 *__restrict__ ab, const StartInfo 
     lfirst[id] = res;
 }
 
-static void live_launch(const gsht_plan &p, int r, int nchunk, int32_t *lfirst, hipStream_t s)
+static void live_launch(const gsht_plan &p, int r, int nchunk, int thr, int32_t *lfirst,
+                        hipStream_t s)
 {
     const int64_t n = (int64_t)(p.mmax + 1) * nchunk;
     dim3 blk(64), grd((unsigned)((n + 63) / 64));
     if (p.spin)
         hipLaunchKernelGGL(leg_live_kernel<true>, grd, blk, 0, s, p.leg.ab, p.leg.start, p.lmax,
-                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, lfirst);
+                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, thr, lfirst);
     else
         hipLaunchKernelGGL(leg_live_kernel<false>, grd, blk, 0, s, p.leg.ab, p.leg.start, p.lmax,
-                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, lfirst);
+                           p.mmax, p.ntheta, p.npairs, 64 * r, nchunk, thr, lfirst);
 }
 
 hipError_t launch_leg_live(const gsht_plan &p, hipStream_t s)
 {
-    live_launch(p, p.syn_r, p.syn_nchunk, p.leg.lfirst_syn, s);
-    live_launch(p, p.adj_r, p.adj_nchunk, p.leg.lfirst_adj, s);
+    live_launch(p, p.syn_r, p.syn_nchunk, SYN_IN_EXP, p.leg.lfirst_syn, s);
+    live_launch(p, p.adj_r, p.adj_nchunk, ADJ_IN_EXP, p.leg.lfirst_adj, s);
     return hipGetLastError();
 }
 
 hipError_t launch_leg_live_adj(const gsht_plan &p, hipStream_t s)
 {
-    live_launch(p, p.adj_r, p.adj_nchunk, p.leg.lfirst_adj, s);
+    live_launch(p, p.adj_r, p.adj_nchunk, ADJ_IN_EXP, p.leg.lfirst_adj, s);
     return hipGetLastError();
 }
 
@@ -858,7 +862,7 @@ static void adj_launch(const gsht_plan &p, const void *Din, bool grad, hipStream
 
 hipError_t launch_leg_live_r1(const gsht_plan &p, int32_t *lfirst1, hipStream_t s)
 {
-    live_launch(p, 1, (p.npairs + 63) / 64, lfirst1, s);
+    live_launch(p, 1, (p.npairs + 63) / 64, SYN_IN_EXP, lfirst1, s);
     return hipGetLastError();
 }
 

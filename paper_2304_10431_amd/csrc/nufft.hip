@@ -706,17 +706,48 @@ template <> struct SpreadAcc<double> {
     __device__ static U quant(double q) { return (U)__double2ll_rn(q); }
 };
 
-// Type-1 spreading of one chunk.  The patch holds the real parts and the imaginary
-// parts in separate planes (row stride g.ps cells), so that the lanes of one atomic
-// instruction, which visit the chunk's points in sorted order and therefore
-// neighbouring cells, fall on distinct LDS banks.  The chunk's patch accumulates in
-// fixed point:
-// every contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with
-// S = sum over the chunk's points of |Re y| + |Im y|, which bounds every cell sum,
-// so the two's-complement integer adds never wrap; the quantisation step is
-// S / RANGE (2^-31 S for FP32, 2^-63 S for FP64).  Non-zero cells are then added to
-// the grid: with global atomics (ATOMIC), or with plain read-add-write when no other
+// Type-1 spreading of one chunk.  The chunk's patch accumulates in fixed point: every
+// contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with S = sum over the
+// chunk's points of |Re y| + |Im y|, which bounds every cell sum, so the
+// two's-complement integer adds never wrap; the quantisation step is S / RANGE
+// (2^-31 S for FP32, 2^-63 S for FP64).  The lanes of one atomic instruction visit
+// the chunk's points st apart in sorted order (see spread_stride).  FP32 complex
+// grids keep both parts of a cell in one 64-bit word, Re 2^32 + Im (as integers):
+// integer addition is exact and associative, and each part's sum stays within
+// 32-bit range, so the word's low 32 bits (read as signed) are the sum of the
+// imaginary parts and the rest, shifted down, that of the real parts -- one atomic
+// per tap and cell instead of two, with the same sums.  FP64 keeps the parts in
+// separate planes (row stride g.ps cells).  The points' values are read once (they
+// give S and are then spread from registers).  Non-zero cells are then added to the
+// grid: with global atomics (ATOMIC), or with plain read-add-write when no other
 // workgroup can touch the patch at the same time (tiles launched by colour).
+constexpr int SPREAD_PER_THREAD = CHUNK / NUFFT_THREADS;
+static_assert(SPREAD_PER_THREAD * NUFFT_THREADS == CHUNK, "chunk points per thread");
+
+// Visit order of a chunk's points: slot k takes point (k st) mod n with st the first
+// odd number from SPREAD_STRIDE on that is coprime to n (a permutation of the chunk).
+// Neighbouring points of a ring often fall into the same cell once deflected, and
+// lanes of one atomic instruction on the same address are serialised; lanes st
+// points apart rarely share a cell.
+constexpr int SPREAD_STRIDE = 97;
+__device__ inline int spread_stride(int n)
+{
+    for (int st = SPREAD_STRIDE;; st += 2) {
+        int a = st, b = n;
+        while (b) {
+            const int t = a % b;
+            a = b;
+            b = t;
+        }
+        if (a == 1)
+            return st;
+    }
+}
+
+template <typename T, bool CPLX> struct SpreadPack {
+    static constexpr bool value = CPLX && std::is_same<T, float>::value;
+};
+
 template <typename T, int W, bool CPLX, bool ATOMIC>
 __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
                                     const double *__restrict__ sph,
@@ -726,21 +757,30 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
 {
     using A = SpreadAcc<T>;
     using U = typename A::U;
+    constexpr bool PACK = SpreadPack<T, CPLX>::value;
     constexpr int NC = CPLX ? 2 : 1;
     const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
     const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
-    const int plane = PR * g.ps;  // real parts, then imaginary parts (one plane each)
+    const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
     const int n = ck.z - ck.y;
     for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
         patch[idx] = 0;
-    // bound S of every cell sum
+    // the chunk's values (read once) and the bound S of every cell sum
+    const int st = n > 1 ? spread_stride(n) : 1;
+    double yr[SPREAD_PER_THREAD], yi[SPREAD_PER_THREAD];
     double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
-        const int32_t src = perm[ck.y + k];
-        s += fabs((double)in[src]);
-        if constexpr (CPLX)
-            s += fabs((double)in[g.npts + src]);
+#pragma unroll
+    for (int q = 0; q < SPREAD_PER_THREAD; ++q) {
+        const int k = threadIdx.x + q * NUFFT_THREADS;
+        yr[q] = yi[q] = 0.0;
+        if (k < n) {
+            const int32_t src = perm[ck.y + (int)(((int64_t)k * st) % n)];
+            yr[q] = (double)in[src];
+            if constexpr (CPLX)
+                yi[q] = (double)in[g.npts + src];
+            s += fabs(yr[q]) + fabs(yi[q]);
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1)
@@ -756,29 +796,43 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
     if (!(S > 0.0) || !isfinite(S))
         return;  // nothing (finite) to spread; uniform over the block
     const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
-    for (int k = threadIdx.x; k < n; k += NUFFT_THREADS) {
-        const int p = ck.y + k;
+    // one rolled loop (a copy of the tap loops per point would double the code)
+#pragma unroll 1
+    for (int q = 0; q < SPREAD_PER_THREAD; ++q) {
+        const int k = threadIdx.x + q * NUFFT_THREADS;
+        if (k >= n)
+            break;
+        const int p = ck.y + (int)(((int64_t)k * st) % n);
         T wx[W], wy[W];
         int lr, lc;
         point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
         if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
             continue;  // cannot happen for points sorted by the same arithmetic
-        const int32_t src = perm[p];
-        const double yr = (double)in[src] * scale;
-        const double yi = CPLX ? (double)in[g.npts + src] * scale : 0.0;
+        const double vr = yr[q] * scale, vi = yi[q] * scale;
         double dy[W];
 #pragma unroll
         for (int j = 0; j < W; ++j)
             dy[j] = (double)wy[j];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            const double fr = (double)wx[i] * yr, fi = (double)wx[i] * yi;
-            U *rowp = patch + (lr + i) * g.ps + lc;
+            const double fr = (double)wx[i] * vr, fi = (double)wx[i] * vi;
+            if constexpr (PACK) {
+                unsigned long long *rowp =
+                    reinterpret_cast<unsigned long long *>(patch) + (lr + i) * g.ps + lc;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-                atomicAdd(rowp + j, A::quant(fr * dy[j]));
-                if constexpr (CPLX)
-                    atomicAdd(rowp + plane + j, A::quant(fi * dy[j]));
+                for (int j = 0; j < W; ++j) {
+                    const long long qr = __double2int_rn(fr * dy[j]);
+                    const long long qi = __double2int_rn(fi * dy[j]);
+                    atomicAdd(rowp + j, ((unsigned long long)qr << 32) + (unsigned long long)qi);
+                }
+            } else {
+                U *rowp = patch + (lr + i) * g.ps + lc;
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    atomicAdd(rowp + j, A::quant(fr * dy[j]));
+                    if constexpr (CPLX)
+                        atomicAdd(rowp + plane + j, A::quant(fi * dy[j]));
+                }
             }
         }
     }
@@ -794,8 +848,15 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
             c -= g.n2;
         T *dst = grid + ((size_t)r * g.stride + c) * NC;
         const int pidx = pr * g.ps + pc;
-        const typename A::S qr = (typename A::S)patch[pidx];
-        const typename A::S qi = CPLX ? (typename A::S)patch[plane + pidx] : 0;
+        typename A::S qr, qi;
+        if constexpr (PACK) {
+            const long long t = (long long)reinterpret_cast<unsigned long long *>(patch)[pidx];
+            qi = (int)(unsigned int)(t & 0xffffffffll);
+            qr = (int)((t - (long long)qi) >> 32);
+        } else {
+            qr = (typename A::S)patch[pidx];
+            qi = CPLX ? (typename A::S)patch[plane + pidx] : 0;
+        }
         if (ATOMIC) {
             if (qr != 0)
                 unsafeAtomicAdd(dst, (T)((double)qr * inv));
