@@ -454,13 +454,11 @@ int setup_legendre(gsht_plan *p, hipStream_t s, bool with_deconv)
 
 size_t csize(int prec) { return prec == GSHT_F64 ? 16 : 8; }
 
-int col_maxr(const gsht_plan *p) { return p->prec == GSHT_F32 ? 8 : 16; }
+int col_maxr(const gsht_plan *p) { return column_max_radix(p->prec); }
 
-// Radices of an in-LDS transform of length n (largest first), or false if n has a
-// prime factor above 7 or needs more than COL_MAXP passes.
-// Radices of an in-LDS transform of length n, largest first.  maxr = 16 or 8: the
-// FP32 kernels are built without the radix-16 pass, whose 16 complex values plus
-// twiddles would make them spill at the register budget of two workgroups per CU.
+// Radices of an in-LDS transform of length n (largest first, none above maxr, the
+// largest radix the kernels are built with), or false if n has a prime factor above
+// 7 or needs more than COL_MAXP passes.
 bool col_radices(int n, std::vector<int> &rad, int maxr)
 {
     rad.clear();
@@ -583,6 +581,9 @@ int make_twist(gsht_plan *p, void **out, int n, hipStream_t s)
     return GSHT_OK;
 }
 
+// Smallest epsilon at which FP64 plans spread in the fast fixed-point form.
+constexpr double kSpreadFastEps = 1e-10;
+
 // Default LDS padding shift of the in-LDS transforms.
 constexpr int kLdsPadShift = 4;
 
@@ -698,6 +699,12 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     p->eps = eps;
     p->prec = prec;
     p->tile_req = tile;
+    // FP64 spreading: the fast fixed-point form where its rounding (relative 2^-50 of
+    // a chunk's value bound per contribution) stays far below epsilon;
+    // GSHT_SPREAD_QUANT=exact|fast forces a form for testing
+    p->spread_fast = prec == GSHT_F64 && eps >= kSpreadFastEps;
+    if (const char *q = getenv("GSHT_SPREAD_QUANT"))
+        p->spread_fast = prec == GSHT_F64 && strcmp(q, "fast") == 0;
     choose_sizes(p);
     if (p->w == 0) {
         const double sg = kEs[es_set].sigma;

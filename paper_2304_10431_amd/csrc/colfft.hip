@@ -14,7 +14,7 @@
 // deconvolution are fused here and the theta transform runs separately on E.
 //
 // The FFTs are in-place mixed-radix decimation-in-frequency passes over LDS (radices
-// 16 (FP64 only), 8, 4, 2, 3, 5, 7): pass i splits sub-transforms of length L into radix r_i
+// 8, 4, 2, 3, 5, 7): pass i splits sub-transforms of length L into radix r_i
 // butterflies of stride s = L / r_i, each followed by the twiddles w_L^(q j).  The
 // result sits in digit-reversed order; a host-built table gives the LDS position of
 // every frequency.  Twiddles come from per-pass tables in the working precision,
@@ -29,23 +29,32 @@ namespace {
 
 constexpr int COL_THREADS = 1024;
 
+// largest radix of the in-LDS transforms (a radix-16 pass, 16 complex values plus 15
+// twiddles, does not fit the 128 registers of either precision's workgroups)
+constexpr int COL_MAXR = 8;
+
 template <typename T> struct cx;
 template <> struct cx<float> { using type = float2; };
 template <> struct cx<double> { using type = double2; };
+template <typename C> struct cx2;  // two complex values
+template <> struct cx2<float2> { using type = float4; };
+template <> struct cx2<double2> { using type = double4; };
 
 // Mode 2 (split theta transform): threads per workgroup and the largest nd or
-// n1 / 2 it takes; each thread stages up to col_half_maxn / 512 values in
-// registers.  FP32: two workgroups (2 x 66 KB of LDS at lmax 4096) share a CU within
-// 128 VGPRs.  FP64: one workgroup per CU (132 KB), up to 256 VGPRs.
+// n1 / 2 it takes; each thread stages up to col_half_maxn / threads values in
+// registers.  FP32: two workgroups of 512 threads (2 x 66 KB of LDS at lmax 4096)
+// share a CU.  FP64: one workgroup per CU (132 KB) of 1024 threads, so that four
+// waves per SIMD hide the LDS latency of the passes (18 % faster than 512 threads
+// with radix-16 passes).  Either way 16 waves per CU and 128 VGPRs.
 template <typename T>
 constexpr int col_half_threads()
 {
-    return 512;
+    return sizeof(T) == 4 ? 512 : 1024;
 }
 template <typename T>
-constexpr int col_half_waves()  // waves per SIMD to fit: two workgroups per CU for FP32
+constexpr int col_half_waves()  // waves per SIMD
 {
-    return sizeof(T) == 4 ? 4 : 2;
+    return 4;
 }
 template <typename T>
 constexpr int col_half_maxn()
@@ -198,7 +207,7 @@ __device__ inline void dft(C (&v)[R])
 // One decimation-in-frequency pass over NT threads: butterflies b < n / R over
 // sub-transforms of length L = R s; butterfly (sub, j) reads positions
 // sub L + j + t s, t < R, and its twiddles w_L^(q j) from tw[j (R - 1) + q - 1]
-// (conjugated for DIR > 0).
+// (conjugated for DIR > 0): a lane's twiddles are contiguous.
 template <typename C, int R, int DIR, int NT>
 __device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s, int sh)
 {
@@ -213,10 +222,9 @@ __device__ inline void dif_pass(C *X, const C *__restrict__ tw, int n, int s, in
             v[t] = X[lds_pos(base + t * s, sh)];
         dft<C, R, DIR>(v);
         if (j != 0) {
-            const C *wt = tw + j * (R - 1);
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                C w = wt[q - 1];
+                C w = tw[j * (R - 1) + q - 1];
                 if (DIR > 0)
                     w.y = -w.y;
                 const C a = v[q];
@@ -241,10 +249,6 @@ __device__ void lds_fft(C *X, const ColFFT &f)
         const int s = L / r;
         const C *tw = reinterpret_cast<const C *>(f.tw) + f.twoff[p];
         switch (r) {
-        case 16:  // FP64 only: FP32 transforms get radices up to 8 (no spills)
-            if constexpr (sizeof(C) == 16)
-                dif_pass<C, 16, DIR, NT>(X, tw, f.n, s, f.psh);
-            break;
         case 8: dif_pass<C, 8, DIR, NT>(X, tw, f.n, s, f.psh); break;
         case 4: dif_pass<C, 4, DIR, NT>(X, tw, f.n, s, f.psh); break;
         case 2: dif_pass<C, 2, DIR, NT>(X, tw, f.n, s, f.psh); break;
@@ -302,6 +306,50 @@ struct ColArgs {
 };
 
 __device__ inline int col_m(const ColArgs &a, int col) { return a.spin ? col - a.mmax : col; }
+
+// Rows 2i (value ev) and 2i + 1 (od) of an E column, those of them the grid keeps;
+// one 2-element store when both are kept (E columns have even length, so the pair is
+// aligned to its own size).
+template <typename C>
+__device__ inline void store_rows(C *ec, int i, C ev, C od, const ColArgs &a)
+{
+    using C2 = typename cx2<C>::type;
+    const bool ke = row_kept(2 * i, a.n1, a.nrows, a.a_min);
+    const bool ko = row_kept(2 * i + 1, a.n1, a.nrows, a.a_min);
+    if (ke && ko) {
+        C2 p;
+        p.x = ev.x;
+        p.y = ev.y;
+        p.z = od.x;
+        p.w = od.y;
+        reinterpret_cast<C2 *>(ec)[i] = p;
+    } else if (ke) {
+        ec[2 * i] = ev;
+    } else if (ko) {
+        ec[2 * i + 1] = od;
+    }
+}
+
+// Rows 2i and 2i + 1 of an E column as (ev, od), zero where the grid keeps no row.
+template <typename C>
+__device__ inline void load_rows(const C *ec, int i, C &ev, C &od, const ColArgs &a)
+{
+    using C2 = typename cx2<C>::type;
+    const bool ke = row_kept(2 * i, a.n1, a.nrows, a.a_min);
+    const bool ko = row_kept(2 * i + 1, a.n1, a.nrows, a.a_min);
+    ev.x = ev.y = od.x = od.y = 0;
+    if (ke && ko) {
+        const C2 p = reinterpret_cast<const C2 *>(ec)[i];
+        ev.x = p.x;
+        ev.y = p.y;
+        od.x = p.z;
+        od.y = p.w;
+    } else if (ke) {
+        ev = ec[2 * i];
+    } else if (ko) {
+        od = ec[2 * i + 1];
+    }
+}
 
 // Mode 2, D column -> E column (kept rows).  The oversampled theta transform is
 // split by output parity: with nh = n1 / 2 and the spectrum c_k, |k| <= lmax,
@@ -378,9 +426,16 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fh);
-    for (int i = tid; i < nh; i += NT)
-        if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
-            ec[2 * i + 1] = X[lds_pos(fh.perm[i], sh)];
+    // the odd rows wait in registers (in place of ye) until the even rows are done,
+    // so that rows 2i and 2i + 1 leave as one contiguous store
+    C od[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        od[v].x = od[v].y = 0;
+        if (i < nh)
+            od[v] = X[lds_pos(fh.perm[i], sh)];
+    }
     __syncthreads();
     // even rows
 #pragma unroll
@@ -391,14 +446,16 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fh);
-    for (int i = tid; i < nh; i += NT)
-        if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
-            ec[2 * i] = X[lds_pos(fh.perm[i], sh)];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh)
+            store_rows(ec, i, X[lds_pos(fh.perm[i], sh)], od[v], a);
+    }
 }
 
 // Mode 2, E column (kept rows; the rest counts as zero) -> D column: the transpose
-// of column_fwd_half_kernel (odd rows first, then even rows, each read straight
-// from E into LDS).
+// of column_fwd_half_kernel (odd rows first, then even rows).
 template <typename T, int NT>
 __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kernel(
     const typename cx<T>::type *__restrict__ E, typename cx<T>::type *__restrict__ D, ColArgs a,
@@ -422,13 +479,18 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
             kh += nh;
         return (k < 0 ? -k : k) <= a.lmax;
     };
-    // odd rows
-    for (int i = tid; i < nh; i += NT) {
-        C v;
-        v.x = v.y = 0;
-        if (row_kept(2 * i + 1, a.n1, a.nrows, a.a_min))
-            v = ec[2 * i + 1];
-        X[lds_pos(i, sh)] = v;
+    // rows 2i and 2i + 1 arrive as one load; the odd rows go first, the even rows
+    // wait in registers
+    C ev[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        ev[v].x = ev[v].y = 0;
+        if (i < nh) {
+            C od;
+            load_rows(ec, i, ev[v], od, a);
+            X[lds_pos(i, sh)] = od;
+        }
     }
     __syncthreads();
     lds_fft<C, -1, NT>(X, fh);
@@ -443,12 +505,11 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kerne
     }
     __syncthreads();
     // even rows
-    for (int i = tid; i < nh; i += NT) {
-        C v;
-        v.x = v.y = 0;
-        if (row_kept(2 * i, a.n1, a.nrows, a.a_min))
-            v = ec[2 * i];
-        X[lds_pos(i, sh)] = v;
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        const int i = tid + v * NT;
+        if (i < nh)
+            X[lds_pos(i, sh)] = ev[v];
     }
     __syncthreads();
     lds_fft<C, -1, NT>(X, fh);
@@ -620,6 +681,8 @@ hipError_t column_set_lds(const gsht_plan &p)
 }
 
 int column_half_maxn(int prec) { return prec == GSHT_F64 ? col_half_maxn<double>() : col_half_maxn<float>(); }
+
+int column_max_radix(int) { return COL_MAXR; }
 
 size_t column_lds_bytes(const gsht_plan &p)
 {

@@ -41,6 +41,7 @@ struct LegendreTables {
 // plan's precision at tw + twoff[p] + j (r - 1) + q - 1; perm[k] = LDS position of
 // frequency k after the last pass (digit reversal).
 constexpr int COL_MAXP = 16;
+
 struct ColFFT {
     int n = 0, npass = 0;
     int psh = 31;  // LDS padding: one free slot after every 2^psh elements (31: none)
@@ -108,6 +109,9 @@ struct gsht_plan {
     bool points_ok = false;
     double eps = 0;
     int prec = GSHT_F64;
+    // FP64 spreading in the fast fixed-point form (quantisation step 2^-50 of each
+    // chunk's value bound; exact form 2^-63)
+    bool spread_fast = false;
     int64_t nalm = 0;
     // grids
     int ntheta = 0, nd = 0, n1 = 0, n2 = 0, w = 0;
@@ -228,6 +232,7 @@ hipError_t launch_fill_real(void *ptr, double value, int64_t n, int prec, hipStr
 // ---- per-column FFT stage (colfft.hip) ------------------------------------
 hipError_t column_set_lds(const gsht_plan &p);                    // once per plan
 int column_half_maxn(int prec);  // largest nd or n1 / 2 of mode 2
+int column_max_radix(int prec);  // largest radix the in-LDS transforms are built with
 size_t column_lds_bytes(const gsht_plan &p);  // LDS per workgroup of the plan's mode
 hipError_t launch_column_fwd(const gsht_plan &p, hipStream_t s);  // D -> E
 hipError_t launch_column_adj(const gsht_plan &p, hipStream_t s);  // E -> D

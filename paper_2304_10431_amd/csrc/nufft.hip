@@ -690,20 +690,47 @@ __global__ __launch_bounds__(NUFFT_THREADS) void interp_deriv_kernel(
     }
 }
 
+// Rounding by the magic constant M = 1.5 2^52: for |x| < 2^51 the double x + M has
+// exponent 52, so its bits read as a 64-bit integer are KM + round(x) (round to
+// nearest even), with KM = bits(M) = 0x4338000000000000, which is zero below bit 51.
+// fma(a, b, M) rounds the exact product a b once.  The low 32 bits are round(x) mod
+// 2^32, and a sum of such words carries the KM terms only in bits 51 and up.
+constexpr double QMAGIC = 6755399441055744.0;
+constexpr unsigned int QMAGIC_HI = 0x43380000u;  // KMhi: bits 32..63 of KM
+__device__ inline unsigned long long qbits(double a, double b)
+{
+    return (unsigned long long)__double_as_longlong(fma(a, b, QMAGIC));
+}
+
 // Fixed-point accumulator of the spreading patch: on gfx950 integer LDS atomic adds
 // run 3.6x (u32) / 2x (u64) faster than FP64 ones and 26x faster than FP32 ones.
-template <typename T> struct SpreadAcc;
-template <> struct SpreadAcc<float> {
+// quant(a, b) is round(a b) in the accumulator's word; total(t) reads a cell sum back.
+// FP32 grids: 32-bit words, step S / 2^31.  FP64 grids, exact form (FQ = false):
+// 64-bit words, step S / 2^63, converted by the library's double -> int64 rounding.
+// FP64, fast form (FQ = true): step S / 2^50, every cell sum stays within 2^50 in
+// magnitude, so the low 51 bits of the sum of magic-rounded words are the sum
+// itself (sign-extended) whatever the KM terms did above them: one FMA per word.
+template <typename T, bool FQ> struct SpreadAcc;
+template <bool FQ> struct SpreadAcc<float, FQ> {
     using U = unsigned int;
     using S = int;
     static constexpr double RANGE = 0x1p31;
-    __device__ static U quant(double q) { return (U)__double2int_rn(q); }
+    __device__ static U quant(double a, double b) { return (U)qbits(a, b); }
+    __device__ static S total(U t) { return (S)t; }
 };
-template <> struct SpreadAcc<double> {
+template <> struct SpreadAcc<double, false> {
     using U = unsigned long long;
     using S = long long;
     static constexpr double RANGE = 0x1p63;
-    __device__ static U quant(double q) { return (U)__double2ll_rn(q); }
+    __device__ static U quant(double a, double b) { return (U)__double2ll_rn(a * b); }
+    __device__ static S total(U t) { return (S)t; }
+};
+template <> struct SpreadAcc<double, true> {
+    using U = unsigned long long;
+    using S = long long;
+    static constexpr double RANGE = 0x1p50;
+    __device__ static U quant(double a, double b) { return qbits(a, b); }
+    __device__ static S total(U t) { return (S)(t << 13) >> 13; }
 };
 
 // Type-1 spreading of one chunk.  The chunk's patch accumulates in fixed point: every
@@ -748,14 +775,14 @@ template <typename T, bool CPLX> struct SpreadPack {
     static constexpr bool value = CPLX && std::is_same<T, float>::value;
 };
 
-template <typename T, int W, bool CPLX, bool ATOMIC>
+template <typename T, int W, bool CPLX, bool ATOMIC, bool FQ>
 __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
                                     const double *__restrict__ sph,
                                     const int32_t *__restrict__ perm, const T *__restrict__ in,
                                     const GridGeom &g, T beta, T *__restrict__ grid,
-                                    typename SpreadAcc<T>::U *patch, double *wsum)
+                                    typename SpreadAcc<T, FQ>::U *patch, double *wsum)
 {
-    using A = SpreadAcc<T>;
+    using A = SpreadAcc<T, FQ>;
     using U = typename A::U;
     constexpr bool PACK = SpreadPack<T, CPLX>::value;
     constexpr int NC = CPLX ? 2 : 1;
@@ -821,17 +848,23 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
                     reinterpret_cast<unsigned long long *>(patch) + (lr + i) * g.ps + lc;
 #pragma unroll
                 for (int j = 0; j < W; ++j) {
-                    const long long qr = __double2int_rn(fr * dy[j]);
-                    const long long qi = __double2int_rn(fi * dy[j]);
-                    atomicAdd(rowp + j, ((unsigned long long)qr << 32) + (unsigned long long)qi);
+                    // Re 2^32 + Im: the low word is round(Im); the high word takes
+                    // round(Re) plus the sign extension of round(Im), which is the
+                    // high word of its magic-rounded bits minus KMhi = KM / 2^32
+                    // (rounding Re with the constant M - 2^32 KMhi leaves the
+                    // subtraction in its low word)
+                    const unsigned long long br = (unsigned long long)__double_as_longlong(
+                        fma(fr, dy[j], QMAGIC - (double)QMAGIC_HI));
+                    const unsigned long long bi = qbits(fi, dy[j]);
+                    atomicAdd(rowp + j, bi + (br << 32));
                 }
             } else {
                 U *rowp = patch + (lr + i) * g.ps + lc;
 #pragma unroll
                 for (int j = 0; j < W; ++j) {
-                    atomicAdd(rowp + j, A::quant(fr * dy[j]));
+                    atomicAdd(rowp + j, A::quant(fr, dy[j]));
                     if constexpr (CPLX)
-                        atomicAdd(rowp + plane + j, A::quant(fi * dy[j]));
+                        atomicAdd(rowp + plane + j, A::quant(fi, dy[j]));
                 }
             }
         }
@@ -854,8 +887,8 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
             qi = (int)(unsigned int)(t & 0xffffffffll);
             qr = (int)((t - (long long)qi) >> 32);
         } else {
-            qr = (typename A::S)patch[pidx];
-            qi = CPLX ? (typename A::S)patch[plane + pidx] : 0;
+            qr = A::total(patch[pidx]);
+            qi = CPLX ? A::total(patch[plane + pidx]) : 0;
         }
         if (ATOMIC) {
             if (qr != 0)
@@ -878,7 +911,7 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
 }
 
 // One workgroup per chunk, atomic flush (any grid).
-template <typename T, int W, bool CPLX>
+template <typename T, int W, bool CPLX, bool FQ>
 __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
     const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
     const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
@@ -886,15 +919,16 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
 {
     extern __shared__ unsigned char smem_raw[];
     __shared__ double wsum[NUFFT_THREADS / 64];
-    spread_chunk<T, W, CPLX, true>(chunks[blockIdx.x], sth, sph, perm, in, g, beta, grid,
-                                   reinterpret_cast<typename SpreadAcc<T>::U *>(smem_raw), wsum);
+    spread_chunk<T, W, CPLX, true, FQ>(chunks[blockIdx.x], sth, sph, perm, in, g, beta, grid,
+                                       reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw),
+                                       wsum);
 }
 
 // One workgroup per tile of one colour (all of the tile's chunks in turn), plain
 // read-add-write flush: tiles of one colour are at least two tiles apart in both
 // directions and a patch reaches only W - 1 cells beyond its tile, so their
 // patches are disjoint.  items[i] = (first chunk, number of chunks).
-template <typename T, int W, bool CPLX>
+template <typename T, int W, bool CPLX, bool FQ>
 __global__ __launch_bounds__(NUFFT_THREADS) void spread_tile_kernel(
     const int2 *__restrict__ items, const int4 *__restrict__ chunks,
     const double *__restrict__ sth, const double *__restrict__ sph,
@@ -905,9 +939,9 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_tile_kernel(
     __shared__ double wsum[NUFFT_THREADS / 64];
     const int2 it = items[blockIdx.x];
     for (int c = 0; c < it.y; ++c)
-        spread_chunk<T, W, CPLX, false>(chunks[it.x + c], sth, sph, perm, in, g, beta, grid,
-                                        reinterpret_cast<typename SpreadAcc<T>::U *>(smem_raw),
-                                        wsum);
+        spread_chunk<T, W, CPLX, false, FQ>(chunks[it.x + c], sth, sph, perm, in, g, beta, grid,
+                                            reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw),
+                                            wsum);
 }
 
 static GridGeom make_geom(const gsht_plan &p)
@@ -987,41 +1021,54 @@ static hipError_t interp_deriv_w(const gsht_plan &p, const DerivOut &o, hipStrea
     return hipGetLastError();
 }
 
-template <typename T, int W>
-static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
+template <typename T, int W, bool FQ>
+static hipError_t spread_wq(const gsht_plan &p, const void *map, hipStream_t s)
 {
     const GridGeom g = make_geom(p);
     const int PR = p.t1 + W - 1, PS = p.t2 + W - 1;
+    using U = typename SpreadAcc<T, FQ>::U;
     if (p.ncolors > 0) {
-        const size_t sm = (size_t)PR * PS * (p.spin ? 2 : 1) * sizeof(typename SpreadAcc<T>::U);
+        const size_t sm = (size_t)PR * PS * (p.spin ? 2 : 1) * sizeof(U);
         for (int c = 0; c < p.ncolors; ++c) {
             const int n = p.color_start[c + 1] - p.color_start[c];
             if (n == 0)
                 continue;
             const int2 *items = p.tile_items + p.color_start[c];
             if (p.spin)
-                hipLaunchKernelGGL((spread_tile_kernel<T, W, true>), dim3((unsigned)n),
+                hipLaunchKernelGGL((spread_tile_kernel<T, W, true, FQ>), dim3((unsigned)n),
                                    dim3(NUFFT_THREADS), sm, s, items, p.chunks, p.sth, p.sph,
                                    p.perm, (const T *)map, g, (T)p.beta, (T *)p.G);
             else
-                hipLaunchKernelGGL((spread_tile_kernel<T, W, false>), dim3((unsigned)n),
+                hipLaunchKernelGGL((spread_tile_kernel<T, W, false, FQ>), dim3((unsigned)n),
                                    dim3(NUFFT_THREADS), sm, s, items, p.chunks, p.sth, p.sph,
                                    p.perm, (const T *)map, g, (T)p.beta, (T *)p.g);
         }
         return hipGetLastError();
     }
     if (p.spin) {
-        const size_t sm = (size_t)PR * PS * 2 * sizeof(typename SpreadAcc<T>::U);
-        hipLaunchKernelGGL((spread_kernel<T, W, true>), dim3((unsigned)p.nchunks),
+        const size_t sm = (size_t)PR * PS * 2 * sizeof(U);
+        hipLaunchKernelGGL((spread_kernel<T, W, true, FQ>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.G);
     } else {
-        const size_t sm = (size_t)PR * PS * sizeof(typename SpreadAcc<T>::U);
-        hipLaunchKernelGGL((spread_kernel<T, W, false>), dim3((unsigned)p.nchunks),
+        const size_t sm = (size_t)PR * PS * sizeof(U);
+        hipLaunchKernelGGL((spread_kernel<T, W, false, FQ>), dim3((unsigned)p.nchunks),
                            dim3(NUFFT_THREADS), sm, s, p.chunks, p.sth, p.sph, p.perm,
                            (const T *)map, g, (T)p.beta, (T *)p.g);
     }
     return hipGetLastError();
+}
+
+// FP32 grids always take the magic rounding; FP64 grids take it where the plan's
+// accuracy allows (gsht_plan::spread_fast).
+template <typename T, int W>
+static hipError_t spread_w(const gsht_plan &p, const void *map, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 8) {
+        if (!p.spread_fast)
+            return spread_wq<T, W, false>(p, map, s);
+    }
+    return spread_wq<T, W, true>(p, map, s);
 }
 
 #define GSHT_W_CASES(F, T)                                                                       \
