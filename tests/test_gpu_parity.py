@@ -356,6 +356,31 @@ def test_spreading_by_tile_colour(G, monkeypatch, lmax, mmax, spin, npts, prec, 
     assert oracle.eps_eff(outs[0] * w, ref * w) <= eps
 
 
+@pytest.mark.parametrize("lmax,mmax,spin,npts,eps", [
+    (130, 130, 2, 30000, 1e-10), (200, 150, 0, 20000, 1e-10), (64, 64, 1, 9000, 1e-8)])
+def test_fp64_spreading_fast_and_exact_forms(G, monkeypatch, lmax, mmax, spin, npts, eps):
+    """FP64 spreading in its two fixed-point forms (step 2^-50 and 2^-63 of a chunk's
+    value bound): the adjoints agree far below epsilon and both meet it against the
+    oracle."""
+    say("spread quantisation", lmax, mmax, spin, npts, eps)
+    rng = np.random.default_rng(950 + lmax)
+    th, ph = wl.uniform_sphere(npts, rng)
+    y = rng.standard_normal((oracle.ncomp(spin), npts))
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    outs = []
+    for form in ("exact", "fast"):
+        monkeypatch.setenv("GSHT_SPREAD_QUANT", form)
+        plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, "f64")
+        outs.append(plan.adjoint(dev(y)).cpu().numpy())
+        plan.close()
+    d = rel_l2(outs[1] * w, outs[0] * w)
+    say("  fast vs exact: %.2e" % d)
+    assert d <= 1e-12
+    ref = oracle.adjoint(y, lmax, mmax, spin, th, ph)
+    for o in outs:
+        assert oracle.eps_eff(o * w, ref * w) <= eps
+
+
 @pytest.mark.parametrize("lmax,mmax,spin,prec", [(130, 130, 2, "f64"), (512, 400, 1, "f32"),
                                                  (47, 47, 0, "f32")])
 def test_lds_padding_is_bitwise_neutral(G, monkeypatch, lmax, mmax, spin, prec):
