@@ -612,10 +612,14 @@ def main():
     for k, v in results.items():
         e = roofline_entry("spread", k, v, spec, npts, args.workload)
         if e is not None:
+            # patch word updates of point-by-point spreading (w^2 cells per point; FP64
+            # complex cells are two words, FP32 complex cells one packed word); FP64
+            # couples of neighbouring points issue fewer LDS atomics than this
             w = v["info"]["w"]
-            atomics = npts * w * w * ncomp
-            e["lds_atomics_per_launch"] = atomics
-            e["lds_atomic_gops"] = atomics / (e["avg_launch_ms"] / 1e3) / 1e9
+            words = ncomp if k.startswith("f64") else 1
+            upd = npts * w * w * words
+            e["patch_words_point_by_point"] = upd
+            e["patch_word_rate_g_per_s"] = upd / (e["avg_launch_ms"] / 1e3) / 1e9
             out["spreading"][k] = e
     if "f64_eps1e-05" in results and f32:
         out["speedup_f32_vs_f64_eps1e-5"] = results["f64_eps1e-05"]["s_per_step"] / f32["s_per_step"]

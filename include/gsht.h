@@ -414,6 +414,8 @@ typedef struct {
     double sigma;       /* nominal oversampling factor (2, 1.5 or 1.25); n1 and n2 are
                            the FFT-friendly lengths at least about sigma (2 lmax + 1) and
                            sigma (2 mmax + 1) */
+    int cell_sort;      /* 1: within a tile, points are ordered by their first kernel cell
+                           (see gsht_plan_get_sort); 0: by input order */
 } gsht_plan_info;
 
 /* Fill *info from a plan (host only). */
@@ -421,12 +423,14 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info);
 
 /*
  * Copy the plan's bin sort out to caller device buffers:
- *   perm        int32 [npts]: perm[k] = input index of the k-th point in tile order
+ *   perm        int32 [npts]: perm[k] = input index of the k-th point in sort order
  *               (stable: ties keep input order);
  *   tile_start  int32 [ntile1 * ntile2 + 1]: first sorted position of each tile.
  * Tile key of a point: u = theta * (n1 / (2 pi)), v = phi * (n2 / (2 pi)) (single
- * rounded FP64 products), a0 = ceil(u - w/2), b0 = ceil(v - w/2),
- * key = ((a0 - a_min) / tile1) * ntile2 + ((b0 mod n2) / tile2).
+ * rounded FP64 products), a0 = ceil(u - w/2), b0 = ceil(v - w/2), r = a0 - a_min,
+ * c = b0 mod n2, tile = (r / tile1) * ntile2 + (c / tile2).  With info.cell_sort the
+ * sort key is tile * tile1 * tile2 + (r mod tile1) * tile2 + (c mod tile2) (points of
+ * a tile by first kernel cell, row-major), otherwise the tile.
  */
 int gsht_plan_get_sort(const gsht_plan *p, int32_t *perm, int32_t *tile_start, void *hip_stream);
 

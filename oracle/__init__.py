@@ -211,13 +211,16 @@ def alm_inner(x, y, lmax: int, mmax: int) -> float:
 
 # ---- bin sort definition (integer; no paper counterpart) -------------------
 
-def bin_keys(theta, phi, n1: int, n2: int, w: int, a_min: int, t1: int, t2: int, ntile2: int):
+def bin_keys(theta, phi, n1: int, n2: int, w: int, a_min: int, t1: int, t2: int, ntile2: int,
+             cells: bool = False):
     """Tile key of each point.
 
     u = theta * (n1 / (2 pi)) and v = phi * (n2 / (2 pi)) are single-rounded FP64
     products; the first kernel cell is a0 = ceil(u - w/2), b0 = ceil(v - w/2);
     the row offset r0 = a0 - a_min and the column b0 mod n2 give the tile
     (r0 // t1, (b0 mod n2) // t2), flattened row-major with ntile2 tile columns.
+    With cells, the key orders a tile's points by that first cell too:
+    tile * t1 * t2 + (r0 mod t1) * t2 + ((b0 mod n2) mod t2).
     """
     th = np.asarray(theta, dtype=np.float64)
     ph = np.asarray(phi, dtype=np.float64)
@@ -230,15 +233,19 @@ def bin_keys(theta, phi, n1: int, n2: int, w: int, a_min: int, t1: int, t2: int,
     b0 = np.ceil(v - half).astype(np.int64)
     r0 = a0 - a_min
     bm = np.mod(b0, n2)
-    return (r0 // t1) * ntile2 + bm // t2
+    tile = (r0 // t1) * ntile2 + bm // t2
+    if cells:
+        return tile * (t1 * t2) + (r0 % t1) * t2 + bm % t2
+    return tile
 
 
-def binsort(keys, ntiles: int):
-    """Stable counting sort: (perm, tile_start) with perm = argsort(keys, stable)
-    and tile_start[t] = number of points with key < t (length ntiles + 1)."""
+def binsort(keys, ntiles: int, keys_per_tile: int = 1):
+    """Stable sort: (perm, tile_start) with perm = argsort(keys, stable) and
+    tile_start[t] = number of points whose tile key // keys_per_tile is < t
+    (length ntiles + 1)."""
     k = np.asarray(keys, dtype=np.int64)
     perm = np.argsort(k, kind="stable").astype(np.int32)
-    counts = np.bincount(k, minlength=ntiles)
+    counts = np.bincount(k // keys_per_tile, minlength=ntiles)
     start = np.zeros(ntiles + 1, dtype=np.int64)
     start[1:] = np.cumsum(counts)
     return perm, start.astype(np.int32)

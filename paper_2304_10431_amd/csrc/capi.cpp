@@ -391,6 +391,11 @@ void choose_sizes(gsht_plan *p)
     p->nt1 = (p->nrows + p->t1 - 1) / p->t1;
     p->nt2 = (p->n2 + p->t2 - 1) / p->t2;
     p->ntiles = (int64_t)p->nt1 * p->nt2;
+    // order the points of a tile by their first kernel cell when the keys fit int32
+    // (GSHT_CELL_SORT=0 keeps tile order for testing)
+    p->cell_sort = p->ntiles * p->t1 * p->t2 < ((int64_t)1 << 31);
+    if (const char *e = getenv("GSHT_CELL_SORT"))
+        p->cell_sort = p->cell_sort && atoi(e) != 0;
     p->ncol = p->spin ? 2 * p->mmax + 1 : p->mmax + 1;
     p->npairs = (p->ntheta + 1) / 2;
 }
@@ -716,9 +721,9 @@ int plan_create_impl(gsht_plan **out, int lmax, int mmax, int spin, const double
     {
         // tile edge: the colour-ordered spreading needs patches (tile + w - 1 cells) that
         // reach at most one tile beyond their own, and each patch (16 bytes per cell in
-        // FP64, 8 in FP32) must fit a workgroup's LDS
+        // FP64, 8 in FP32) must fit a workgroup's LDS beside the spreading's staging
         const int t = p->t1, pe = t + p->w - 1;
-        const size_t patch = (size_t)pe * pe * (prec == GSHT_F64 ? 16 : 8);
+        const size_t patch = (size_t)pe * pe * (prec == GSHT_F64 ? 16 : 8) + SPREAD_STAGE_BYTES;
         if (t < 16 || t > 128 || t < p->w - 1 || patch > COL_MAX_BYTES) {
             delete p;
             return fail(GSHT_EINVAL, "tile edge %d is not possible with kernel support %d "
@@ -1820,6 +1825,7 @@ int gsht_plan_get_info(const gsht_plan *p, gsht_plan_info *info)
     info->workspace_bytes = p->workspace_bytes;
     info->column_mode = p->colmode;
     info->spread_colors = p->ncolors;
+    info->cell_sort = p->cell_sort ? 1 : 0;
     info->syn_r = p->syn_r;
     info->adj_r = p->adj_r;
     info->adj_b = p->adj_b;

@@ -65,6 +65,8 @@ __host__ __device__ inline int lds_pos(int i, int sh) { return i + (i >> sh); }
 __host__ __device__ inline int lds_pad_n(int n, int sh) { return sh >= 31 ? n : n + (n >> sh) + 1; }
 // Largest LDS buffer a column workgroup may use.
 constexpr size_t COL_MAX_BYTES = 163840;
+// static LDS of a spreading workgroup beside its patch (work lists and sums)
+constexpr size_t SPREAD_STAGE_BYTES = 2048;
 
 enum Stage {
     ST_PREP = 0,
@@ -112,6 +114,9 @@ struct gsht_plan {
     // FP64 spreading in the fast fixed-point form (quantisation step 2^-50 of each
     // chunk's value bound; exact form 2^-63)
     bool spread_fast = false;
+    // points sorted by tile and, within a tile, by first kernel cell (row, then
+    // column); needs ntiles t1 t2 < 2^31 (int32 keys)
+    bool cell_sort = false;
     int64_t nalm = 0;
     // grids
     int ntheta = 0, nd = 0, n1 = 0, n2 = 0, w = 0;

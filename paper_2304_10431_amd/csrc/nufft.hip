@@ -38,6 +38,7 @@ constexpr double PHI_MAX = 1048576.0;
 struct KeyParams {
     double c1, c2, half;
     int a_min, n2, t1, t2, nt2, nrows, w;
+    int cells;  // key within the tile too: tile t1 t2 + row t2 + column (cell order)
 };
 
 // First kernel cell of a point.  u = theta c1 and v = phi c2 are single-rounded
@@ -87,6 +88,8 @@ __global__ void keys_kernel(const double *__restrict__ theta, const double *__re
     } else {
         const Cell c = point_cell(th, ph, kp.c1, kp.c2, kp.half, kp.a_min, kp.n2, kp.nrows, kp.w);
         key = (c.r0 / kp.t1) * kp.nt2 + c.bi / kp.t2;
+        if (kp.cells)
+            key = key * (kp.t1 * kp.t2) + (c.r0 % kp.t1) * kp.t2 + c.bi % kp.t2;
     }
     keys[i] = key;
     vals[i] = (int32_t)i;
@@ -244,15 +247,15 @@ __global__ __launch_bounds__(SORT_THREADS) void radix_scatter_kernel(
     }
 }
 
-// tile_start[t] = first sorted position with key >= t.
+// tile_start[t] = first sorted position whose tile (key / cpt, cpt keys per tile) is >= t.
 __global__ void tile_start_kernel(const int32_t *__restrict__ skeys, int64_t n, int64_t ntiles,
-                                  int32_t *__restrict__ start)
+                                  int cpt, int32_t *__restrict__ start)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > n)
         return;
-    const int64_t lo = (p == 0) ? 0 : (int64_t)skeys[p - 1] + 1;
-    const int64_t hi = (p == n) ? ntiles : (int64_t)skeys[p];
+    const int64_t lo = (p == 0) ? 0 : (int64_t)(skeys[p - 1] / cpt) + 1;
+    const int64_t hi = (p == n) ? ntiles : (int64_t)(skeys[p] / cpt);
     for (int64_t t = lo; t <= hi; ++t)
         start[t] = (int32_t)p;
 }
@@ -328,11 +331,13 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
         kp.nt2 = p.nt2;
         kp.nrows = p.nrows;
         kp.w = p.w;
+        kp.cells = p.cell_sort ? 1 : 0;
         hipLaunchKernelGGL(keys_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, theta, phi, n, kp, k0,
                            v0, inval);
         if ((e = hipGetLastError()) != hipSuccess) goto out;
+        const int64_t nkeys = p.ntiles * (p.cell_sort ? (int64_t)p.t1 * p.t2 : 1);
         int bits = 1;
-        while (bits < 31 && ((int64_t)1 << bits) < p.ntiles)
+        while (bits < 31 && ((int64_t)1 << bits) < nkeys)
             ++bits;
         for (int shift = 0; shift < bits; shift += RADIX_BITS) {
             hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nblocks), dim3(SORT_THREADS), 0, s,
@@ -346,7 +351,7 @@ hipError_t run_binsort(gsht_plan &p, const double *theta, const double *phi, hip
         }
     }
     hipLaunchKernelGGL(tile_start_kernel, dim3(nblk(n + 1, 256)), dim3(256), 0, s, k0, n, p.ntiles,
-                       p.tile_start);
+                       p.cell_sort ? p.t1 * p.t2 : 1, p.tile_start);
     if ((e = hipMemcpyAsync(p.perm, v0, nn * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess) goto out;
     if (n > 0) {
         hipLaunchKernelGGL(gather_coords_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, theta, phi,
@@ -711,11 +716,20 @@ __device__ inline unsigned long long qbits(double a, double b)
 // magnitude, so the low 51 bits of the sum of magic-rounded words are the sum
 // itself (sign-extended) whatever the KM terms did above them: one FMA per word.
 template <typename T, bool FQ> struct SpreadAcc;
+// quant2(a1, b1, a2, b2) rounds a1 b1 + a2 b2 (two points' contributions to one cell).
+__device__ inline unsigned long long qbits2(double a1, double b1, double a2, double b2)
+{
+    return (unsigned long long)__double_as_longlong(fma(a2, b2, fma(a1, b1, QMAGIC)));
+}
 template <bool FQ> struct SpreadAcc<float, FQ> {
     using U = unsigned int;
     using S = int;
     static constexpr double RANGE = 0x1p31;
     __device__ static U quant(double a, double b) { return (U)qbits(a, b); }
+    __device__ static U quant2(double a1, double b1, double a2, double b2)
+    {
+        return (U)qbits2(a1, b1, a2, b2);
+    }
     __device__ static S total(U t) { return (S)t; }
 };
 template <> struct SpreadAcc<double, false> {
@@ -723,6 +737,10 @@ template <> struct SpreadAcc<double, false> {
     using S = long long;
     static constexpr double RANGE = 0x1p63;
     __device__ static U quant(double a, double b) { return (U)__double2ll_rn(a * b); }
+    __device__ static U quant2(double a1, double b1, double a2, double b2)
+    {
+        return (U)__double2ll_rn(fma(a2, b2, a1 * b1));
+    }
     __device__ static S total(U t) { return (S)t; }
 };
 template <> struct SpreadAcc<double, true> {
@@ -730,6 +748,10 @@ template <> struct SpreadAcc<double, true> {
     using S = long long;
     static constexpr double RANGE = 0x1p50;
     __device__ static U quant(double a, double b) { return qbits(a, b); }
+    __device__ static U quant2(double a1, double b1, double a2, double b2)
+    {
+        return qbits2(a1, b1, a2, b2);
+    }
     __device__ static S total(U t) { return (S)(t << 13) >> 13; }
 };
 
@@ -737,25 +759,25 @@ template <> struct SpreadAcc<double, true> {
 // contribution y w_i w_j is scaled by RANGE (1 - 2^-20) / S with S = sum over the
 // chunk's points of |Re y| + |Im y|, which bounds every cell sum, so the
 // two's-complement integer adds never wrap; the quantisation step is S / RANGE
-// (2^-31 S for FP32, 2^-63 S for FP64).  The lanes of one atomic instruction visit
-// the chunk's points st apart in sorted order (see spread_stride).  FP32 complex
+// (2^-31 S for FP32, 2^-63 or 2^-50 S for FP64, see SpreadAcc).  Couples of
+// neighbouring points go as one window (SPREAD_GAP), the rest one by one; the lanes
+// of one atomic instruction visit the couples, then the single points, st apart (see
+// spread_stride).  FP32 complex
 // grids keep both parts of a cell in one 64-bit word, Re 2^32 + Im (as integers):
 // integer addition is exact and associative, and each part's sum stays within
 // 32-bit range, so the word's low 32 bits (read as signed) are the sum of the
 // imaginary parts and the rest, shifted down, that of the real parts -- one atomic
 // per tap and cell instead of two, with the same sums.  FP64 keeps the parts in
 // separate planes (row stride g.ps cells).  The points' values are read once (they
-// give S and are then spread from registers).  Non-zero cells are then added to the
+// give S and are then spread from LDS).  Non-zero cells are then added to the
 // grid: with global atomics (ATOMIC), or with plain read-add-write when no other
 // workgroup can touch the patch at the same time (tiles launched by colour).
-constexpr int SPREAD_PER_THREAD = CHUNK / NUFFT_THREADS;
-static_assert(SPREAD_PER_THREAD * NUFFT_THREADS == CHUNK, "chunk points per thread");
 
 // Visit order of a chunk's points: slot k takes point (k st) mod n with st the first
 // odd number from SPREAD_STRIDE on that is coprime to n (a permutation of the chunk).
-// Neighbouring points of a ring often fall into the same cell once deflected, and
-// lanes of one atomic instruction on the same address are serialised; lanes st
-// points apart rarely share a cell.
+// Points next to each other in sorted (cell) order often share a cell, and lanes of
+// one atomic instruction on the same address are serialised; lanes st points apart
+// rarely share a cell.
 constexpr int SPREAD_STRIDE = 97;
 __device__ inline int spread_stride(int n)
 {
@@ -775,30 +797,51 @@ template <typename T, bool CPLX> struct SpreadPack {
     static constexpr bool value = CPLX && std::is_same<T, float>::value;
 };
 
-template <typename T, int W, bool CPLX, bool ATOMIC, bool FQ>
-__device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
-                                    const double *__restrict__ sph,
-                                    const int32_t *__restrict__ perm, const T *__restrict__ in,
-                                    const GridGeom &g, T beta, T *__restrict__ grid,
-                                    typename SpreadAcc<T, FQ>::U *patch, double *wsum)
+// Points of a chunk in cell order are mostly one or two cells apart along a row.
+// Couples of sorted points (2t, 2t + 1) whose first kernel cells share the row and lie
+// at most SPREAD_GAP columns apart are spread as one window of W rows by
+// W + gap columns (each cell takes both contributions in one atomic word); the other
+// points are spread one by one.
+constexpr int SPREAD_GAP = 2;
+
+// Waves per SIMD the spreading kernels are compiled for: a 128-register budget
+// (FP64 w = 15 needs 135 registers without it; four waves per SIMD instead of three
+// took its spreading from 7.24 to 6.41 ms at the benchmark).
+constexpr int SPREAD_WAVES = 4;
+
+// Per-chunk staging of the spreading (static LDS beside the patch).
+struct SpreadStage {
+    short pairs[NUFFT_THREADS];            // couples spread as one window
+    short singles[CHUNK];                  // points spread on their own
+    int cnt[2 * (NUFFT_THREADS / 64)];     // per wave: couples, single points
+    double wsum[NUFFT_THREADS / 64];       // per wave: partial bound S
+};
+static_assert(sizeof(SpreadStage) <= SPREAD_STAGE_BYTES, "spreading stage within its LDS budget");
+
+// One point per lane at a time: the points' values are read once (they give S and
+// are then spread from registers); the lanes of one atomic instruction visit the
+// chunk's points st apart in sorted order.  Returns false (nothing spread) when the
+// chunk's values are all zero or not finite.
+template <typename T, int W, bool CPLX, bool FQ>
+__device__ inline bool spread_single(int4 ck, const double *__restrict__ sth,
+                                     const double *__restrict__ sph,
+                                     const int32_t *__restrict__ perm, const T *__restrict__ in,
+                                     const GridGeom &g, T beta, typename SpreadAcc<T, FQ>::U *patch,
+                                     double *wsum, int row0, int col0, double &scale)
 {
     using A = SpreadAcc<T, FQ>;
     using U = typename A::U;
     constexpr bool PACK = SpreadPack<T, CPLX>::value;
-    constexpr int NC = CPLX ? 2 : 1;
-    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
-    const int row0 = tr * g.t1, col0 = tc * g.t2;
-    const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
-    const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
+    constexpr int PER = CHUNK / NUFFT_THREADS;
+    const int PR = g.t1 + W - 1;
+    const int plane = PR * g.ps;
     const int n = ck.z - ck.y;
-    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
-        patch[idx] = 0;
     // the chunk's values (read once) and the bound S of every cell sum
     const int st = n > 1 ? spread_stride(n) : 1;
-    double yr[SPREAD_PER_THREAD], yi[SPREAD_PER_THREAD];
+    double yr[PER], yi[PER];
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < SPREAD_PER_THREAD; ++q) {
+    for (int q = 0; q < PER; ++q) {
         const int k = threadIdx.x + q * NUFFT_THREADS;
         yr[q] = yi[q] = 0.0;
         if (k < n) {
@@ -821,11 +864,11 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
         S += wsum[w];
     __syncthreads();  // wsum is reused by the next chunk of the same workgroup
     if (!(S > 0.0) || !isfinite(S))
-        return;  // nothing (finite) to spread; uniform over the block
-    const double scale = A::RANGE * (1.0 - 0x1p-20) / S;
+        return false;  // nothing (finite) to spread; uniform over the block
+    scale = A::RANGE * (1.0 - 0x1p-20) / S;
     // one rolled loop (a copy of the tap loops per point would double the code)
 #pragma unroll 1
-    for (int q = 0; q < SPREAD_PER_THREAD; ++q) {
+    for (int q = 0; q < PER; ++q) {
         const int k = threadIdx.x + q * NUFFT_THREADS;
         if (k >= n)
             break;
@@ -869,6 +912,229 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
             }
         }
     }
+    return true;
+}
+
+// Couples as one window, then the single points (values re-read from the map:
+// the preamble's reads leave them in the caches).  Returns false (nothing spread)
+// when the chunk's values are all zero or not finite.
+template <typename T, int W, bool CPLX, bool FQ>
+__device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
+                                     const double *__restrict__ sph,
+                                     const int32_t *__restrict__ perm, const T *__restrict__ in,
+                                     const GridGeom &g, T beta, typename SpreadAcc<T, FQ>::U *patch,
+                                     SpreadStage &sg, int row0, int col0, double &scale)
+{
+    using A = SpreadAcc<T, FQ>;
+    using U = typename A::U;
+    constexpr bool PACK = SpreadPack<T, CPLX>::value;
+    constexpr int NW = NUFFT_THREADS / 64;
+    constexpr int WG = W + SPREAD_GAP;
+    static_assert(2 * NUFFT_THREADS == CHUNK, "one couple of points per thread");
+    const int PR = g.t1 + W - 1;
+    const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
+    const int n = ck.z - ck.y;
+    // couple t: the chunk's points 2t and 2t + 1; the bound S of every cell sum, and
+    // whether they go as one window
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int lrc[2] = {0, 0}, lcc[2] = {0, 0};
+    bool has[2];
+    double s = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k = 2 * t + h;
+        has[h] = k < n;
+        if (has[h]) {
+            const int32_t src = perm[ck.y + k];
+            const double a = (double)in[src];
+            const double b = CPLX ? (double)in[g.npts + src] : 0.0;
+            s += fabs(a) + fabs(b);
+            const Cell c = point_cell(sth[ck.y + k], sph[ck.y + k], g.c1, g.c2, g.half, g.a_min,
+                                      g.n2, g.nrows, W);
+            lrc[h] = c.r0 - row0;
+            lcc[h] = c.bi - col0;
+        }
+    }
+    const bool pair = has[0] && has[1] && lrc[0] == lrc[1] && lcc[1] >= lcc[0] &&
+                      lcc[1] - lcc[0] <= SPREAD_GAP;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        s += __shfl_xor(s, d, 64);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long bp = __ballot(pair);
+    const unsigned long long b0 = __ballot(!pair && has[0]), b1 = __ballot(!pair && has[1]);
+    if (lane == 0) {
+        sg.wsum[wv] = s;
+        sg.cnt[wv] = __popcll(bp);
+        sg.cnt[NW + wv] = __popcll(b0) + __popcll(b1);
+    }
+    __syncthreads();
+    double S = 0.0;
+    int npair = 0, nsing = 0, opair = 0, osing = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        S += sg.wsum[w];
+        const int cp = sg.cnt[w], cs = sg.cnt[NW + w];
+        if (w < wv) {
+            opair += cp;
+            osing += cs;
+        }
+        npair += cp;
+        nsing += cs;
+    }
+    if (pair) {
+        sg.pairs[opair + __popcll(bp & below)] = (short)t;
+    } else {
+        int r = osing + __popcll(b0 & below) + __popcll(b1 & below);
+        if (has[0])
+            sg.singles[r++] = (short)(2 * t);
+        if (has[1])
+            sg.singles[r] = (short)(2 * t + 1);
+    }
+    __syncthreads();
+    if (!(S > 0.0) || !isfinite(S))
+        return false;  // nothing (finite) to spread; uniform over the block
+    scale = A::RANGE * (1.0 - 0x1p-20) / S;
+    auto value = [&](int p, double &vr, double &vi) {
+        const int32_t src = perm[p];
+        vr = (double)in[src] * scale;
+        vi = CPLX ? (double)in[g.npts + src] * scale : 0.0;
+    };
+    // windows of couples (at most one per thread), visited st apart
+    {
+        const int st = npair > 1 ? spread_stride(npair) : 1;
+        const int i = t;
+        if (i < npair) {
+            const int k = 2 * sg.pairs[(int)(((int64_t)i * st) % npair)];
+            const int pa = ck.y + k;
+            T wxa[W], wya[W], wxb[W], wyb[W];
+            int lra, lca, lrb, lcb;
+            point_weights<T, W>(sth[pa], sph[pa], g, row0, col0, beta, lra, lca, wxa, wya);
+            point_weights<T, W>(sth[pa + 1], sph[pa + 1], g, row0, col0, beta, lrb, lcb, wxb, wyb);
+            const int gap = lcb - lca;  // 0..SPREAD_GAP, same row (checked above)
+            if (lra >= 0 && lra < g.t1 && lca >= 0 && lcb < g.t2) {
+                // column weights over the window: a's at 0..W-1, b's shifted by gap
+                double da[WG], db[WG];
+#pragma unroll
+                for (int j = 0; j < WG; ++j) {
+                    da[j] = j < W ? (double)wya[j] : 0.0;
+                    double v = 0.0;
+#pragma unroll
+                    for (int gg = 0; gg <= SPREAD_GAP; ++gg)
+                        if (j - gg >= 0 && j - gg < W && gap == gg)
+                            v = (double)wyb[j - gg];
+                    db[j] = v;
+                }
+                double vra, via, vrb, vib;
+                value(pa, vra, via);
+                value(pa + 1, vrb, vib);
+#pragma unroll
+                for (int i2 = 0; i2 < W; ++i2) {
+                    const double fra = (double)wxa[i2] * vra, fia = (double)wxa[i2] * via;
+                    const double frb = (double)wxb[i2] * vrb, fib = (double)wxb[i2] * vib;
+                    // cell (lra + i2, lca) of the patch: 64-bit words when packed
+                    const int cell0 = (lra + i2) * g.ps + lca;
+                    U *rowp = patch + cell0;
+                    unsigned long long *roww = reinterpret_cast<unsigned long long *>(patch) + cell0;
+#pragma unroll
+                    for (int j = 0; j < WG; ++j) {
+                        if (j >= W && j >= W + gap)
+                            continue;  // beyond b's window
+                        if constexpr (PACK) {
+                            const unsigned long long br = (unsigned long long)__double_as_longlong(
+                                fma(frb, db[j], fma(fra, da[j], QMAGIC - (double)QMAGIC_HI)));
+                            const unsigned long long bi = (unsigned long long)__double_as_longlong(
+                                fma(fib, db[j], fma(fia, da[j], QMAGIC)));
+                            atomicAdd(roww + j, bi + (br << 32));
+                        } else {
+                            atomicAdd(rowp + j, A::quant2(fra, da[j], frb, db[j]));
+                            if constexpr (CPLX)
+                                atomicAdd(rowp + plane + j, A::quant2(fia, da[j], fib, db[j]));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // the other points one by one (one rolled loop: a copy of the tap loops per
+    // point would double the code)
+    const int st = nsing > 1 ? spread_stride(nsing) : 1;
+#pragma unroll 1
+    for (int i = t; i < nsing; i += NUFFT_THREADS) {
+        const int k = sg.singles[(int)(((int64_t)i * st) % nsing)];
+        const int p = ck.y + k;
+        T wx[W], wy[W];
+        int lr, lc;
+        point_weights<T, W>(sth[p], sph[p], g, row0, col0, beta, lr, lc, wx, wy);
+        if (lr < 0 || lr >= g.t1 || lc < 0 || lc >= g.t2)
+            continue;  // cannot happen for points sorted by the same arithmetic
+        double vr, vi;
+        value(p, vr, vi);
+        double dy[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            dy[j] = (double)wy[j];
+#pragma unroll
+        for (int i2 = 0; i2 < W; ++i2) {
+            const double fr = (double)wx[i2] * vr, fi = (double)wx[i2] * vi;
+            if constexpr (PACK) {
+                unsigned long long *rowp =
+                    reinterpret_cast<unsigned long long *>(patch) + (lr + i2) * g.ps + lc;
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    // Re 2^32 + Im: the low word is round(Im); the high word takes
+                    // round(Re) plus the sign extension of round(Im), which is the
+                    // high word of its magic-rounded bits minus KMhi = KM / 2^32
+                    // (rounding Re with the constant M - 2^32 KMhi leaves the
+                    // subtraction in its low word)
+                    const unsigned long long br = (unsigned long long)__double_as_longlong(
+                        fma(fr, dy[j], QMAGIC - (double)QMAGIC_HI));
+                    const unsigned long long bi = qbits(fi, dy[j]);
+                    atomicAdd(rowp + j, bi + (br << 32));
+                }
+            } else {
+                U *rowp = patch + (lr + i2) * g.ps + lc;
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    atomicAdd(rowp + j, A::quant(fr, dy[j]));
+                    if constexpr (CPLX)
+                        atomicAdd(rowp + plane + j, A::quant(fi, dy[j]));
+                }
+            }
+        }
+    }
+    return true;
+}
+
+// Spreading of one chunk into its patch, then the flush of the patch to the grid.
+// FP64 grids spread couples of neighbouring points as one window (fewer LDS
+// atomics, which bound them); FP32 grids, bound by their arithmetic, point by point.
+template <typename T, int W, bool CPLX, bool ATOMIC, bool FQ>
+__device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
+                                    const double *__restrict__ sph,
+                                    const int32_t *__restrict__ perm, const T *__restrict__ in,
+                                    const GridGeom &g, T beta, T *__restrict__ grid,
+                                    typename SpreadAcc<T, FQ>::U *patch, SpreadStage &sg)
+{
+    using A = SpreadAcc<T, FQ>;
+    constexpr bool PACK = SpreadPack<T, CPLX>::value;
+    constexpr int NC = CPLX ? 2 : 1;
+    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
+    const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
+    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
+        patch[idx] = 0;
+    double scale = 0.0;
+    bool any;
+    if constexpr (std::is_same<T, double>::value)
+        any = spread_paired<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg, row0, col0,
+                                            scale);
+    else
+        any = spread_single<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg.wsum, row0,
+                                            col0, scale);
+    if (!any)
+        return;
     __syncthreads();
     const double inv = 1.0 / scale;
     for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
@@ -912,16 +1178,16 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
 
 // One workgroup per chunk, atomic flush (any grid).
 template <typename T, int W, bool CPLX, bool FQ>
-__global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
+__global__ __launch_bounds__(NUFFT_THREADS, SPREAD_WAVES) void spread_kernel(
     const int4 *__restrict__ chunks, const double *__restrict__ sth, const double *__restrict__ sph,
     const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
     T *__restrict__ grid)
 {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double wsum[NUFFT_THREADS / 64];
+    __shared__ SpreadStage sg;
     spread_chunk<T, W, CPLX, true, FQ>(chunks[blockIdx.x], sth, sph, perm, in, g, beta, grid,
                                        reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw),
-                                       wsum);
+                                       sg);
 }
 
 // One workgroup per tile of one colour (all of the tile's chunks in turn), plain
@@ -929,19 +1195,19 @@ __global__ __launch_bounds__(NUFFT_THREADS) void spread_kernel(
 // directions and a patch reaches only W - 1 cells beyond its tile, so their
 // patches are disjoint.  items[i] = (first chunk, number of chunks).
 template <typename T, int W, bool CPLX, bool FQ>
-__global__ __launch_bounds__(NUFFT_THREADS) void spread_tile_kernel(
+__global__ __launch_bounds__(NUFFT_THREADS, SPREAD_WAVES) void spread_tile_kernel(
     const int2 *__restrict__ items, const int4 *__restrict__ chunks,
     const double *__restrict__ sth, const double *__restrict__ sph,
     const int32_t *__restrict__ perm, const T *__restrict__ in, GridGeom g, T beta,
     T *__restrict__ grid)
 {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double wsum[NUFFT_THREADS / 64];
+    __shared__ SpreadStage sg;
     const int2 it = items[blockIdx.x];
     for (int c = 0; c < it.y; ++c)
         spread_chunk<T, W, CPLX, false, FQ>(chunks[it.x + c], sth, sph, perm, in, g, beta, grid,
                                             reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw),
-                                            wsum);
+                                            sg);
 }
 
 static GridGeom make_geom(const gsht_plan &p)

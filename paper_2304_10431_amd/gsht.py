@@ -47,7 +47,7 @@ class PlanInfo(ctypes.Structure):
                 ("ntile2", ctypes.c_int), ("nchunks", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("column_mode", ctypes.c_int),
                 ("spread_colors", ctypes.c_int), ("syn_r", ctypes.c_int), ("adj_r", ctypes.c_int),
-                ("adj_b", ctypes.c_int), ("sigma", ctypes.c_double)]
+                ("adj_b", ctypes.c_int), ("sigma", ctypes.c_double), ("cell_sort", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

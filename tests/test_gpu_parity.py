@@ -245,10 +245,11 @@ def test_binsort_bit_exact(G, kind, npts):
     plan = G.Plan(dev(th), dev(ph), 127, 127, 2, 1e-5, "f32")
     inf = plan.info()
     perm, start = plan.sort()
+    assert inf["cell_sort"] == 1
     keys = oracle.bin_keys(th, ph, inf["n1"], inf["n2"], inf["w"], inf["a_min"], inf["tile1"],
-                           inf["tile2"], inf["ntile2"])
+                           inf["tile2"], inf["ntile2"], cells=True)
     ntiles = inf["ntile1"] * inf["ntile2"]
-    ref_perm, ref_start = oracle.binsort(keys, ntiles)
+    ref_perm, ref_start = oracle.binsort(keys, ntiles, inf["tile1"] * inf["tile2"])
     assert np.array_equal(perm.cpu().numpy(), ref_perm)
     assert np.array_equal(start.cpu().numpy(), ref_start)
 

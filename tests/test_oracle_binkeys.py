@@ -7,7 +7,8 @@ phi, cyclically over n2 cells), and the key is (row tile of its first row cell r
 a_min) * ntile2 + (column tile of its first column cell mod n2).  Here the first cell
 is found by scanning integers with exact rational arithmetic, independently of the
 ceil-based formula, and the key is rebuilt from it; points on cell boundaries,
-at the poles and across phi = 0 are included."""
+at the poles and across phi = 0 are included.  The cell-order key adds the first
+cell's place inside its tile (row-major)."""
 import math
 from fractions import Fraction
 
@@ -43,6 +44,7 @@ def test_bin_keys_window_starts_in_its_tile():
         th = np.concatenate([th, (k + (w % 2) * 0.5) * (2 * math.pi / n1)])
         ph = np.concatenate([ph, rng.uniform(0, 2 * math.pi, 40)])
         keys = oracle.bin_keys(th, ph, n1, n2, w, a_min, t1, t2, ntile2)
+        ckeys = oracle.bin_keys(th, ph, n1, n2, w, a_min, t1, t2, ntile2, cells=True)
         c1 = np.float64(n1) / (np.float64(2.0) * np.float64(np.pi))
         c2 = np.float64(n2) / (np.float64(2.0) * np.float64(np.pi))
         for i in range(th.size):
@@ -52,3 +54,12 @@ def test_bin_keys_window_starts_in_its_tile():
             row, col = (a0 - a_min) // t1, (b0 % n2) // t2
             assert 0 <= a0 - a_min and 0 <= col < ntile2
             assert keys[i] == row * ntile2 + col, (w, i, th[i], ph[i], keys[i], row, col)
+            # cell order: the tile, then the first cell's row and column inside it.  The
+            # FP64 formula's first cell equals the exact one except where u - w/2 or
+            # v - w/2 rounds onto an integer (phi = 1e-300 here), one cell lower.
+            half = np.float64(w) * np.float64(0.5)
+            af = int(np.ceil(np.float64(u) - half))
+            bf = int(np.ceil(np.float64(v) - half))
+            for e, f, x in ((a0, af, u), (b0, bf, v)):
+                assert e == f or (e - f == 1 and float(np.float64(x) - half) == f), (w, i, e, f)
+            assert ckeys[i] == keys[i] * t1 * t2 + ((af - a_min) % t1) * t2 + (bf % n2) % t2
