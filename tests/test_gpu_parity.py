@@ -237,19 +237,23 @@ def test_gpu_pair_is_adjoint(G, spin):
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(ax), (lhs, rhs)
 
 
+@pytest.mark.parametrize("cells", [True, False])
 @pytest.mark.parametrize("kind,npts", [("uniform", 50000), ("gl", 40000), ("poles", 3000),
                                        ("wrap", 20001)])
-def test_binsort_bit_exact(G, kind, npts):
-    say("binsort", kind, npts)
+def test_binsort_bit_exact(G, monkeypatch, kind, npts, cells):
+    """Sorted by tile and first kernel cell (the default), or by tile alone."""
+    say("binsort", kind, npts, cells)
+    if not cells:
+        monkeypatch.setenv("GSHT_CELL_SORT", "0")
     th, ph = make_case(kind, npts, 99)
     plan = G.Plan(dev(th), dev(ph), 127, 127, 2, 1e-5, "f32")
     inf = plan.info()
     perm, start = plan.sort()
-    assert inf["cell_sort"] == 1
+    assert inf["cell_sort"] == (1 if cells else 0)
     keys = oracle.bin_keys(th, ph, inf["n1"], inf["n2"], inf["w"], inf["a_min"], inf["tile1"],
-                           inf["tile2"], inf["ntile2"], cells=True)
+                           inf["tile2"], inf["ntile2"], cells=cells)
     ntiles = inf["ntile1"] * inf["ntile2"]
-    ref_perm, ref_start = oracle.binsort(keys, ntiles, inf["tile1"] * inf["tile2"])
+    ref_perm, ref_start = oracle.binsort(keys, ntiles, inf["tile1"] * inf["tile2"] if cells else 1)
     assert np.array_equal(perm.cpu().numpy(), ref_perm)
     assert np.array_equal(start.cpu().numpy(), ref_start)
 
@@ -380,6 +384,46 @@ def test_fp64_spreading_fast_and_exact_forms(G, monkeypatch, lmax, mmax, spin, n
     ref = oracle.adjoint(y, lmax, mmax, spin, th, ph)
     for o in outs:
         assert oracle.eps_eff(o * w, ref * w) <= eps
+
+
+@pytest.mark.parametrize("lmax,mmax,spin,npts,prec,eps", [
+    (130, 130, 2, 30000, "f64", 1e-10), (96, 80, 0, 20000, "f64", 1e-12),
+    (200, 200, 2, 40000, "f32", 1e-5)])
+def test_point_order_within_tiles(G, monkeypatch, lmax, mmax, spin, npts, prec, eps):
+    """Points in cell order (FP64 spreading pairs neighbours) and in tile order (few
+    pairs) give the same transforms up to rounding, both within epsilon of the oracle,
+    on thin Gauss-Legendre rings (dense rows, many couples)."""
+    say("point order", lmax, mmax, spin, npts, prec, eps)
+    rng = np.random.default_rng(970 + lmax)
+    nring = max(8, int(np.sqrt(npts / 2)))
+    th, ph = wl.gl_grid(nring, 2 * nring)[:2]
+    th, ph = th[:npts], ph[:npts]
+    th, ph = deflect_small(th, ph, 24, 5)
+    y = rng.standard_normal((oracle.ncomp(spin), th.size))
+    a = wl.gaussian_alm(lmax, mmax, spin, rng)
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    w = np.sqrt(oracle.alm_weights(lmax, mmax))[None, :]
+    outs = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("GSHT_CELL_SORT", raising=False)
+        else:
+            monkeypatch.setenv("GSHT_CELL_SORT", env)
+        plan = G.Plan(dev(th), dev(ph), lmax, mmax, spin, eps, prec)
+        assert plan.info()["cell_sort"] == (1 if env is None else 0)
+        outs.append((plan.synth(dev(a).to(cdt)).cpu().numpy().astype(np.float64),
+                     plan.adjoint(dev(y).to(rdt)).cpu().numpy().astype(np.complex128)))
+        plan.close()
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert rel_l2(outs[0][0], outs[1][0]) <= tol
+    assert rel_l2(outs[0][1] * w, outs[1][1] * w) <= tol
+    ref_a = oracle.adjoint(y, lmax, mmax, spin, th, ph)
+    idx = rng.choice(th.size, 500, replace=False)
+    ref_s = oracle.synth(a, lmax, mmax, spin, th[idx], ph[idx])
+    for s_out, a_out in outs:
+        assert oracle.eps_eff(a_out * w, ref_a * w) <= eps
+        assert oracle.eps_eff(s_out[:, idx], ref_s) <= eps
 
 
 @pytest.mark.parametrize("lmax,mmax,spin,prec", [(130, 130, 2, "f64"), (512, 400, 1, "f32"),
