@@ -127,7 +127,7 @@ __device__ inline f32x16_t mma(const u32x4_t &a, const u32x4_t &b, const f32x16_
 // boff[m]; block kb holds [type][cb][hi, lo][lane] half8 entries for degrees
 // l0 + 16 kb + 8 (lane / 32) + j.  oscale[m][map] undoes the coefficient scaling.
 template <bool SPIN, int NCB>
-__global__ __launch_bounds__(64) void leg_synth_mfma_kernel(
+__global__ __launch_bounds__(64, 2) void leg_synth_mfma_kernel(
     const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, const int64_t *__restrict__ boff,
     const u32x4_t *__restrict__ Bt, const float *__restrict__ oscale, int nm, int lmax, int mmax,
@@ -187,13 +187,7 @@ __global__ __launch_bounds__(64) void leg_synth_mfma_kernel(
                         for (int hl = 0; hl < 2; ++hl)
                             Bx[t][c][hl] = bb[((t * NCB + c) * 2 + hl) * 64];
             };
-            load_b(kb, Bc);
-            make_a<SPIN>(rg, abm, l0 + MK * kb, lmax, A[0], A[NT - 1]);
-            for (; kb < nkb; ++kb) {
-                // next block (past the end: a harmless repeat of the last tile and
-                // recurrence steps on zero coefficients)
-                load_b(kb + 1 < nkb ? kb + 1 : kb, Bn);
-                make_a<SPIN>(rg, abm, l0 + MK * (kb + 1), lmax, An[0], An[NT - 1]);
+            auto products = [&](const AOps (&Ax)[NT], const u32x4_t (&Bx)[NT][NCB][2]) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -201,21 +195,28 @@ __global__ __launch_bounds__(64) void leg_synth_mfma_kernel(
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
                             f32x16_t x = acc[h][t][c];
-                            x = mma(A[t].v[h], Bc[t][c][0], x);
-                            x = mma(A[t].v[h], Bc[t][c][1], x);
-                            x = mma(A[t].v[2 + h], Bc[t][c][0], x);
+                            x = mma(Ax[t].v[h], Bx[t][c][0], x);
+                            x = mma(Ax[t].v[h], Bx[t][c][1], x);
+                            x = mma(Ax[t].v[2 + h], Bx[t][c][0], x);
                             acc[h][t][c] = x;
                         }
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    A[t] = An[t];
-#pragma unroll
-                    for (int c = 0; c < NCB; ++c) {
-                        Bc[t][c][0] = Bn[t][c][0];
-                        Bc[t][c][1] = Bn[t][c][1];
-                    }
-                }
+            };
+            load_b(kb, Bc);
+            make_a<SPIN>(rg, abm, l0 + MK * kb, lmax, A[0], A[NT - 1]);
+            // two blocks per iteration with the operand sets swapping roles, so no
+            // register copies between blocks; the next block's operands (past the
+            // end: a harmless repeat of the last tile and recurrence steps on zero
+            // coefficients) are formed while the current block's products run
+            for (; kb + 1 < nkb; kb += 2) {
+                load_b(kb + 1, Bn);
+                make_a<SPIN>(rg, abm, l0 + MK * (kb + 1), lmax, An[0], An[NT - 1]);
+                products(A, Bc);
+                load_b(kb + 2 < nkb ? kb + 2 : kb + 1, Bc);
+                make_a<SPIN>(rg, abm, l0 + MK * (kb + 2), lmax, A[0], A[NT - 1]);
+                products(An, Bn);
             }
+            if (kb < nkb)
+                products(A, Bc);
         }
     }
     // Results through LDS, one (type, column block) at a time: lane L then holds the
