@@ -74,15 +74,18 @@ def sources_sha(stage):
     return h.hexdigest()
 
 
-def measured_traffic(workload, form, stage):
+def measured_traffic(workload, form, stage, w=None):
     """HBM bytes per call of a stage (summed over its launches) from the committed
-    counter runs, or None if they were taken on another workload or form, or on a
-    different version of the stage's kernel sources."""
+    counter runs, or None if they were taken on another workload or form, on a
+    different version of the stage's kernel sources, or (NUFFT stages) with another
+    kernel support w."""
     try:
         rec = json.load(open(TRAFFIC_FILE % workload))[form][stage]
     except (OSError, ValueError, KeyError):
         return None
     if rec.get("kernel_source_sha256") != sources_sha(stage):
+        return None
+    if "w" in rec and w is not None and rec["w"] != w:
         return None
     return rec.get("bytes_per_call")
 
@@ -146,7 +149,7 @@ def roofline_entry(stage, form_key, r, spec, npts, workload):
         e = {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "bytes_per_launch": nb}
     e["avg_launch_ms"] = avg_s * 1e3
-    e["traffic"] = measured_traffic(workload, form_key, stage)
+    e["traffic"] = measured_traffic(workload, form_key, stage, info["w"])
     return e
 
 

@@ -3,11 +3,11 @@
 For each oversampling factor sigma the library stores, per support w, the relative
 L2 error of a 2-D type-2 NUFFT with the exponential-of-semicircle kernel (Sect. 3) at
 its beta / w, measured on 81 x 81 random Fourier modes at 2000 random points against
-the direct sum; a plan takes the smallest w whose entry is at most epsilon / 4.  This
+the direct sum; a plan takes the smallest w whose entry is at most epsilon / 2.  This
 test parses the table from the library source, recomputes every entry with the
 oracle's plain FP64 type-2 NUFFT (oracle.nufft_sht.nufft_type2) on the same draw, and
 checks that each stored value matches (within a factor 1.5 where the error is above
-FP64 rounding) and that every support the plans pick stays within epsilon / 4."""
+FP64 rounding) and that every support the plans pick stays within epsilon / 2."""
 import os
 import re
 
@@ -60,12 +60,12 @@ def test_table_entries_recomputed(draw):
 
 
 @pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-8, 1e-10, 1e-12])
-def test_chosen_support_meets_quarter_eps(draw, eps):
-    """The support a plan picks (smallest w with stored error <= eps / 4) reaches
-    eps / 4 on the recomputed draw too, and one cell less would not be chosen."""
+def test_chosen_support_meets_half_eps(draw, eps):
+    """The support a plan picks (smallest w with stored error <= eps / 2) reaches
+    eps / 2 on the recomputed draw too, and one cell less would not be chosen."""
     K, c, x, y, exact = draw
     for sigma, bw, errs in stored_tables():
-        ws = [w for w in range(4, 17) if errs[w] <= 0.25 * eps]
+        ws = [w for w in range(4, 17) if errs[w] <= 0.5 * eps]
         if not ws:
             continue
         w = ws[0]
@@ -73,6 +73,6 @@ def test_chosen_support_meets_quarter_eps(draw, eps):
         n += n % 2
         got = nufft_sht.nufft_type2(c, x, y, n, n, w, bw * w)
         e = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
-        assert e <= 0.25 * eps * 1.5, (sigma, eps, w, e)
+        assert e <= 0.5 * eps * 1.5, (sigma, eps, w, e)
         if w > 4:
-            assert errs[w - 1] > 0.25 * eps
+            assert errs[w - 1] > 0.5 * eps
