@@ -380,21 +380,18 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
         const int ak = k < 0 ? -k : k;
         return scale_c(X[lds_pos(fd.perm[k < 0 ? k + a.nd : k], sh)], a.kf1[ak] * fm);
     };
-    // Fold: residue i < nh receives c_i (i <= lmax) and c_{i - nh} (i >= nh - lmax).
-    // Only the even-row input ye = c_i + c_{i-nh} stays in registers: the odd-row
-    // input is t^i (c_i - c_{i-nh}) (t^{-nh} = -1), i.e. t^i (+-ye) where only one
-    // term exists.  The residues with both (2 lmax + 1 - nh of them: one at
-    // oversampling 2, a quarter of the column at 1.5) keep c_i - c_{i-nh} in this
-    // column of E, which holds nothing until its rows are written after the
-    // transforms; each thread reads back only what it wrote, so no barrier is needed
-    // for it, and the LDS stays at the column's own size.
+    // Fold: residue i < nh receives c_i (i <= lmax) and c_{i - nh} (i >= nh - lmax);
+    // absent terms count as zero.  The even-row input is ye = c_i + c_{i-nh}, the
+    // odd-row input t^i (c_i - c_{i-nh}) (t^{-nh} = -1).  Both are formed in
+    // registers before the odd input overwrites the spectrum in LDS; ye stays there
+    // until the even transform.
     const int ov0 = nh - a.lmax;
-    C *ovl = ec;
-    C ye[MAXV];
+    C ye[MAXV], yd[MAXV];
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
         const int i = tid + v * NT;
         ye[v].x = ye[v].y = 0;
+        yd[v] = ye[v];
         if (i < nh) {
             C c1, c2;
             c1.x = c1.y = 0;
@@ -404,8 +401,7 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
             if (i >= ov0)
                 c2 = chat(i - nh);
             ye[v] = cadd(c1, c2);
-            if (i >= ov0 && i <= a.lmax)
-                ovl[i - ov0] = csub(c1, c2);
+            yd[v] = csub(c1, c2);
         }
     }
     __syncthreads();
@@ -413,16 +409,8 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
         const int i = tid + v * NT;
-        if (i < nh) {
-            C d = ye[v];
-            if (i >= ov0 && i <= a.lmax) {
-                d = ovl[i - ov0];
-            } else if (i > a.lmax) {
-                d.x = -d.x;
-                d.y = -d.y;
-            }
-            X[lds_pos(i, sh)] = cmulc(d, twist[i]);
-        }
+        if (i < nh)
+            X[lds_pos(i, sh)] = cmulc(yd[v], twist[i]);
     }
     __syncthreads();
     lds_fft<C, 1, NT>(X, fh);
