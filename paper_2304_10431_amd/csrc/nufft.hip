@@ -716,6 +716,18 @@ __device__ inline unsigned long long qbits(double a, double b)
 // magnitude, so the low 51 bits of the sum of magic-rounded words are the sum
 // itself (sign-extended) whatever the KM terms did above them: one FMA per word.
 template <typename T, bool FQ> struct SpreadAcc;
+// Packed FP32 cell word from the magic-rounded bits of Re (taken with M - 2^32 KMhi)
+// and Im: bi + (br << 32), formed as its two 32-bit halves (no carry crosses them):
+// one 32-bit add on the high half (written as such, since the compiler otherwise
+// rebuilds the 64-bit form with an extra move).
+__device__ inline unsigned long long pack_word(unsigned long long br, unsigned long long bi)
+{
+    uint2 w;
+    w.x = (unsigned int)bi;
+    asm("v_add_u32 %0, %1, %2" : "=v"(w.y) : "v"((unsigned int)br), "v"((unsigned int)(bi >> 32)));
+    return __builtin_bit_cast(unsigned long long, w);
+}
+
 // quant2(a1, b1, a2, b2) rounds a1 b1 + a2 b2 (two points' contributions to one cell).
 __device__ inline unsigned long long qbits2(double a1, double b1, double a2, double b2)
 {
@@ -899,7 +911,7 @@ __device__ inline bool spread_single(int4 ck, const double *__restrict__ sth,
                     const unsigned long long br = (unsigned long long)__double_as_longlong(
                         fma(fr, dy[j], QMAGIC - (double)QMAGIC_HI));
                     const unsigned long long bi = qbits(fi, dy[j]);
-                    atomicAdd(rowp + j, bi + (br << 32));
+                    atomicAdd(rowp + j, pack_word(br, bi));
                 }
             } else {
                 U *rowp = patch + (lr + i) * g.ps + lc;
@@ -1045,7 +1057,7 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
                                 fma(frb, db[j], fma(fra, da[j], QMAGIC - (double)QMAGIC_HI)));
                             const unsigned long long bi = (unsigned long long)__double_as_longlong(
                                 fma(fib, db[j], fma(fia, da[j], QMAGIC)));
-                            atomicAdd(roww + j, bi + (br << 32));
+                            atomicAdd(roww + j, pack_word(br, bi));
                         } else {
                             atomicAdd(rowp + j, A::quant2(fra, da[j], frb, db[j]));
                             if constexpr (CPLX)
@@ -1090,7 +1102,7 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
                     const unsigned long long br = (unsigned long long)__double_as_longlong(
                         fma(fr, dy[j], QMAGIC - (double)QMAGIC_HI));
                     const unsigned long long bi = qbits(fi, dy[j]);
-                    atomicAdd(rowp + j, bi + (br << 32));
+                    atomicAdd(rowp + j, pack_word(br, bi));
                 }
             } else {
                 U *rowp = patch + (lr + i2) * g.ps + lc;
