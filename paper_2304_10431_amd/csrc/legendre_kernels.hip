@@ -620,6 +620,19 @@ __device__ inline double swap_add16(double a, double b)
     return a2 + b2;
 }
 
+// Degrees per masked block of the adjoint (blocks before every lane is in range): the
+// masked blocks set the kernel's register count, and at 4 degrees the R = 3 shapes fit
+// 168 registers, three waves per SIMD (9.43 ms at the benchmark against 9.55 for
+// 8-degree masked blocks at two waves, and 10.18 for 4-degree ones at two waves).
+constexpr int ADJ_MASKED_B = 4;
+
+// Waves per SIMD each adjoint shape is compiled for.
+template <int R, int B>
+constexpr int adj_waves()
+{
+    return R == 3 ? 3 : 1;
+}
+
 // One wave per (m, chunk).  Per block of B degrees the V = B NC per-lane sums are
 // reduced over the 64 lanes: two swap-add stages in registers leave V/4 values per
 // lane, each value spread over the 16 lanes of one row; these go through LDS
@@ -627,7 +640,8 @@ __device__ inline double swap_add16(double a, double b)
 // results are added to acc[idx][0..NC-1] with one coalesced FP64 atomic per
 // (degree, component).
 template <typename T, bool SPIN, int R, int B, bool GRAD = false>
-__global__ __launch_bounds__(64) void leg_adjoint_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(adj_waves<R, B>())))
+void leg_adjoint_kernel(
     const double2 *__restrict__ ab, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, const typename cplxk<T>::type *__restrict__ D, int lmax,
     int mmax, int s, int ntheta, int nd, int npairs, int nchunk, double *__restrict__ acc)
@@ -636,6 +650,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     constexpr int NC = SPIN ? 4 : 2;         // per-lane sums per degree
     constexpr int NR = GRAD ? 2 : NC;        // reduced values per degree
     constexpr int V = B * NR;
+    constexpr int BM = ADJ_MASKED_B < B ? ADJ_MASKED_B : B;  // degrees per masked block
     static_assert(64 % V == 0 && V >= 8, "block values must divide the wave");
     __shared__ double red[V * 16];
     int m, chunk;
@@ -704,46 +719,51 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
         some_in = some_in || ph[r] != 0;
     }
 
-    // Reduce the block sums cb over the wave and add them to acc (degrees lb..).
-    auto reduce_add = [&](double (&cb)[V], int lb) {
-        // stage 1: lanes L, L + 32 -> V/2 values; value k + (L / 32) V/2 in slot k
-        double c1[V / 2];
+    // Reduce the block sums cb (VB values: VB / NR degrees) over the wave and add them
+    // to acc (degrees lb..).
+    auto reduce_add = [&](auto &cb, int lb) {
+        constexpr int VB = std::extent<std::remove_reference_t<decltype(cb)>>::value;
+        static_assert(64 % VB == 0 && VB >= 8 && VB <= V, "block values must divide the wave");
+        // stage 1: lanes L, L + 32 -> VB/2 values; value k + (L / 32) VB/2 in slot k
+        double c1[VB / 2];
 #pragma unroll
-        for (int k = 0; k < V / 2; ++k)
-            c1[k] = swap_add32(cb[k], cb[k + V / 2]);
-        // stage 2: rows (0,1), (2,3) -> V/4 values per lane; slot k of row g holds
-        // value k + (g & 1) V/4 + (g >> 1) V/2, partially summed over 4 lanes
-        double c2[V / 4];
+        for (int k = 0; k < VB / 2; ++k)
+            c1[k] = swap_add32(cb[k], cb[k + VB / 2]);
+        // stage 2: rows (0,1), (2,3) -> VB/4 values per lane; slot k of row g holds
+        // value k + (g & 1) VB/4 + (g >> 1) VB/2, partially summed over 4 lanes
+        double c2[VB / 4];
 #pragma unroll
-        for (int k = 0; k < V / 4; ++k)
-            c2[k] = swap_add16(c1[k], c1[k + V / 4]);
+        for (int k = 0; k < VB / 4; ++k)
+            c2[k] = swap_add16(c1[k], c1[k + VB / 4]);
         const int g = lane >> 4, li = lane & 15;
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < V / 4; ++k) {
-            const int vv = k + (g & 1) * (V / 4) + (g >> 1) * (V / 2);
+        for (int k = 0; k < VB / 4; ++k) {
+            const int vv = k + (g & 1) * (VB / 4) + (g >> 1) * (VB / 2);
             red[vv * 16 + ((li + vv) & 15)] = c2[k];
         }
         __syncthreads();
-        constexpr int H = 64 / V;       // lanes per value
+        constexpr int H = 64 / VB;      // lanes per value
         constexpr int SPAN = 16 / H;    // row partials summed per lane
-        const int v = lane % V, h = lane / V;
+        const int v = lane % VB, h = lane / VB;
         double sum = 0.0;
 #pragma unroll
         for (int i = 0; i < SPAN; ++i)
             sum += red[v * 16 + ((h * SPAN + i + v) & 15)];
 #pragma unroll
-        for (int d = V; d < 64; d <<= 1)
+        for (int d = VB; d < 64; d <<= 1)
             sum += __shfl_xor(sum, d, 64);
-        if (lane < V && lb + lane / NR <= lmax)
+        if (lane < VB && lb + lane / NR <= lmax)
             unsafeAtomicAdd(acc + (base + lb) * NR + lane, sum);
     };
-    // per-lane sums of a block -> the values reduced over the wave
-    auto reduce_block = [&](double (&cf)[B * NC], int lb) {
+    // per-lane sums of a block of BB = size / NC degrees -> the values reduced over
+    // the wave
+    auto reduce_block = [&](auto &cf, int lb) {
+        constexpr int BB = std::extent<std::remove_reference_t<decltype(cf)>>::value / NC;
         if constexpr (GRAD) {
-            double cr[V];
+            double cr[2 * BB];
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
+            for (int b = 0; b < BB; ++b) {
                 cr[2 * b] = cf[4 * b] + cf[4 * b + 2];
                 cr[2 * b + 1] = cf[4 * b + 1] + cf[4 * b + 3];
             }
@@ -752,14 +772,14 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             reduce_add(cf, lb);
         }
     };
-    // Masked block: channels out of range (offset < 0, constant inside a block) get
-    // the weight 0 for the block; rescaling and phase update at its end.  Only the
-    // final partial block (TAIL) checks the degree bound.
+    // Masked block of BM degrees: channels out of range (offset < 0, constant inside a
+    // block) get the weight 0 for the block; rescaling and phase update at its end.
+    // Only partial blocks at the end (TAIL) check the degree bound.
     auto masked_block = [&](int lb, auto tail) {
         constexpr bool TAIL = decltype(tail)::value;
-        double cb[B * NC];
+        double cb[BM * NC];
 #pragma unroll
-        for (int k = 0; k < B * NC; ++k)
+        for (int k = 0; k < BM * NC; ++k)
             cb[k] = 0.0;
         const double2 *abl = ab + base + lb;
         const bool had_some = some_in;
@@ -770,7 +790,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             wb[r] = (SPIN && rg[r].eb == 0) ? 1.0 : 0.0;
         }
 #pragma unroll
-        for (int b = 0; b < B; b += 2) {
+        for (int b = 0; b < BM; b += 2) {
             const int l = lb + b;
             if (TAIL && l > lmax)
                 break;
@@ -789,6 +809,9 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
                                             rg[r].b1 * wb[r]);
                 ring_advance<SPIN>(rg[r], c1.x, c1.y);
             }
+            // one degree pair per scheduling region: hoisting later degrees'
+            // recurrence steps ahead of this pair's sums costs registers
+            __builtin_amdgcn_sched_barrier(0);
         }
         all_in = true;
         some_in = false;
@@ -806,7 +829,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
     // masked full blocks until every lane is in range, full plain blocks, and a
     // masked partial tail.
     int lb = l0;
-    for (; lb + B - 1 <= lmax && !all_in; lb += B)
+    for (; lb + BM - 1 <= lmax && !all_in; lb += BM)
         masked_block(lb, flag<false>());
     // Plain blocks; the coefficients of each degree pair are loaded one pair ahead
     // (across block ends too), so the scalar loads overlap the current pair's work.
@@ -835,7 +858,7 @@ __global__ __launch_bounds__(64) void leg_adjoint_kernel(
             reduce_block(cb, lb);
         }
     }
-    if (lb <= lmax)
+    for (; lb <= lmax; lb += BM)
         masked_block(lb, flag<true>());
 }
 
