@@ -202,6 +202,35 @@ __device__ inline int slice_phase(const Ring &r)
     return __any(some) ? 1 : 0;
 }
 
+// Silent blocks: while no lane of the wave holds a channel in range every term would
+// get the weight 0, so only the recurrence runs (no sums, no reductions), with the
+// rescaling and the slice phases after every 8 degrees as in the masked blocks.  ab_m
+// points at the degree-indexed coefficients of the wave's m; lb advances.
+template <bool SPIN, int INX, int R>
+__device__ inline void silent_blocks(Ring (&rg)[R], const double2 *ab_m, int &lb, int lmax,
+                                     bool &all_in, bool &some_in)
+{
+    for (; lb + 7 <= lmax && !some_in; lb += 8) {
+        const double2 *abl = ab_m + lb;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const double2 cc = abl[b];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                ring_advance<SPIN>(rg[r], cc.x, cc.y);
+        }
+        all_in = true;
+        some_in = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ring_rescale<SPIN, INX>(rg[r]);
+            const int p = slice_phase<SPIN>(rg[r]);
+            all_in = all_in && p == 2;
+            some_in = some_in || p != 0;
+        }
+    }
+}
+
 template <bool B>
 using flag = std::integral_constant<bool, B>;
 

@@ -825,10 +825,11 @@ void leg_adjoint_kernel(
         if (had_some)  // otherwise every lane was out of range for the whole block
             reduce_block(cb, lb);
     };
-    // Three sequential loops (no loop-carried value crosses a branch merge):
-    // masked full blocks until every lane is in range, full plain blocks, and a
-    // masked partial tail.
+    // Sequential loops (no loop-carried value crosses a branch merge): silent blocks
+    // until some lane is in range, masked full blocks until every lane is, full plain
+    // blocks, and masked partial blocks at the end.
     int lb = l0;
+    silent_blocks<SPIN, ADJ_IN_EXP>(rg, ab + base, lb, lmax, all_in, some_in);
     for (; lb + BM - 1 <= lmax && !all_in; lb += BM)
         masked_block(lb, flag<false>());
     // Plain blocks; the coefficients of each degree pair are loaded one pair ahead
