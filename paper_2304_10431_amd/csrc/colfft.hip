@@ -62,6 +62,19 @@ constexpr int col_half_maxn()
     return sizeof(T) == 4 ? 17 * 512 : 20 * 512;
 }
 
+// FP64 mode-2 kernels are instantiated for every register slot count MAXV up to
+// col_half_maxn / threads and launched with the smallest that holds the plan's
+// transforms (the forward kernel's slots cover nh = n1 / 2, the adjoint's max(nd, nh)):
+// slots sized for the largest case held 40 VGPRs per array and spilled 24 registers
+// to scratch at lmax 4096, where 6 and 9 slots suffice (column forward 1.70 -> 1.61 ms,
+// adjoint 1.72 -> 1.67 ms at sigma 1.5).  FP32 runs with the largest count: its 512
+// threads leave it 128 registers for half the slots, and it does not spill.
+template <typename T>
+constexpr int col_half_maxv()
+{
+    return col_half_maxn<T>() / col_half_threads<T>();
+}
+
 template <typename C>
 __device__ inline C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
 template <typename C>
@@ -357,13 +370,12 @@ __device__ inline void load_rows(const C *ec, int i, C &ev, C &od, const ColArgs
 // t = e^{2 pi i / n1}: two length-nh transforms of the spectra folded modulo nh (at
 // most two k per residue, since nh > lmax), so the LDS buffer holds max(nd, nh)
 // values.  twist[k] = e^{-2 pi i k / n1}, k < n1.
-template <typename T, int NT>
+template <typename T, int NT, int MAXV>
 __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kernel(
     const typename cx<T>::type *__restrict__ D, typename cx<T>::type *__restrict__ E, ColArgs a,
     ColFFT fd, ColFFT fh, const typename cx<T>::type *__restrict__ twist)
 {
     using C = typename cx<T>::type;
-    constexpr int MAXV = col_half_maxn<T>() / NT;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
     const int sh = fd.psh;  // LDS padding shift
@@ -444,13 +456,12 @@ __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_fwd_half_kerne
 
 // Mode 2, E column (kept rows; the rest counts as zero) -> D column: the transpose
 // of column_fwd_half_kernel (odd rows first, then even rows).
-template <typename T, int NT>
+template <typename T, int NT, int MAXV>
 __global__ __launch_bounds__(NT, col_half_waves<T>()) void column_adj_half_kernel(
     const typename cx<T>::type *__restrict__ E, typename cx<T>::type *__restrict__ D, ColArgs a,
     ColFFT fd, ColFFT fh, const typename cx<T>::type *__restrict__ twist)
 {
     using C = typename cx<T>::type;
-    constexpr int MAXV = col_half_maxn<T>() / NT;
     extern __shared__ unsigned char smem_raw[];
     C *X = reinterpret_cast<C *>(smem_raw);
     const int sh = fd.psh;  // LDS padding shift
@@ -608,17 +619,48 @@ size_t col_lds(const gsht_plan &p)
     return sizeof(typename cx<T>::type) * (size_t)n;
 }
 
+// Register slots of the mode-2 kernels for this plan (see col_half_maxv).
+template <typename T>
+int half_slots(const gsht_plan &p, bool adjoint)
+{
+    constexpr int NT = col_half_threads<T>();
+    const int nh = p.n1 / 2, n = adjoint ? (p.nd > nh ? p.nd : nh) : nh;
+    const int v = (n + NT - 1) / NT;
+    return v < 1 ? 1 : v;
+}
+
+// Calls f with the kernel instance of MV = v slots (MV counts down from the largest;
+// FP32 has only the largest).
+template <typename T, int MV, typename F>
+hipError_t with_fwd_half(int v, F &&f)
+{
+    if constexpr (sizeof(T) == 8 && MV > 1)
+        if (v < MV)
+            return with_fwd_half<T, MV - 1>(v, f);
+    return f(column_fwd_half_kernel<T, col_half_threads<T>(), MV>);
+}
+template <typename T, int MV, typename F>
+hipError_t with_adj_half(int v, F &&f)
+{
+    if constexpr (sizeof(T) == 8 && MV > 1)
+        if (v < MV)
+            return with_adj_half<T, MV - 1>(v, f);
+    return f(column_adj_half_kernel<T, col_half_threads<T>(), MV>);
+}
+
 template <typename T>
 hipError_t set_lds(const gsht_plan &p)
 {
     const int b = (int)col_lds<T>(p);
     hipError_t e;
     if (p.colmode == 2) {
-        e = hipFuncSetAttribute((const void *)column_fwd_half_kernel<T, col_half_threads<T>()>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        auto attr = [&](auto kern) {
+            return hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        };
+        e = with_fwd_half<T, col_half_maxv<T>()>(half_slots<T>(p, false), attr);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void *)column_adj_half_kernel<T, col_half_threads<T>()>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, b);
+            e = with_adj_half<T, col_half_maxv<T>()>(half_slots<T>(p, true), attr);
     } else {
         e = hipFuncSetAttribute((const void *)column_fwd_kernel<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, b);
@@ -637,8 +679,11 @@ void launch_fwd(const gsht_plan &p, hipStream_t s)
     const size_t b = col_lds<T>(p);
     if (p.colmode == 2) {
         constexpr int NT = col_half_threads<T>();
-        hipLaunchKernelGGL((column_fwd_half_kernel<T, NT>), dim3(p.ncol), dim3(NT), b, s,
-                           (const C *)p.D, (C *)p.E, a, p.cf_d, p.cf_h, (const C *)p.twist);
+        (void)with_fwd_half<T, col_half_maxv<T>()>(half_slots<T>(p, false), [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(p.ncol), dim3(NT), b, s, (const C *)p.D, (C *)p.E, a,
+                               p.cf_d, p.cf_h, (const C *)p.twist);
+            return hipSuccess;
+        });
     } else {
         hipLaunchKernelGGL((column_fwd_kernel<T>), dim3(p.ncol), dim3(COL_THREADS), b, s,
                            (const C *)p.D, (C *)p.E, a, p.cf_d);
@@ -653,8 +698,11 @@ void launch_adj(const gsht_plan &p, hipStream_t s)
     const size_t b = col_lds<T>(p);
     if (p.colmode == 2) {
         constexpr int NT = col_half_threads<T>();
-        hipLaunchKernelGGL((column_adj_half_kernel<T, NT>), dim3(p.ncol), dim3(NT), b, s,
-                           (const C *)p.E, (C *)p.D, a, p.cf_d, p.cf_h, (const C *)p.twist);
+        (void)with_adj_half<T, col_half_maxv<T>()>(half_slots<T>(p, true), [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(p.ncol), dim3(NT), b, s, (const C *)p.E, (C *)p.D, a,
+                               p.cf_d, p.cf_h, (const C *)p.twist);
+            return hipSuccess;
+        });
     } else {
         hipLaunchKernelGGL((column_adj_kernel<T>), dim3(p.ncol), dim3(COL_THREADS), b, s,
                            (const C *)p.E, (C *)p.D, a, p.cf_d);
