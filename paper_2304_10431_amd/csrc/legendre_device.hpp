@@ -166,21 +166,21 @@ __device__ inline void ring_advance(Ring &r, double a, double b)
 }
 
 // A scaled channel whose true value p 2^e has reached 2^INX is folded to e = 0;
-// otherwise it is rescaled by 2^-512 once |p| reaches 2^256.
+// otherwise it is rescaled by 2^-512 once |p| reaches 2^256.  Selects only, no
+// lane-divergent branch (the matrix-core kernels schedule their products among the
+// recurrence steps; the vector kernels run the same code, at equal speed and bits).
+// A fold happens only at e = -512 or -1024 (values reach at most 2^288 before the
+// next check), where 2^e is still a double, so the product by it is exact like ldexp.
 template <int INX>
 __device__ inline void rescale_channel(double &p0, double &p1, int &e)
 {
-    if (e >= 0)
-        return;
-    if (fabs(p1) >= ldexp(1.0, INX - e)) {
-        p0 = ldexp(p0, e);
-        p1 = ldexp(p1, e);
-        e = 0;
-    } else if (fabs(p1) >= TWO_P256) {
-        p0 *= TWO_M512;
-        p1 *= TWO_M512;
-        e += 512;
-    }
+    const bool neg = e < 0;
+    const bool fold = neg && fabs(p1) >= ldexp(1.0, INX - e);
+    const bool down = neg && !fold && fabs(p1) >= TWO_P256;
+    const double f = fold ? ldexp(1.0, e) : (down ? TWO_M512 : 1.0);
+    p0 *= f;
+    p1 *= f;
+    e = fold ? 0 : (down ? e + 512 : e);
 }
 
 template <bool SPIN, int INX>

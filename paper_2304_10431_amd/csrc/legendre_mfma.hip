@@ -57,22 +57,6 @@ __device__ inline void to_operands(u32x4_t &x, u32x4_t &y)
     }
 }
 
-// rescale_channel without branches (selects only, so that the block's matrix
-// products can be scheduled among the recurrence steps).  A fold happens only at
-// e = -512 or -1024 (values reach at most 2^288 before the next check), where 2^e is
-// still a double.
-template <int INX>
-__device__ inline void rescale_channel_sel(double &p0, double &p1, int &e)
-{
-    const bool neg = e < 0;
-    const bool fold = neg && fabs(p1) >= ldexp(1.0, INX - e);
-    const bool down = neg && !fold && fabs(p1) >= TWO_P256;
-    const double f = fold ? ldexp(1.0, e) : (down ? TWO_M512 : 1.0);
-    p0 *= f;
-    p1 *= f;
-    e = fold ? 0 : (down ? e + 512 : e);
-}
-
 // One channel's operands: [0] hi rings 0..31, [1] hi rings 32..63, [2], [3] lo.
 struct AOps {
     u32x4_t v[4];
@@ -94,9 +78,9 @@ __device__ inline void make_a(Ring &rg, const double2 *__restrict__ abm, int lb,
         const double2 c = abm[l < lmax ? l : lmax];
         ring_advance<SPIN>(rg, c.x, c.y);
     }
-    rescale_channel_sel<SYN_IN_EXP>(rg.a0, rg.a1, rg.ea);
+    rescale_channel<SYN_IN_EXP>(rg.a0, rg.a1, rg.ea);
     if (SPIN)
-        rescale_channel_sel<SYN_IN_EXP>(rg.b0, rg.b1, rg.eb);
+        rescale_channel<SYN_IN_EXP>(rg.b0, rg.b1, rg.eb);
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         unsigned hi, lo;
@@ -536,9 +520,9 @@ __global__ __launch_bounds__(64 * adj_wmax<NB>()) void leg_adjoint_mfma_kernel(
                     const double2 c = abm[l < lmax ? l : lmax];
                     ring_advance<SPIN>(rg, c.x, c.y);
                 }
-                rescale_channel_sel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
+                rescale_channel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
                 if (SPIN)
-                    rescale_channel_sel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
+                    rescale_channel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
                 ring_store(rg, rs, nr, q);
                 continue;
             }
@@ -568,9 +552,9 @@ __global__ __launch_bounds__(64 * adj_wmax<NB>()) void leg_adjoint_mfma_kernel(
                 const double2 c = abm[l < lmax ? l : lmax];
                 ring_advance<SPIN>(rg, c.x, c.y);
             }
-            rescale_channel_sel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
+            rescale_channel<ADJ_IN_EXP>(rg.a0, rg.a1, rg.ea);
             if (SPIN)
-                rescale_channel_sel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
+                rescale_channel<ADJ_IN_EXP>(rg.b0, rg.b1, rg.eb);
             ring_store(rg, rs, nr, q);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
