@@ -204,8 +204,9 @@ __device__ inline int slice_phase(const Ring &r)
 
 // Silent blocks: while no lane of the wave holds a channel in range every term would
 // get the weight 0, so only the recurrence runs (no sums, no reductions), with the
-// rescaling and the slice phases after every 8 degrees as in the masked blocks.  ab_m
-// points at the degree-indexed coefficients of the wave's m; lb advances.
+// rescaling and the slice phases after every 8 degrees (the longest interval between
+// checks the growth bound of the rescaling allows).  ab_m points at the
+// degree-indexed coefficients of the wave's m; lb advances.
 template <bool SPIN, int INX, int R>
 __device__ inline void silent_blocks(Ring (&rg)[R], const double2 *ab_m, int &lb, int lmax,
                                      bool &all_in, bool &some_in)
