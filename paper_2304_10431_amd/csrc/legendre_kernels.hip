@@ -188,8 +188,18 @@ __device__ inline void synth_fold(double (&c)[8], const double (&t)[8], const Ri
 
 constexpr int LB = 8;  // degrees per block
 
+// Waves per SIMD each synthesis shape is compiled for: R = 2 fits 96 registers, five
+// waves (about 1 % faster than four at 124 registers; a few values spill around the
+// loops, none inside them).
+template <int R>
+constexpr int syn_waves()
+{
+    return R == 2 ? 5 : 1;
+}
+
 template <typename T, bool SPIN, int R, bool GRAD = false>
-__global__ __launch_bounds__(64) void leg_synth_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(syn_waves<R>())))
+void leg_synth_kernel(
     const double2 *__restrict__ ab, const double *__restrict__ u, const StartInfo *__restrict__ st,
     const int32_t *__restrict__ lfirst, int lmax, int mmax, int s, int ntheta, int nd, int npairs,
     int nchunk, typename cplxk<T>::type *__restrict__ D)
