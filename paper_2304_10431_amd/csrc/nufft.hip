@@ -810,10 +810,10 @@ template <typename T, bool CPLX> struct SpreadPack {
 };
 
 // Points of a chunk in cell order are mostly one or two cells apart along a row.
-// Couples of sorted points (2t, 2t + 1) whose first kernel cells share the row and lie
-// at most SPREAD_GAP columns apart are spread as one window of W rows by
-// W + gap columns (each cell takes both contributions in one atomic word); the other
-// points are spread one by one.
+// Couples of neighbouring sorted points whose first kernel cells share the row and lie
+// at most SPREAD_GAP columns apart (chosen greedily along each run of such
+// neighbours) are spread as one window of W rows by W + gap columns (each cell takes
+// both contributions in one atomic word); the other points are spread one by one.
 constexpr int SPREAD_GAP = 2;
 
 // Waves per SIMD the spreading kernels are compiled for: a 128-register budget
@@ -942,20 +942,25 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
     constexpr bool PACK = SpreadPack<T, CPLX>::value;
     constexpr int NW = NUFFT_THREADS / 64;
     constexpr int WG = W + SPREAD_GAP;
-    static_assert(2 * NUFFT_THREADS == CHUNK, "one couple of points per thread");
+    static_assert(2 * NUFFT_THREADS == CHUNK, "two points per thread");
     const int PR = g.t1 + W - 1;
     const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
     const int n = ck.z - ck.y;
-    // couple t: the chunk's points 2t and 2t + 1; the bound S of every cell sum, and
-    // whether they go as one window
+    // Thread t looks at the chunk's points k = t + 256 h (h = 0, 1): wave wv holds the
+    // two 64-point segments starting at 64 wv and 256 + 64 wv.  Point k couples with
+    // k + 1 when both exist and their first kernel cells share the row at most
+    // SPREAD_GAP columns apart (within a segment).  Couples are chosen greedily along
+    // each run of such neighbours (its 1st and 2nd point, 3rd and 4th, ...); the
+    // other points go one by one.  Also the bound S of every cell sum.
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    int lrc[2] = {0, 0}, lcc[2] = {0, 0};
-    bool has[2];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    bool has[2], start[2], single[2];
     double s = 0.0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int k = 2 * t + h;
+        const int k = t + NUFFT_THREADS * h;
         has[h] = k < n;
+        int lr = 0, lc = 0;
         if (has[h]) {
             const int32_t src = perm[ck.y + k];
             const double a = (double)in[src];
@@ -963,22 +968,30 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
             s += fabs(a) + fabs(b);
             const Cell c = point_cell(sth[ck.y + k], sph[ck.y + k], g.c1, g.c2, g.half, g.a_min,
                                       g.n2, g.nrows, W);
-            lrc[h] = c.r0 - row0;
-            lcc[h] = c.bi - col0;
+            lr = c.r0 - row0;
+            lc = c.bi - col0;
         }
+        const int lrn = __shfl_down(lr, 1, 64), lcn = __shfl_down(lc, 1, 64);
+        const bool hasn = lane < 63 && k + 1 < n;
+        const bool cond = has[h] && hasn && lrn == lr && lcn >= lc && lcn - lc <= SPREAD_GAP;
+        const unsigned long long cm = __ballot(cond);
+        // ones of cm right below this lane: lane - (highest zero below it) - 1
+        const unsigned long long zb = ~cm & below;
+        const int p0 = zb ? 63 - __clzll((long long)zb) : -1;
+        start[h] = cond && ((lane - p0 - 1) & 1) == 0;
+        const unsigned long long sm = __ballot(start[h]);
+        const bool second = lane > 0 && ((sm >> (lane - 1)) & 1ull);
+        single[h] = has[h] && !start[h] && !second;
     }
-    const bool pair = has[0] && has[1] && lrc[0] == lrc[1] && lcc[1] >= lcc[0] &&
-                      lcc[1] - lcc[0] <= SPREAD_GAP;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1)
         s += __shfl_xor(s, d, 64);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const unsigned long long bp = __ballot(pair);
-    const unsigned long long b0 = __ballot(!pair && has[0]), b1 = __ballot(!pair && has[1]);
+    const unsigned long long bp0 = __ballot(start[0]), bp1 = __ballot(start[1]);
+    const unsigned long long bs0 = __ballot(single[0]), bs1 = __ballot(single[1]);
     if (lane == 0) {
         sg.wsum[wv] = s;
-        sg.cnt[wv] = __popcll(bp);
-        sg.cnt[NW + wv] = __popcll(b0) + __popcll(b1);
+        sg.cnt[wv] = __popcll(bp0) + __popcll(bp1);
+        sg.cnt[NW + wv] = __popcll(bs0) + __popcll(bs1);
     }
     __syncthreads();
     double S = 0.0;
@@ -994,15 +1007,15 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
         npair += cp;
         nsing += cs;
     }
-    if (pair) {
-        sg.pairs[opair + __popcll(bp & below)] = (short)t;
-    } else {
-        int r = osing + __popcll(b0 & below) + __popcll(b1 & below);
-        if (has[0])
-            sg.singles[r++] = (short)(2 * t);
-        if (has[1])
-            sg.singles[r] = (short)(2 * t + 1);
-    }
+    // couples by their first point, then the single points (segment 0, then 1)
+    if (start[0])
+        sg.pairs[opair + __popcll(bp0 & below)] = (short)t;
+    if (start[1])
+        sg.pairs[opair + __popcll(bp0) + __popcll(bp1 & below)] = (short)(t + NUFFT_THREADS);
+    if (single[0])
+        sg.singles[osing + __popcll(bs0 & below)] = (short)t;
+    if (single[1])
+        sg.singles[osing + __popcll(bs0) + __popcll(bs1 & below)] = (short)(t + NUFFT_THREADS);
     __syncthreads();
     if (!(S > 0.0) || !isfinite(S))
         return false;  // nothing (finite) to spread; uniform over the block
@@ -1017,7 +1030,7 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
         const int st = npair > 1 ? spread_stride(npair) : 1;
         const int i = t;
         if (i < npair) {
-            const int k = 2 * sg.pairs[(int)(((int64_t)i * st) % npair)];
+            const int k = sg.pairs[(int)(((int64_t)i * st) % npair)];
             const int pa = ck.y + k;
             T wxa[W], wya[W], wxb[W], wyb[W];
             int lra, lca, lrb, lcb;
