@@ -940,8 +940,9 @@ __device__ inline bool spread_single(int4 ck, const double *__restrict__ sth,
 
 // Couples as one window, then the single points (values re-read from the map:
 // the preamble's reads leave them in the caches).  Returns false (nothing spread)
-// when the chunk's values are all zero or not finite.
-template <typename T, int W, bool CPLX, bool FQ>
+// when the chunk's values are all zero or not finite.  OWN_S: the chunk's own bound S
+// sets scale; otherwise the caller's scale (a bound over more points) is used.
+template <typename T, int W, bool CPLX, bool FQ, bool OWN_S = true>
 __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
                                      const double *__restrict__ sph,
                                      const int32_t *__restrict__ perm, const T *__restrict__ in,
@@ -973,10 +974,12 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
         has[h] = k < n;
         int lr = 0, lc = 0;
         if (has[h]) {
-            const int32_t src = perm[ck.y + k];
-            const double a = (double)in[src];
-            const double b = CPLX ? (double)in[g.npts + src] : 0.0;
-            s += fabs(a) + fabs(b);
+            if constexpr (OWN_S) {
+                const int32_t src = perm[ck.y + k];
+                const double a = (double)in[src];
+                const double b = CPLX ? (double)in[g.npts + src] : 0.0;
+                s += fabs(a) + fabs(b);
+            }
             const Cell c = point_cell(sth[ck.y + k], sph[ck.y + k], g.c1, g.c2, g.half, g.a_min,
                                       g.n2, g.nrows, W);
             lr = c.r0 - row0;
@@ -1000,7 +1003,8 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
     const unsigned long long bp0 = __ballot(start[0]), bp1 = __ballot(start[1]);
     const unsigned long long bs0 = __ballot(single[0]), bs1 = __ballot(single[1]);
     if (lane == 0) {
-        sg.wsum[wv] = s;
+        if constexpr (OWN_S)  // (otherwise the caller may still be reading wsum)
+            sg.wsum[wv] = s;
         sg.cnt[wv] = __popcll(bp0) + __popcll(bp1);
         sg.cnt[NW + wv] = __popcll(bs0) + __popcll(bs1);
     }
@@ -1009,7 +1013,8 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
     int npair = 0, nsing = 0, opair = 0, osing = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        S += sg.wsum[w];
+        if constexpr (OWN_S)
+            S += sg.wsum[w];
         const int cp = sg.cnt[w], cs = sg.cnt[NW + w];
         if (w < wv) {
             opair += cp;
@@ -1028,9 +1033,11 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
     if (single[1])
         sg.singles[osing + __popcll(bs0) + __popcll(bs1 & below)] = (short)(t + NUFFT_THREADS);
     __syncthreads();
-    if (!(S > 0.0) || !isfinite(S))
-        return false;  // nothing (finite) to spread; uniform over the block
-    scale = A::RANGE * (1.0 - 0x1p-20) / S;
+    if constexpr (OWN_S) {
+        if (!(S > 0.0) || !isfinite(S))
+            return false;  // nothing (finite) to spread; uniform over the block
+        scale = A::RANGE * (1.0 - 0x1p-20) / S;
+    }
     auto value = [&](int p, double &vr, double &vi) {
         const int32_t src = perm[p];
         vr = (double)in[src] * scale;
@@ -1142,36 +1149,18 @@ __device__ inline bool spread_paired(int4 ck, const double *__restrict__ sth,
     return true;
 }
 
-// Spreading of one chunk into its patch, then the flush of the patch to the grid.
-// FP64 grids spread couples of neighbouring points as one window (fewer LDS
-// atomics, which bound them); FP32 grids, bound by their arithmetic, point by point.
+// Adds a spread patch (fixed point, step 1 / scale) to the grid: with global atomics
+// (ATOMIC), or with plain read-add-write when no other workgroup can touch the patch
+// at the same time (tiles launched by colour).  The caller has synchronised the block.
 template <typename T, int W, bool CPLX, bool ATOMIC, bool FQ>
-__device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
-                                    const double *__restrict__ sph,
-                                    const int32_t *__restrict__ perm, const T *__restrict__ in,
-                                    const GridGeom &g, T beta, T *__restrict__ grid,
-                                    typename SpreadAcc<T, FQ>::U *patch, SpreadStage &sg)
+__device__ inline void flush_patch(const typename SpreadAcc<T, FQ>::U *patch, const GridGeom &g,
+                                   int row0, int col0, double scale, T *__restrict__ grid)
 {
     using A = SpreadAcc<T, FQ>;
     constexpr bool PACK = SpreadPack<T, CPLX>::value;
     constexpr int NC = CPLX ? 2 : 1;
-    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
-    const int row0 = tr * g.t1, col0 = tc * g.t2;
     const int PR = g.t1 + W - 1, PC = g.t2 + W - 1;
     const int plane = PR * g.ps;  // FP64 complex: real parts, then imaginary parts
-    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
-        patch[idx] = 0;
-    double scale = 0.0;
-    bool any;
-    if constexpr (std::is_same<T, double>::value)
-        any = spread_paired<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg, row0, col0,
-                                            scale);
-    else
-        any = spread_single<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg.wsum, row0,
-                                            col0, scale);
-    if (!any)
-        return;
-    __syncthreads();
     const double inv = 1.0 / scale;
     for (int idx = threadIdx.x; idx < PR * PC; idx += NUFFT_THREADS) {
         const int pr = idx / PC, pc = idx - (idx / PC) * PC;
@@ -1185,7 +1174,7 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
         const int pidx = pr * g.ps + pc;
         typename A::S qr, qi;
         if constexpr (PACK) {
-            const long long t = (long long)reinterpret_cast<unsigned long long *>(patch)[pidx];
+            const long long t = (long long)reinterpret_cast<const unsigned long long *>(patch)[pidx];
             qi = (int)(unsigned int)(t & 0xffffffffll);
             qr = (int)((t - (long long)qi) >> 32);
         } else {
@@ -1209,7 +1198,90 @@ __device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
             }
         }
     }
+}
+
+// Spreading of one chunk into its patch, then the flush of the patch to the grid.
+// FP64 grids spread couples of neighbouring points as one window (fewer LDS
+// atomics, which bound them); FP32 grids, bound by their arithmetic, point by point.
+template <typename T, int W, bool CPLX, bool ATOMIC, bool FQ>
+__device__ inline void spread_chunk(int4 ck, const double *__restrict__ sth,
+                                    const double *__restrict__ sph,
+                                    const int32_t *__restrict__ perm, const T *__restrict__ in,
+                                    const GridGeom &g, T beta, T *__restrict__ grid,
+                                    typename SpreadAcc<T, FQ>::U *patch, SpreadStage &sg)
+{
+    constexpr int NC = CPLX ? 2 : 1;
+    const int tr = ck.x / g.nt2, tc = ck.x - (ck.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1;
+    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
+        patch[idx] = 0;
+    double scale = 0.0;
+    bool any;
+    if constexpr (std::is_same<T, double>::value)
+        any = spread_paired<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg, row0, col0,
+                                            scale);
+    else
+        any = spread_single<T, W, CPLX, FQ>(ck, sth, sph, perm, in, g, beta, patch, sg.wsum, row0,
+                                            col0, scale);
+    if (!any)
+        return;
+    __syncthreads();
+    flush_patch<T, W, CPLX, ATOMIC, FQ>(patch, g, row0, col0, scale, grid);
     __syncthreads();  // the patch is reused by the next chunk of the same workgroup
+}
+
+// FP64 tiles of at most SPREAD_TILE_CHUNKS chunks are spread as a whole into one patch
+// (cleared and flushed once) with one bound S over the tile's points: at most two
+// chunks' worth, so the quantisation step S / RANGE stays within twice the per-chunk
+// one (2^-50 S of at most 1024 values in the fast form, far below the epsilon it
+// serves).  Denser tiles go chunk by chunk.
+constexpr int SPREAD_TILE_CHUNKS = 2;
+
+// FP64, a whole tile (chunks first .. first + count - 1, one contiguous range of
+// points) into one patch, plain read-add-write (tiles launched by colour).
+template <int W, bool CPLX, bool FQ>
+__device__ inline void spread_tile_f64(int2 it, const int4 *__restrict__ chunks,
+                                       const double *__restrict__ sth,
+                                       const double *__restrict__ sph,
+                                       const int32_t *__restrict__ perm,
+                                       const double *__restrict__ in, const GridGeom &g,
+                                       double beta, double *__restrict__ grid,
+                                       typename SpreadAcc<double, FQ>::U *patch, SpreadStage &sg)
+{
+    using A = SpreadAcc<double, FQ>;
+    constexpr int NC = CPLX ? 2 : 1;
+    constexpr int NW = NUFFT_THREADS / 64;
+    const int4 c0 = chunks[it.x];
+    const int y0 = c0.y, z1 = chunks[it.x + it.y - 1].z;
+    const int tr = c0.x / g.nt2, tc = c0.x - (c0.x / g.nt2) * g.nt2;
+    const int row0 = tr * g.t1, col0 = tc * g.t2;
+    const int PR = g.t1 + W - 1;
+    double s = 0.0;
+    for (int p = y0 + (int)threadIdx.x; p < z1; p += NUFFT_THREADS) {
+        const int32_t src = perm[p];
+        s += fabs(in[src]) + (CPLX ? fabs(in[g.npts + src]) : 0.0);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+        s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0)
+        sg.wsum[threadIdx.x >> 6] = s;
+    for (int idx = threadIdx.x; idx < PR * g.ps * NC; idx += NUFFT_THREADS)
+        patch[idx] = 0;
+    __syncthreads();
+    double S = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+        S += sg.wsum[w];
+    if (!(S > 0.0) || !isfinite(S))
+        return;  // nothing (finite) to spread; uniform over the block
+    double scale = A::RANGE * (1.0 - 0x1p-20) / S;
+    for (int c = 0; c < it.y; ++c)
+        spread_paired<double, W, CPLX, FQ, false>(chunks[it.x + c], sth, sph, perm, in, g, beta,
+                                                  patch, sg, row0, col0, scale);
+    __syncthreads();
+    flush_patch<double, W, CPLX, false, FQ>(patch, g, row0, col0, scale, grid);
 }
 
 // One workgroup per chunk, atomic flush (any grid).
@@ -1240,10 +1312,15 @@ __global__ __launch_bounds__(NUFFT_THREADS, SPREAD_WAVES) void spread_tile_kerne
     extern __shared__ unsigned char smem_raw[];
     __shared__ SpreadStage sg;
     const int2 it = items[blockIdx.x];
-    for (int c = 0; c < it.y; ++c)
-        spread_chunk<T, W, CPLX, false, FQ>(chunks[it.x + c], sth, sph, perm, in, g, beta, grid,
-                                            reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw),
-                                            sg);
+    auto *patch = reinterpret_cast<typename SpreadAcc<T, FQ>::U *>(smem_raw);
+    if (std::is_same<T, double>::value && it.y <= SPREAD_TILE_CHUNKS) {
+        if constexpr (std::is_same<T, double>::value)
+            spread_tile_f64<W, CPLX, FQ>(it, chunks, sth, sph, perm, in, g, beta, grid, patch, sg);
+    } else {
+        for (int c = 0; c < it.y; ++c)
+            spread_chunk<T, W, CPLX, false, FQ>(chunks[it.x + c], sth, sph, perm, in, g, beta,
+                                                grid, patch, sg);
+    }
 }
 
 static GridGeom make_geom(const gsht_plan &p)
