@@ -218,7 +218,7 @@ void leg_synth_kernel(
 
     Ring rg[R];
     double c[R][8];
-    bool all_in = true;
+    bool all_in = true, some_in = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int q = chunk * 64 * R + 64 * r + lane;
@@ -226,7 +226,9 @@ void leg_synth_kernel(
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             c[r][k] = 0.0;
-        all_in = all_in && (slice_phase<SPIN>(rg[r]) == 2);
+        const int ph = slice_phase<SPIN>(rg[r]);
+        all_in = all_in && ph == 2;
+        some_in = some_in || ph != 0;
     }
     // Masked block: the block's terms are summed separately and added only for
     // channels in range (offset 0, constant inside a block); then rescaling and the
@@ -276,10 +278,11 @@ void leg_synth_kernel(
         }
     };
     if (live) {
-        // Three sequential loops (no loop-carried value crosses a branch merge):
-        // masked full blocks until every lane is in range, full plain blocks, and
-        // a masked partial tail.
+        // Sequential loops (no loop-carried value crosses a branch merge): silent
+        // blocks until some lane is in range, masked full blocks until every lane is,
+        // full plain blocks, and a masked partial tail.
         int lb = l0;
+        silent_blocks<SPIN, SYN_IN_EXP>(rg, ab + base, lb, lmax, all_in, some_in);
         for (; lb + LB - 1 <= lmax && !all_in; lb += LB)
             masked_block(lb, flag<false>());
         // Full plain blocks, run as degree pairs whose coefficients are loaded one
