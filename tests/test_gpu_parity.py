@@ -361,6 +361,38 @@ def test_spreading_by_tile_colour(G, monkeypatch, lmax, mmax, spin, npts, prec, 
     assert oracle.eps_eff(outs[0] * w, ref * w) <= eps
 
 
+@pytest.mark.parametrize("spin,eps", [(2, 1e-10), (0, 1e-12)])
+def test_spreading_mixed_tile_densities(G, monkeypatch, spin, eps):
+    """FP64 colour-ordered spreading on one point set with sparse tiles (at most two
+    chunks: spread as a whole with one value bound) and dense ones (a 20000-point cap
+    of 0.05 x 0.05 rad near theta = 1, phi = 2, a few tiles of dozens of chunks: chunk
+    by chunk), against the per-chunk atomic flush and against the oracle."""
+    say("spread mixed densities", spin, eps)
+    lmax = 127
+    rng = np.random.default_rng(1700 + spin)
+    th1, ph1 = wl.uniform_sphere(8000, rng)
+    th2 = 1.0 + 0.05 * rng.random(20000)
+    ph2 = 2.0 + 0.05 * rng.random(20000)
+    th, ph = np.concatenate([th1, th2]), np.concatenate([ph1, ph2])
+    y = rng.standard_normal((oracle.ncomp(spin), th.size))
+    w = np.sqrt(oracle.alm_weights(lmax, lmax))[None, :]
+    outs = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("GSHT_SPREAD_COLORS", raising=False)
+        else:
+            monkeypatch.setenv("GSHT_SPREAD_COLORS", env)
+        plan = G.Plan(dev(th), dev(ph), lmax, lmax, spin, eps, "f64")
+        assert (plan.info()["spread_colors"] > 0) == (env is None)
+        outs.append(plan.adjoint(dev(y)).cpu().numpy())
+        plan.close()
+    d = rel_l2(outs[0] * w, outs[1] * w)
+    say("  colour vs atomic: %.2e" % d)
+    assert d <= 1e-12
+    ref = oracle.adjoint(y, lmax, lmax, spin, th, ph)
+    assert oracle.eps_eff(outs[0] * w, ref * w) <= eps
+
+
 @pytest.mark.parametrize("lmax,mmax,spin,npts,eps", [
     (130, 130, 2, 30000, 1e-10), (200, 150, 0, 20000, 1e-10), (64, 64, 1, 9000, 1e-8)])
 def test_fp64_spreading_fast_and_exact_forms(G, monkeypatch, lmax, mmax, spin, npts, eps):
